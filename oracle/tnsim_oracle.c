@@ -1,0 +1,673 @@
+/*
+ * tnsim_oracle.c -- CPU reference for MPS gate application.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Plain, slow, complex128 C99 (+ optional OpenMP)
+ * with no BLAS/LAPACK.  Only the tests, the smoke check and the benchmark's
+ * CPU-baseline leg may load it; the GPU library never does, and the two share
+ * no code, headers or tables.
+ *
+ * What it computes (arXiv 2601.04422):
+ *   - state: an MPS of n rank-3 site tensors A_q[a,s,b] (Sec. II, eq. 2),
+ *     initialised to |0...0> with every bond of dimension 1 (Sec. IV.A);
+ *   - one-qubit gate: A'[a,s',b] = sum_s U[s',s] A[a,s,b] (Sec. II, eq. 3);
+ *   - local two-qubit gate: contract the two sites (Sec. IV.A, Fig. 2), contract
+ *     with the gate, decompose by SVD, put the left singular vectors on the
+ *     left (control) site and the singular values with the right singular
+ *     vectors on the right (target) site (Sec. III.A), truncating the bond
+ *     (Sec. II, best low-rank approximation; Sec. IV.A, truncation in the SVD).
+ *
+ * Readings where the paper is silent (each is listed in the design notes):
+ *   - Gauge: every site is kept left-canonical and lambda_q holds the Schmidt
+ *     values of bond q.  The SVD is taken of theta' * diag(lambda_{i+1}) and
+ *     the right site is U_k^H theta' / N, so lambda is never divided out
+ *     (Hastings, J. Math. Phys. 50, 095207 (2009)).
+ *   - SVD: one-sided (Hestenes) Jacobi on the columns of M, in round-robin
+ *     pair order (Brent & Luk 1985); a pair is rotated when
+ *     |x^H y| > tol * ||x|| ||y||, tol = max(rows, 16) * 2^-53 by default.  The paper's
+ *     GPU SVD is a Jacobi SVD (Sec. IV, cusolverDnZgesvdj).  When M has more
+ *     columns than rows, M^H is first reduced by Householder QR and the Jacobi
+ *     runs on R^H, which has the same left singular vectors.
+ *   - Truncation: sigma sorted descending (ties by column index);
+ *     sigma_j^2 <= rows * 2^-53 * sigma_1^2 counts as zero; k is the smallest
+ *     k >= 1 whose discarded weight sum_{j>k} sigma_j^2 <= cutoff * W
+ *     (W = sum sigma_j^2), capped by chi_max and the non-zero count; the kept
+ *     values are renormalised by N = sqrt(sum_{j<=k} sigma_j^2).
+ *   - Basis: a 4x4 gate acts on |s_q0 s_q1> with row 2*s_q0 + s_q1.  A gate
+ *     given as (q0, q0-1) is applied as SWAP*G*SWAP on (q0-1, q0).
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef double complex cplx;
+
+enum { OM_OK = 0, OM_E_ARG = 1, OM_E_NONLOCAL = 2, OM_E_OVERLAP = 3,
+       OM_E_CAPACITY = 4, OM_E_DEVICE = 5, OM_E_NOCONV = 6 };
+
+#define OM_EPS 1.1102230246251565e-16 /* 2^-53 */
+
+typedef struct {
+  int n, chi_max, max_sweeps;
+  double cutoff, tol; /* tol <= 0 selects max(rows, 16) * 2^-53 */
+  int *dim;           /* n+1 entries, dim[0] = dim[n] = 1, dim[q+1] = bond q */
+  cplx **A;           /* site q: dim[q] x 2 x dim[q+1], row-major */
+  double **lam;       /* bond q (0..n-2): dim[q+1] values */
+  double sum_eps, prod_keep;
+  int64_t n2q;
+  int last_k, last_sweeps;
+  double last_eps;
+} om_mps;
+
+/* ------------------------------------------------------------------ helpers */
+
+static void *xalloc(size_t bytes) {
+  void *p = calloc(bytes ? bytes : 1, 1);
+  if (!p) abort();
+  return p;
+}
+
+static int om_threads = 0;
+
+void om_set_threads(int t) {
+  om_threads = t;
+#ifdef _OPENMP
+  if (t > 0) omp_set_num_threads(t);
+#endif
+}
+
+int om_get_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------ state */
+
+om_mps *om_create(int n, int chi_max, double cutoff, int max_sweeps, double tol) {
+  if (n < 1 || chi_max < 1) return NULL;
+  om_mps *m = (om_mps *)xalloc(sizeof(om_mps));
+  m->n = n;
+  m->chi_max = chi_max;
+  m->cutoff = cutoff;
+  m->max_sweeps = max_sweeps > 0 ? max_sweeps : 60;
+  m->tol = tol;
+  m->dim = (int *)xalloc(sizeof(int) * (n + 1));
+  m->A = (cplx **)xalloc(sizeof(cplx *) * n);
+  m->lam = (double **)xalloc(sizeof(double *) * (n > 1 ? n - 1 : 1));
+  for (int q = 0; q <= n; q++) m->dim[q] = 1;
+  for (int q = 0; q < n; q++) {
+    m->A[q] = (cplx *)xalloc(sizeof(cplx) * 2);
+    m->A[q][0] = 1.0; /* |0> */
+    m->A[q][1] = 0.0;
+  }
+  for (int q = 0; q + 1 < n; q++) {
+    m->lam[q] = (double *)xalloc(sizeof(double));
+    m->lam[q][0] = 1.0;
+  }
+  m->prod_keep = 1.0;
+  return m;
+}
+
+void om_destroy(om_mps *m) {
+  if (!m) return;
+  for (int q = 0; q < m->n; q++) free(m->A[q]);
+  for (int q = 0; q + 1 < m->n; q++) free(m->lam[q]);
+  free(m->A);
+  free(m->lam);
+  free(m->dim);
+  free(m);
+}
+
+int om_n(const om_mps *m) { return m->n; }
+
+void om_bond_dims(const om_mps *m, int32_t *out) {
+  for (int q = 0; q + 1 < m->n; q++) out[q] = m->dim[q + 1];
+}
+
+void om_stats(const om_mps *m, double *sum_eps, double *prod_keep, int64_t *n2q,
+              int *last_k, double *last_eps, int *last_sweeps) {
+  if (sum_eps) *sum_eps = m->sum_eps;
+  if (prod_keep) *prod_keep = m->prod_keep;
+  if (n2q) *n2q = m->n2q;
+  if (last_k) *last_k = m->last_k;
+  if (last_eps) *last_eps = m->last_eps;
+  if (last_sweeps) *last_sweeps = m->last_sweeps;
+}
+
+/* Site q as interleaved (re,im) doubles; chiL/chiR returned. out may be NULL. */
+int om_get_site(const om_mps *m, int q, double *out, int *chiL, int *chiR) {
+  if (q < 0 || q >= m->n) return OM_E_ARG;
+  int a = m->dim[q], b = m->dim[q + 1];
+  if (chiL) *chiL = a;
+  if (chiR) *chiR = b;
+  if (out) memcpy(out, m->A[q], sizeof(cplx) * (size_t)a * 2 * b);
+  return OM_OK;
+}
+
+int om_get_lambda(const om_mps *m, int bond, double *out, int *chi) {
+  if (bond < 0 || bond + 1 >= m->n) return OM_E_ARG;
+  int c = m->dim[bond + 1];
+  if (chi) *chi = c;
+  if (out) memcpy(out, m->lam[bond], sizeof(double) * c);
+  return OM_OK;
+}
+
+/* Replace the state: sites[q] interleaved complex (dims[q] x 2 x dims[q+1]),
+   lambdas[q] (dims[q+1] values), dims has n+1 entries with dims[0]=dims[n]=1. */
+int om_set_state(om_mps *m, const double *const *sites, const double *const *lambdas,
+                 const int32_t *dims) {
+  int n = m->n;
+  if (dims[0] != 1 || dims[n] != 1) return OM_E_ARG;
+  for (int q = 1; q < n; q++)
+    if (dims[q] < 1) return OM_E_ARG;
+  for (int q = 0; q <= n; q++) m->dim[q] = dims[q];
+  for (int q = 0; q < n; q++) {
+    size_t cnt = (size_t)dims[q] * 2 * dims[q + 1];
+    free(m->A[q]);
+    m->A[q] = (cplx *)xalloc(sizeof(cplx) * cnt);
+    memcpy(m->A[q], sites[q], sizeof(cplx) * cnt);
+  }
+  for (int q = 0; q + 1 < n; q++) {
+    free(m->lam[q]);
+    m->lam[q] = (double *)xalloc(sizeof(double) * dims[q + 1]);
+    memcpy(m->lam[q], lambdas[q], sizeof(double) * dims[q + 1]);
+  }
+  return OM_OK;
+}
+
+/* ------------------------------------------------------------------ 1q gate */
+
+/* A'[a,s',b] = sum_s U[s',s] A[a,s,b]   (Sec. II, eq. 3) */
+int om_apply_1q(om_mps *m, int q, const double *u_ri) {
+  if (q < 0 || q >= m->n) return OM_E_ARG;
+  const cplx *U = (const cplx *)u_ri;
+  int a_n = m->dim[q], b_n = m->dim[q + 1];
+  cplx *A = m->A[q];
+  for (int a = 0; a < a_n; a++)
+    for (int b = 0; b < b_n; b++) {
+      cplx x0 = A[(a * 2 + 0) * b_n + b], x1 = A[(a * 2 + 1) * b_n + b];
+      A[(a * 2 + 0) * b_n + b] = U[0] * x0 + U[1] * x1;
+      A[(a * 2 + 1) * b_n + b] = U[2] * x0 + U[3] * x1;
+    }
+  return OM_OK;
+}
+
+/* ------------------------------------------------------------------ SVD */
+
+/* Householder QR of X (rows x cols, column-major, rows >= cols): on return the
+   upper triangle of the leading cols x cols block holds R (X = Q R).  Golub &
+   Van Loan, Matrix Computations, Sec. 5.2 (complex reflectors). */
+static void householder_r(cplx *X, int rows, int cols) {
+  for (int j = 0; j < cols; j++) {
+    cplx *x = X + (size_t)j * rows;
+    double nrm2 = 0.0;
+    for (int i = j; i < rows; i++) nrm2 += creal(x[i]) * creal(x[i]) + cimag(x[i]) * cimag(x[i]);
+    double nrm = sqrt(nrm2);
+    if (nrm == 0.0) continue;
+    cplx x0 = x[j];
+    double ax0 = cabs(x0);
+    cplx ph = ax0 > 0.0 ? x0 / ax0 : 1.0;
+    cplx alpha = -ph * nrm;           /* new diagonal entry R_jj */
+    /* v = x - alpha e_j on rows j..rows-1, H = I - 2 v v^H / (v^H v) */
+    cplx v0 = x0 - alpha;
+    double vnorm2 = nrm2 - ax0 * ax0 + creal(v0) * creal(v0) + cimag(v0) * cimag(v0);
+    x[j] = v0;                        /* x now stores v */
+    for (int c = j + 1; c < cols; c++) {
+      cplx *y = X + (size_t)c * rows;
+      cplx d = 0.0;
+      for (int i = j; i < rows; i++) d += conj(x[i]) * y[i];
+      cplx f = 2.0 * d / vnorm2;
+      for (int i = j; i < rows; i++) y[i] -= f * x[i];
+    }
+    x[j] = alpha;
+    for (int i = j + 1; i < rows; i++) x[i] = 0.0;
+  }
+}
+
+/* One-sided Jacobi on the columns of X (rows x cols, column-major).  Pairs are
+   visited in round-robin order so that the pairs of one round touch disjoint
+   columns.  Returns the number of sweeps, or -1 if max_sweeps was reached. */
+static int jacobi_columns(cplx *X, int rows, int cols, double tol, int max_sweeps) {
+  if (cols < 2) return 0;
+  int P = cols + (cols & 1);
+  int npairs = P / 2;
+  /* Columns below 2^-200 of the matrix's squared Frobenius norm are zero for
+     every purpose of the method (far under the numerical-zero floor); pairs
+     holding one are not rotated, which keeps denormals out of the rotation. */
+  double fro2 = 0.0;
+  for (size_t i = 0; i < (size_t)rows * cols; i++)
+    fro2 += creal(X[i]) * creal(X[i]) + cimag(X[i]) * cimag(X[i]);
+  const double small = fro2 * 0x1p-200;
+  for (int sweep = 1; sweep <= max_sweeps; sweep++) {
+    int rotated = 0;
+    for (int r = 0; r < P - 1; r++) {
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : rotated) if (cols >= 96)
+      for (int k = 0; k < npairs; k++) {
+        int p, q;
+        if (k == 0) {
+          p = P - 1;
+          q = r;
+        } else {
+          p = (r + k) % (P - 1);
+          q = (r - k + (P - 1)) % (P - 1);
+        }
+        if (p > q) { int t = p; p = q; q = t; }
+        if (q >= cols) continue;
+        cplx *x = X + (size_t)p * rows, *y = X + (size_t)q * rows;
+        double alpha = 0.0, beta = 0.0;
+        cplx gamma = 0.0;
+        for (int i = 0; i < rows; i++) {
+          alpha += creal(x[i]) * creal(x[i]) + cimag(x[i]) * cimag(x[i]);
+          beta += creal(y[i]) * creal(y[i]) + cimag(y[i]) * cimag(y[i]);
+          gamma += conj(x[i]) * y[i];
+        }
+        double ag = cabs(gamma);
+        if (alpha <= small || beta <= small) continue;
+        if (!(ag > tol * sqrt(alpha) * sqrt(beta))) continue;
+        rotated = 1;
+        cplx eiphi = gamma / ag;            /* e^{i phi} */
+        double zeta = (beta - alpha) / (2.0 * ag);
+        double sg = zeta >= 0.0 ? 1.0 : -1.0;
+        double t = sg / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        double c = 1.0 / sqrt(1.0 + t * t);
+        double s = c * t;
+        for (int i = 0; i < rows; i++) {
+          cplx xv = x[i];
+          cplx yt = conj(eiphi) * y[i];     /* y~ = e^{-i phi} y */
+          x[i] = c * xv - s * yt;
+          y[i] = s * xv + c * yt;
+        }
+      }
+    }
+    if (!rotated) return sweep;
+  }
+  return -1;
+}
+
+/* Sort indices by sigma descending, ties by index ascending. */
+static __thread const double *g_sort_key;
+static int cmp_desc(const void *pa, const void *pb) {
+  int a = *(const int *)pa, b = *(const int *)pb;
+  double sa = g_sort_key[a], sb = g_sort_key[b];
+  if (sa > sb) return -1;
+  if (sa < sb) return 1;
+  return a < b ? -1 : (a > b);
+}
+
+/* Left singular vectors and singular values of M (rows x cols, column-major,
+   copied).  U gets min(rows,cols) columns (rows x r, column-major), sorted by
+   descending sigma.  Returns the sweep count or -1 (no convergence). */
+static int svd_left(const cplx *M, int rows, int cols, double tol, int max_sweeps,
+                    cplx *U, double *sigma) {
+  int r = rows < cols ? rows : cols;
+  cplx *X;
+  int xcols;
+  if (cols <= rows) {
+    X = (cplx *)xalloc(sizeof(cplx) * (size_t)rows * cols);
+    memcpy(X, M, sizeof(cplx) * (size_t)rows * cols);
+    xcols = cols;
+  } else {
+    /* M^H = Q R  =>  M = R^H Q^H ; left singular vectors of M are those of R^H */
+    cplx *Y = (cplx *)xalloc(sizeof(cplx) * (size_t)cols * rows); /* M^H, cols x rows */
+    for (int i = 0; i < rows; i++)
+      for (int j = 0; j < cols; j++) Y[(size_t)i * cols + j] = conj(M[(size_t)j * rows + i]);
+    householder_r(Y, cols, rows);
+    X = (cplx *)xalloc(sizeof(cplx) * (size_t)rows * rows); /* R^H, rows x rows */
+    for (int i = 0; i < rows; i++)   /* row i of R^H */
+      for (int j = 0; j < rows; j++) /* column j of R^H = conj of row j of R */
+        X[(size_t)j * rows + i] = (i >= j) ? conj(Y[(size_t)i * cols + j]) : 0.0;
+    free(Y);
+    xcols = rows;
+  }
+  if (tol <= 0.0) tol = (rows > 16 ? rows : 16) * OM_EPS;
+  int sweeps = jacobi_columns(X, rows, xcols, tol, max_sweeps);
+  double *nrm = (double *)xalloc(sizeof(double) * xcols);
+  int *idx = (int *)xalloc(sizeof(int) * xcols);
+  for (int j = 0; j < xcols; j++) {
+    double s = 0.0;
+    for (int i = 0; i < rows; i++) {
+      cplx v = X[(size_t)j * rows + i];
+      s += creal(v) * creal(v) + cimag(v) * cimag(v);
+    }
+    nrm[j] = sqrt(s);
+    idx[j] = j;
+  }
+  g_sort_key = nrm;
+  qsort(idx, xcols, sizeof(int), cmp_desc);
+  for (int j = 0; j < r; j++) {
+    double s = nrm[idx[j]];
+    sigma[j] = s;
+    for (int i = 0; i < rows; i++)
+      U[(size_t)j * rows + i] = s > 0.0 ? X[(size_t)idx[j] * rows + i] / s : (i == j ? 1.0 : 0.0);
+  }
+  free(nrm);
+  free(idx);
+  free(X);
+  return sweeps;
+}
+
+/* Exported for the SVD pins: M row-major interleaved (rows x cols); U out
+   column-major interleaved (rows x min), sigma out (min). */
+int om_svd(const double *m_ri, int rows, int cols, double tol, int max_sweeps,
+           double *u_ri, double *sigma, int *sweeps) {
+  if (rows < 1 || cols < 1) return OM_E_ARG;
+  cplx *M = (cplx *)xalloc(sizeof(cplx) * (size_t)rows * cols);
+  const cplx *src = (const cplx *)m_ri;
+  for (int i = 0; i < rows; i++)
+    for (int j = 0; j < cols; j++) M[(size_t)j * rows + i] = src[(size_t)i * cols + j];
+  int s = svd_left(M, rows, cols, tol, max_sweeps > 0 ? max_sweeps : 60, (cplx *)u_ri, sigma);
+  free(M);
+  if (sweeps) *sweeps = s;
+  return s < 0 ? OM_E_NOCONV : OM_OK;
+}
+
+/* Truncation rule on a descending spectrum.  rows is the row count of the
+   decomposed matrix (sets the numerical-zero floor). */
+int om_truncation(const double *sigma, int count, int rows, int chi_max, double cutoff,
+                  int *k_out, double *eps_out, double *norm_out) {
+  if (count < 1) return OM_E_ARG;
+  double W = 0.0;
+  for (int j = 0; j < count; j++) W += sigma[j] * sigma[j];
+  double floor2 = rows * OM_EPS * sigma[0] * sigma[0];
+  int nz = 0;
+  for (int j = 0; j < count; j++)
+    if (sigma[j] * sigma[j] > floor2) nz++;
+  if (nz < 1) nz = 1;
+  /* tail[k] = sum_{j>k} sigma_j^2 (1-based k), summed from the small end */
+  double *tail = (double *)xalloc(sizeof(double) * (count + 1));
+  tail[count] = 0.0;
+  for (int k = count - 1; k >= 0; k--) tail[k] = tail[k + 1] + sigma[k] * sigma[k];
+  int kc = count;
+  for (int k = 1; k <= count; k++)
+    if (tail[k] <= cutoff * W) { kc = k; break; }
+  int k = kc;
+  if (k > nz) k = nz;
+  if (k > chi_max) k = chi_max;
+  if (k < 1) k = 1;
+  double head = 0.0;
+  for (int j = 0; j < k; j++) head += sigma[j] * sigma[j];
+  if (k_out) *k_out = k;
+  if (eps_out) *eps_out = W > 0.0 ? tail[k] / W : 0.0;
+  if (norm_out) *norm_out = sqrt(head);
+  free(tail);
+  return OM_OK;
+}
+
+/* ------------------------------------------------------------------ 2q gate */
+
+static int apply_2q_local(om_mps *m, int i, const cplx *G) {
+  int chiL = m->dim[i], chiM = m->dim[i + 1], chiR = m->dim[i + 2];
+  int rows = 2 * chiL, cols = 2 * chiR;
+  const cplx *A0 = m->A[i], *A1 = m->A[i + 1];
+  /* theta[a,s,t,c] = sum_b A_i[a,s,b] A_{i+1}[b,t,c]   (Fig. 2 merge) */
+  cplx *th = (cplx *)xalloc(sizeof(cplx) * (size_t)rows * cols);
+  for (int as = 0; as < rows; as++)
+    for (int b = 0; b < chiM; b++) {
+      cplx w = A0[(size_t)as * chiM + b];
+      if (w == 0.0) continue;
+      const cplx *r1 = A1 + (size_t)b * cols;
+      cplx *o = th + (size_t)as * cols;
+      for (int tc = 0; tc < cols; tc++) o[tc] += w * r1[tc];
+    }
+  /* theta'[a,s',t',c] = sum_{s,t} G[2s'+t', 2s+t] theta[a,s,t,c]   (gate contraction) */
+  cplx *thp = (cplx *)xalloc(sizeof(cplx) * (size_t)rows * cols);
+  for (int a = 0; a < chiL; a++)
+    for (int c = 0; c < chiR; c++) {
+      cplx v[4];
+      for (int s = 0; s < 2; s++)
+        for (int t = 0; t < 2; t++) v[2 * s + t] = th[(size_t)(2 * a + s) * cols + t * chiR + c];
+      for (int sp = 0; sp < 2; sp++)
+        for (int tp = 0; tp < 2; tp++) {
+          cplx acc = 0.0;
+          for (int j = 0; j < 4; j++) acc += G[(2 * sp + tp) * 4 + j] * v[j];
+          thp[(size_t)(2 * a + sp) * cols + tp * chiR + c] = acc;
+        }
+    }
+  free(th);
+  /* M[2a+s, t*chiR+c] = theta'[a,s,t,c] * lambda_{i+1}[c], column-major */
+  const double *lr = (i + 1 <= m->n - 2) ? m->lam[i + 1] : NULL;
+  cplx *M = (cplx *)xalloc(sizeof(cplx) * (size_t)rows * cols);
+  for (int r = 0; r < rows; r++)
+    for (int t = 0; t < 2; t++)
+      for (int c = 0; c < chiR; c++) {
+        double w = lr ? lr[c] : 1.0;
+        M[(size_t)(t * chiR + c) * rows + r] = thp[(size_t)r * cols + t * chiR + c] * w;
+      }
+  int rk = rows < cols ? rows : cols;
+  cplx *U = (cplx *)xalloc(sizeof(cplx) * (size_t)rows * rk);
+  double *sig = (double *)xalloc(sizeof(double) * rk);
+  int sweeps = svd_left(M, rows, cols, m->tol, m->max_sweeps, U, sig);
+  free(M);
+  if (sweeps < 0) {
+    free(U); free(sig); free(thp);
+    return OM_E_NOCONV;
+  }
+  int k;
+  double eps, N;
+  om_truncation(sig, rk, rows, m->chi_max, m->cutoff, &k, &eps, &N);
+  if (!(N > 0.0)) N = 1.0;
+  /* A_i' = U_k as (chiL, 2, k); lambda_i' = sigma/N; A_{i+1}' = U_k^H theta' / N */
+  cplx *nA0 = (cplx *)xalloc(sizeof(cplx) * (size_t)rows * k);
+  for (int r = 0; r < rows; r++)
+    for (int j = 0; j < k; j++) nA0[(size_t)r * k + j] = U[(size_t)j * rows + r];
+  cplx *nA1 = (cplx *)xalloc(sizeof(cplx) * (size_t)k * cols);
+  for (int j = 0; j < k; j++) {
+    cplx *o = nA1 + (size_t)j * cols;
+    for (int r = 0; r < rows; r++) {
+      cplx w = conj(U[(size_t)j * rows + r]) / N;
+      const cplx *src = thp + (size_t)r * cols;
+      for (int tc = 0; tc < cols; tc++) o[tc] += w * src[tc];
+    }
+  }
+  double *nl = (double *)xalloc(sizeof(double) * k);
+  for (int j = 0; j < k; j++) nl[j] = sig[j] / N;
+  free(m->A[i]);
+  free(m->A[i + 1]);
+  free(m->lam[i]);
+  m->A[i] = nA0;
+  m->A[i + 1] = nA1;
+  m->lam[i] = nl;
+  m->dim[i + 1] = k;
+  m->sum_eps += eps;
+  m->prod_keep *= (1.0 - eps);
+  m->n2q += 1;
+  m->last_k = k;
+  m->last_eps = eps;
+  m->last_sweeps = sweeps;
+  free(U); free(sig); free(thp);
+  return OM_OK;
+}
+
+int om_apply_2q(om_mps *m, int q0, int q1, const double *g_ri) {
+  if (q0 < 0 || q0 >= m->n || q1 < 0 || q1 >= m->n || q0 == q1) return OM_E_ARG;
+  const cplx *G = (const cplx *)g_ri;
+  if (q1 == q0 + 1) return apply_2q_local(m, q0, G);
+  if (q1 == q0 - 1) {
+    /* same gate with the two qubits listed in the other order: SWAP G SWAP */
+    cplx Gs[16];
+    for (int sp = 0; sp < 2; sp++)
+      for (int tp = 0; tp < 2; tp++)
+        for (int s = 0; s < 2; s++)
+          for (int t = 0; t < 2; t++)
+            Gs[(2 * sp + tp) * 4 + 2 * s + t] = G[(2 * tp + sp) * 4 + 2 * t + s];
+    return apply_2q_local(m, q1, Gs);
+  }
+  return OM_E_NONLOCAL;
+}
+
+/* Gates of one layer: q1[g] = -1 marks a one-qubit gate (matrix in the first
+   4 complex entries of its 16-entry slot).  Qubits must be disjoint. */
+int om_apply_layer(om_mps *m, const int32_t *q0, const int32_t *q1, const double *g_ri,
+                   int ngates) {
+  char *used = (char *)xalloc(m->n);
+  int st = OM_OK;
+  for (int g = 0; g < ngates && st == OM_OK; g++) {
+    int a = q0[g], b = q1[g];
+    if (a < 0 || a >= m->n || b >= m->n || b < -1 || a == b) st = OM_E_ARG;
+    else if (b >= 0 && a - b != 1 && b - a != 1) st = OM_E_NONLOCAL;
+    else if (used[a] || (b >= 0 && used[b])) st = OM_E_OVERLAP;
+    else {
+      used[a] = 1;
+      if (b >= 0) used[b] = 1;
+    }
+  }
+  free(used);
+  if (st != OM_OK) return st;
+  for (int g = 0; g < ngates; g++) {
+    const double *G = g_ri + (size_t)g * 32;
+    int r = q1[g] < 0 ? om_apply_1q(m, q0[g], G) : om_apply_2q(m, q0[g], q1[g], G);
+    if (r != OM_OK) return r;
+  }
+  return OM_OK;
+}
+
+/* ------------------------------------------------------------------ readouts */
+
+static const cplx PAULI_M[4][4] = {
+    {1, 0, 0, 1},   /* I */
+    {0, 1, 1, 0},   /* X */
+    {0, -I, I, 0},  /* Y */
+    {1, 0, 0, -1}}; /* Z */
+
+static int pauli_index(char c) {
+  switch (c) {
+    case 'I': return 0;
+    case 'X': return 1;
+    case 'Y': return 2;
+    case 'Z': return 3;
+  }
+  return -1;
+}
+
+/* <bra| P |ket> by left-to-right transfer contraction:
+   E'[b,b'] = sum conj(B[a,s,b]) P[s,s'] E[a,a'] K[a',s',b'].  bra, ket may be
+   the same MPS.  P == NULL means identity everywhere. */
+static cplx transfer(const om_mps *bra, const om_mps *ket, const int *pidx) {
+  int n = ket->n;
+  cplx *E = (cplx *)xalloc(sizeof(cplx));
+  E[0] = 1.0;
+  for (int q = 0; q < n; q++) {
+    int la = bra->dim[q], lb = ket->dim[q];
+    int ra = bra->dim[q + 1], rb = ket->dim[q + 1];
+    const cplx *B = bra->A[q], *K = ket->A[q];
+    const cplx *P = PAULI_M[pidx ? pidx[q] : 0];
+    /* F[a,s',b'] = sum_a' E[a,a'] K[a',s',b'] */
+    cplx *F = (cplx *)xalloc(sizeof(cplx) * (size_t)la * 2 * rb);
+    for (int a = 0; a < la; a++)
+      for (int ap = 0; ap < lb; ap++) {
+        cplx e = E[(size_t)a * lb + ap];
+        if (e == 0.0) continue;
+        for (int sb = 0; sb < 2 * rb; sb++) F[(size_t)a * 2 * rb + sb] += e * K[(size_t)ap * 2 * rb + sb];
+      }
+    /* F2[a,s,b'] = sum_s' P[s,s'] F[a,s',b'] */
+    cplx *F2 = (cplx *)xalloc(sizeof(cplx) * (size_t)la * 2 * rb);
+    for (int a = 0; a < la; a++)
+      for (int s = 0; s < 2; s++)
+        for (int bp = 0; bp < rb; bp++) {
+          cplx acc = 0.0;
+          for (int sp = 0; sp < 2; sp++) acc += P[2 * s + sp] * F[((size_t)a * 2 + sp) * rb + bp];
+          F2[((size_t)a * 2 + s) * rb + bp] = acc;
+        }
+    free(F);
+    /* E'[b,b'] = sum_{a,s} conj(B[a,s,b]) F2[a,s,b'] */
+    cplx *E2 = (cplx *)xalloc(sizeof(cplx) * (size_t)ra * rb);
+    for (int a = 0; a < la; a++)
+      for (int s = 0; s < 2; s++)
+        for (int b = 0; b < ra; b++) {
+          cplx w = conj(B[((size_t)a * 2 + s) * ra + b]);
+          if (w == 0.0) continue;
+          const cplx *f = F2 + ((size_t)a * 2 + s) * rb;
+          cplx *o = E2 + (size_t)b * rb;
+          for (int bp = 0; bp < rb; bp++) o[bp] += w * f[bp];
+        }
+    free(F2);
+    free(E);
+    E = E2;
+  }
+  cplx v = E[0];
+  free(E);
+  return v;
+}
+
+int om_expect_pauli(const om_mps *m, const char *pauli, double *re, double *im) {
+  int *pidx = (int *)xalloc(sizeof(int) * m->n);
+  for (int q = 0; q < m->n; q++) {
+    pidx[q] = pauli_index(pauli[q]);
+    if (pidx[q] < 0) { free(pidx); return OM_E_ARG; }
+  }
+  cplx num = transfer(m, m, pidx);
+  cplx den = transfer(m, m, NULL);
+  free(pidx);
+  cplx v = num / den;
+  if (re) *re = creal(v);
+  if (im) *im = cimag(v);
+  return OM_OK;
+}
+
+int om_norm2(const om_mps *m, double *out) {
+  *out = creal(transfer(m, m, NULL));
+  return OM_OK;
+}
+
+/* <a|b> */
+int om_overlap(const om_mps *a, const om_mps *b, double *re, double *im) {
+  if (a->n != b->n) return OM_E_ARG;
+  cplx v = transfer(a, b, NULL);
+  *re = creal(v);
+  *im = cimag(v);
+  return OM_OK;
+}
+
+/* <bits|psi> = prod_q A_q[:, bits[q], :] */
+int om_amplitude(const om_mps *m, const uint8_t *bits, double *re, double *im) {
+  cplx *v = (cplx *)xalloc(sizeof(cplx));
+  v[0] = 1.0;
+  for (int q = 0; q < m->n; q++) {
+    if (bits[q] > 1) { free(v); return OM_E_ARG; }
+    int la = m->dim[q], rb = m->dim[q + 1];
+    cplx *w = (cplx *)xalloc(sizeof(cplx) * rb);
+    for (int a = 0; a < la; a++)
+      for (int b = 0; b < rb; b++) w[b] += v[a] * m->A[q][((size_t)a * 2 + bits[q]) * rb + b];
+    free(v);
+    v = w;
+  }
+  *re = creal(v[0]);
+  *im = cimag(v[0]);
+  free(v);
+  return OM_OK;
+}
+
+/* Dense state, index x = sum_q b_q 2^q; out has 2^n interleaved entries. */
+int om_statevector(const om_mps *m, double *out) {
+  int n = m->n;
+  if (n > 24) return OM_E_ARG;
+  size_t cur = 1;
+  cplx *T = (cplx *)xalloc(sizeof(cplx)); /* T[x][b], bond dim 1 */
+  T[0] = 1.0;
+  for (int q = 0; q < n; q++) {
+    int la = m->dim[q], rb = m->dim[q + 1];
+    cplx *T2 = (cplx *)xalloc(sizeof(cplx) * cur * 2 * rb);
+    for (size_t x = 0; x < cur; x++)
+      for (int s = 0; s < 2; s++)
+        for (int a = 0; a < la; a++) {
+          cplx w = T[x * la + a];
+          if (w == 0.0) continue;
+          const cplx *row = m->A[q] + ((size_t)a * 2 + s) * rb;
+          cplx *o = T2 + (x + (size_t)s * cur) * rb;
+          for (int b = 0; b < rb; b++) o[b] += w * row[b];
+        }
+    free(T);
+    T = T2;
+    cur *= 2;
+  }
+  memcpy(out, T, sizeof(cplx) * cur);
+  free(T);
+  return OM_OK;
+}

@@ -1,0 +1,361 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test names the part of the oracle it pins.  None of them compares the
+oracle with itself: expected values come from closed forms, a brute-force
+state vector (numpy), numpy's SVD, Clifford Pauli propagation, or the golden
+fixtures under tests/golden/ (each citing the paper).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from checkers import (amplitude_index, expect_dense, fidelity_dense, pauli_expect_clifford,
+                      schmidt_values, stabilizer_generator, statevector)
+from oracle import oracle as O
+from paper_2601_04422_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _read_table(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append([float(x) for x in line.split()])
+    return rows
+
+
+# ---------------------------------------------------------------- P1: 1q gates
+
+def test_product_state_closed_forms():
+    """Pins init |0...0> and the one-qubit contraction (eq. 3)."""
+    rows = _read_table("product_state.txt")
+    n = 3 * len(rows)
+    m = O.OracleMPS(n, 4)
+    for r, (th, ph, al) in enumerate(rows):
+        m.apply((3 * r, -1, W.ry(th)))
+        m.apply((3 * r, -1, W.rz(ph)))
+        m.apply((3 * r + 1, -1, W.rx(al)))
+    for r, (th, ph, al) in enumerate(rows):
+        def e(q, c):
+            s = ["I"] * n
+            s[q] = c
+            return m.expect("".join(s))
+        assert abs(e(3 * r, "Z") - math.cos(th)) < 1e-14
+        assert abs(e(3 * r, "X") - math.sin(th) * math.cos(ph)) < 1e-14
+        assert abs(e(3 * r, "Y") - math.sin(th) * math.sin(ph)) < 1e-14
+        assert abs(e(3 * r + 1, "Z") - math.cos(al)) < 1e-14
+        assert abs(e(3 * r + 1, "Y") + math.sin(al)) < 1e-14
+        assert abs(e(3 * r + 1, "X")) < 1e-14
+        assert abs(e(3 * r + 2, "Z") - 1.0) < 1e-14  # untouched qubit stays |0>
+    assert list(m.bond_dims()) == [1] * (n - 1)
+
+
+# ---------------------------------------------------------------- P2: untruncated circuits
+
+def test_small_brickwork_matches_statevector():
+    """Pins a3-a8 without truncation: the n=10, depth-10 Haar brickwork at
+    chi_max=32 (no cut possible) against the brute-force state vector."""
+    cfg = W.config_small()
+    m = O.OracleMPS(cfg.n, cfg.chi_max, cfg.cutoff)
+    m.run_layers(cfg.layers)
+    ref = statevector(cfg.n, cfg.gates())
+    got = m.statevector()
+    assert np.max(np.abs(got - ref)) < 1e-12
+    rng = np.random.default_rng(7)
+    for _ in range(20):
+        bits = rng.integers(0, 2, cfg.n)
+        assert abs(m.amplitude(bits) - ref[amplitude_index(bits)]) < 1e-12
+    assert m.stats()["sum_eps"] < 1e-24
+
+
+@pytest.mark.parametrize("seed", [11, 12, 13])
+def test_random_circuits_with_1q_and_reversed_gates(seed):
+    """Mixed 1q/2q gates, gates given as (q, q-1), odd n: brute force."""
+    rng = np.random.default_rng(seed)
+    n = 7
+    gates = []
+    for _ in range(40):
+        if rng.random() < 0.4:
+            q = int(rng.integers(0, n))
+            gates.append((q, -1, W.rot("XYZ"[int(rng.integers(0, 3))], rng.uniform(0, 6.3))))
+        else:
+            j = int(rng.integers(0, n - 1))
+            g = W.haar_u4(rng)
+            gates.append((j, j + 1, g) if rng.random() < 0.5 else (j + 1, j, g))
+    m = O.run_gates(n, 64, 0.0, gates)
+    ref = statevector(n, gates)
+    assert np.max(np.abs(m.statevector() - ref)) < 1e-12
+
+
+# ---------------------------------------------------------------- P3: GHZ golden
+
+def test_ghz_golden():
+    """Sec. V.A: GHZ = (|0..0> + |1..1>)/sqrt(2) with chi = 2 on every bond."""
+    for n, a0, a1, chi in _read_table("ghz.txt"):
+        n = int(n)
+        m = O.run_gates(n, 64, 0.0, W.ghz(n))
+        assert abs(m.amplitude([0] * n) - a0) < 1e-14
+        assert abs(m.amplitude([1] * n) - a1) < 1e-14
+        bits = [0] * n
+        bits[n // 2] = 1
+        assert abs(m.amplitude(bits)) < 1e-14
+        assert max(m.bond_dims()) <= chi
+        assert int(max(m.bond_dims())) == int(chi)
+
+
+# ---------------------------------------------------------------- P4, P5: spectra, norms
+
+def test_lambda_are_schmidt_values_and_norm():
+    """lambda_q equals the Schmidt spectrum of the exact state at cut q (P4);
+    <psi|psi> = 1 and sum lambda^2 = 1 (P5)."""
+    n = 8
+    layers = W.brickwork_haar(n, 7, 2024)
+    gates = [g for l in layers for g in l]
+    m = O.OracleMPS(n, 256, 0.0)
+    m.run_layers(layers)
+    psi = statevector(n, gates)
+    for b in range(n - 1):
+        ref = schmidt_values(psi, n, b)
+        lam = m.lam(b)
+        ref = ref[: lam.size]
+        assert np.max(np.abs(lam - ref)) < 1e-12
+        assert abs(np.sum(lam ** 2) - 1) < 1e-12
+    assert abs(m.norm2() - 1) < 1e-12
+    # left-canonical sites (the gauge reading): sum_{a,s} conj(A) A = I
+    for q in range(n - 1):
+        a = m.site(q)
+        mat = a.reshape(-1, a.shape[2])
+        assert np.max(np.abs(mat.conj().T @ mat - np.eye(a.shape[2]))) < 1e-12
+
+
+# ---------------------------------------------------------------- P6: truncation weight
+
+def test_truncation_error_equals_discarded_weight():
+    """On an exactly canonical state one truncated gate gives
+    1 - F(exact, truncated) = eps and ||psi_exact - N psi_trunc||^2 = eps."""
+    n = 8
+    layers = W.brickwork_haar(n, 6, 77)
+    exact = O.OracleMPS(n, 256, 0.0)
+    exact.run_layers(layers)
+    sites = [exact.site(q) for q in range(n)]
+    lams = [exact.lam(b) for b in range(n - 1)]
+    rng = np.random.default_rng(5)
+    g = W.haar_u4(rng)
+    bond = 3
+    full = O.OracleMPS(n, 256, 0.0)
+    full.set_state(sites, lams)
+    full.apply_2q(bond, bond + 1, g)
+    chi_before = exact.bond_dims()[bond]
+    for chi_cut in (chi_before // 2, chi_before // 4, 1):
+        tr = O.OracleMPS(n, chi_cut, 0.0)
+        tr.set_state(sites, lams)
+        assert tr.apply_2q(bond, bond + 1, g) == O.OK
+        eps = tr.stats()["last_eps"]
+        assert eps > 1e-6
+        psi_e = full.statevector()
+        psi_t = tr.statevector()
+        f = fidelity_dense(psi_e, psi_t)
+        assert abs((1 - f) - eps) < 1e-12
+        assert abs(np.sum(np.abs(psi_e - math.sqrt(1 - eps) * psi_t) ** 2) - eps) < 1e-12
+        assert abs(np.sum(tr.lam(bond) ** 2) - 1) < 1e-12  # kept weights renormalised
+        # discarded weight from the exact Schmidt spectrum at that bond
+        lam_full = full.lam(bond)
+        assert abs(np.sum(lam_full[chi_cut:] ** 2) - eps) < 1e-12
+
+
+# ---------------------------------------------------------------- P7: SVD
+
+@pytest.mark.parametrize("shape", [(6, 6), (16, 8), (8, 16), (64, 64), (40, 128), (130, 70)])
+def test_jacobi_svd_against_numpy(shape):
+    """The oracle's Jacobi SVD against numpy's LAPACK SVD: singular values,
+    orthonormal U, and U U^H M = M (U spans the column space)."""
+    rng = np.random.default_rng(sum(shape))
+    a = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    u, s, sweeps = O.svd(a)
+    ref = np.linalg.svd(a, compute_uv=False)
+    assert sweeps > 0
+    assert np.max(np.abs(s - ref)) / ref[0] < 1e-13
+    r = min(shape)
+    assert np.max(np.abs(u.conj().T @ u - np.eye(r))) < 1e-13
+    assert np.linalg.norm(a - u @ (u.conj().T @ a)) / np.linalg.norm(a) < 1e-13
+    # sigma_j = || u_j^H M ||
+    assert np.max(np.abs(np.linalg.norm(u.conj().T @ a, axis=1) - s)) / s[0] < 1e-13
+
+
+def test_jacobi_svd_graded_and_rank_deficient():
+    rng = np.random.default_rng(9)
+    q1 = W.random_isometry(rng, 50, 50)
+    q2 = W.random_isometry(rng, 50, 50)
+    sig = np.logspace(0, -12, 50)
+    a = (q1 * sig) @ q2.conj().T
+    u, s, _ = O.svd(a)
+    # forming a in floating point perturbs it by ~1e-16 * ||a||: absolute accuracy
+    # at that level for all values, relative accuracy for the values well above it
+    assert np.max(np.abs(s - sig)) < 1e-13
+    big = sig > 1e-6
+    assert np.max(np.abs(s[big] - sig[big]) / sig[big]) < 1e-9
+    # rank 3 in a 20 x 20 matrix
+    b = W.random_isometry(rng, 20, 3) @ W.random_isometry(rng, 20, 3).conj().T
+    _, s2, _ = O.svd(b)
+    assert np.allclose(s2[:3], 1.0, atol=1e-13) and np.max(s2[3:]) < 1e-13
+
+
+def test_noconvergence_is_reported():
+    rng = np.random.default_rng(1)
+    a = rng.standard_normal((32, 32)) + 1j * rng.standard_normal((32, 32))
+    with pytest.raises(O.OracleError) as e:
+        O.svd(a, max_sweeps=1)
+    assert e.value.code == O.E_NOCONV
+    # a sweep with no rotation is needed to stop, so one sweep never suffices
+    m = O.OracleMPS(4, 16, 0.0, max_sweeps=1)
+    assert m.apply_2q(1, 2, W.haar_u4(rng)) == O.E_NOCONV
+    assert list(m.bond_dims()) == [1, 1, 1]  # state left unchanged
+
+
+# ---------------------------------------------------------------- truncation rule
+
+def test_truncation_rule():
+    # sigma^2 = [9/16, 1/4, 1/16, 1/16, 1/16]: dyadic, so W = 1 and every tail is exact
+    s = np.array([0.75, 0.5, 0.25, 0.25, 0.25])
+    # a tail exactly equal to cutoff * W is discarded (tail <= cutoff * W)
+    assert O.truncation(s, 10, 99, 0.0625)[0] == 4
+    assert O.truncation(s, 10, 99, 0.0625 - 1e-12)[0] == 5
+    assert O.truncation(s, 10, 99, 0.125)[0] == 3
+    k, eps, nrm = O.truncation(s, 10, 2, 0.0)
+    assert k == 2 and abs(eps - 0.1875) < 1e-15 and abs(nrm - math.sqrt(0.8125)) < 1e-15
+    assert O.truncation(s, 10, 99, 10.0)[0] == 1  # k >= 1
+    # numerical-zero floor: sigma^2 <= rows * 2^-53 * sigma_1^2
+    z = np.array([1.0, 1e-3, 1e-9])
+    assert O.truncation(z, 4, 99, 0.0)[0] == 2
+    assert O.truncation(np.array([1.0, 3e-8]), 2, 99, 0.0)[0] == 2
+    assert O.truncation(np.array([1.0, 1e-8]), 2, 99, 0.0)[0] == 1
+
+
+# ---------------------------------------------------------------- P8: layer order
+
+def test_layer_order_independence():
+    n = 10
+    layers = W.brickwork_haar(n, 6, 31)
+    a = O.OracleMPS(n, 8, 1e-10)
+    b = O.OracleMPS(n, 8, 1e-10)
+    rng = np.random.default_rng(0)
+    for layer in layers:
+        assert a.apply_layer(layer) == O.OK
+        perm = rng.permutation(len(layer))
+        assert b.apply_layer([layer[i] for i in perm]) == O.OK
+    for q in range(n):
+        assert np.array_equal(a.site(q), b.site(q))
+    assert a.stats()["sum_eps"] > 0  # the check runs with truncation active
+
+
+def test_layer_validation():
+    m = O.OracleMPS(6, 8)
+    g = W.cnot()
+    assert m.apply_layer([(0, 1, g), (1, 2, g)]) == O.E_OVERLAP
+    assert m.apply_layer([(0, 2, g)]) == O.E_NONLOCAL
+    assert m.apply_layer([(5, 6, g)]) == O.E_ARG
+    assert m.apply_layer([(0, -1, W.hadamard()), (0, 1, g)]) == O.E_OVERLAP
+    assert list(m.bond_dims()) == [1] * 5  # state unchanged
+
+
+# ---------------------------------------------------------------- P9: large-n structure
+
+def test_basis_state_circuit_n100():
+    """Rx in {0, pi}: CNOTs act as reversible logic, chi stays 1, |amp| = 1."""
+    n, nl = 100, 12
+    layers = W.rxrz_cnot_layers(n, nl, 3, angle_set=[0.0, math.pi])
+    m = O.OracleMPS(n, 1024, 1e-12)
+    m.run_layers(layers)
+    bits = [0] * n
+    for layer in layers:
+        for q0, q1, g in layer:
+            if q1 < 0:
+                if abs(abs(g[0, 1]) - 1) < 1e-12:  # Rx(pi) flips, Rz keeps
+                    bits[q0] ^= 1
+            elif bits[q0]:
+                bits[q1] ^= 1
+    assert max(m.bond_dims()) == 1
+    assert abs(abs(m.amplitude(bits)) - 1) < 1e-12
+    for q in (0, 17, 50, 99):
+        s = ["I"] * n
+        s[q] = "Z"
+        assert abs(m.expect("".join(s)).real - (1 - 2 * bits[q])) < 1e-12
+
+
+def test_clifford_circuit_against_pauli_propagation():
+    """Angles in multiples of pi/2: a stabiliser state; <Z_i>, <Z_i Z_i+1>
+    in {0, +-1} from Pauli propagation (no truncation reached)."""
+    n, nl = 40, 8
+    layers = W.rxrz_cnot_layers(n, nl, 4, angle_set=[0.0, math.pi / 2, math.pi, 3 * math.pi / 2])
+    gates = [g for l in layers for g in l]
+    m = O.OracleMPS(n, 1024, 1e-12)
+    m.run_layers(layers)
+    checked_nonzero = 0
+    for q in range(0, n - 2):
+        for ops in (("Z",), ("Z", "Z"), ("X", "X"), ("Y", "Z"), ("X", "Y", "Z"), ("Z", "X", "Z")):
+            s = ["I"] * n
+            for k, c in enumerate(ops):
+                s[q + k] = c
+            s = "".join(s)
+            ref = pauli_expect_clifford(n, gates, s)
+            got = m.expect(s)
+            assert abs(got - ref) < 1e-12, (s, got, ref)
+            checked_nonzero += abs(ref) > 0.5
+    # stabiliser generators U Z_q U^dag have expectation exactly 1/c
+    for q in range(0, n, 5):
+        c, pstr = stabilizer_generator(n, gates, q)
+        assert abs(m.expect(pstr) - 1 / c) < 1e-12, (q, pstr)
+        assert abs(pauli_expect_clifford(n, gates, pstr) - 1 / c) < 1e-12
+        checked_nonzero += 1
+    assert checked_nonzero >= 3
+    assert max(m.bond_dims()) >= 4
+
+
+# ---------------------------------------------------------------- P10: gradients
+
+def test_ansatz_closed_form_and_parameter_shift():
+    """No CNOTs: L = sum_i cos(t_i) cos(t_{i+1}) over the Ry angles, dL/dRz = 0."""
+    n = 6
+    angles = W.ansatz_angles(n, 1, 42)
+    gates = W.ansatz_gates(angles, n, 1, ladder=False)
+    paulis = W.zz_chain(n)
+    coeffs = [1.0] * len(paulis)
+    m = O.run_gates(n, 16, 0.0, gates)
+    th = angles[0::2]
+    ref = sum(math.cos(th[i]) * math.cos(th[i + 1]) for i in range(n - 1))
+    assert abs(O.loss_pauli_sum(m, paulis, coeffs) - ref) < 1e-13
+    g = O.parameter_shift(lambda a: W.ansatz_gates(a, n, 1, ladder=False), angles, n, 16, 0.0,
+                          paulis, coeffs)
+    gref = np.zeros_like(angles)
+    for i in range(n):
+        nb = (math.cos(th[i - 1]) if i > 0 else 0.0) + (math.cos(th[i + 1]) if i < n - 1 else 0.0)
+        gref[2 * i] = -math.sin(th[i]) * nb
+    assert np.max(np.abs(g - gref)) < 1e-12
+
+
+def test_parameter_shift_matches_finite_differences_with_cnots():
+    n, nl = 5, 2
+    angles = W.ansatz_angles(n, nl, 3)
+    paulis = W.zz_chain(n)
+    coeffs = [1.0] * len(paulis)
+    make = lambda a: W.ansatz_gates(a, n, nl)
+    g = O.parameter_shift(make, angles, n, 64, 0.0, paulis, coeffs)
+    h = 1e-5
+    fd = np.zeros_like(angles)
+    for p in range(angles.size):
+        vals = []
+        for sgn in (1, -1):
+            a = angles.copy()
+            a[p] += sgn * h
+            vals.append(O.loss_pauli_sum(O.run_gates(n, 64, 0.0, make(a)), paulis, coeffs))
+        fd[p] = (vals[0] - vals[1]) / (2 * h)
+    assert np.max(np.abs(g - fd)) < 1e-8
+    # and the loss itself against the brute-force state vector
+    psi = statevector(n, make(angles))
+    ref = sum(expect_dense(psi, n, p).real for p in paulis)
+    assert abs(O.loss_pauli_sum(O.run_gates(n, 64, 0.0, make(angles)), paulis, coeffs) - ref) < 1e-12
