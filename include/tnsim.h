@@ -1,0 +1,181 @@
+/*
+ * tnsim.h -- C ABI of the MI355X (gfx950) MPS gate-application library.
+ *
+ * The library applies quantum gates to a Matrix Product State (arXiv
+ * 2601.04422, Sec. II eq. 2 for the state, Sec. III.A for the gate
+ * algorithms, Sec. IV.A for the merge of two sites and the truncated SVD).
+ *
+ * Conventions
+ *   - Site q holds A_q[a,s,b] of shape (chi_{q-1}, 2, chi_q), row-major;
+ *     bond q joins sites q and q+1 and has dimension chi_q; the outer bonds
+ *     have dimension 1.  The state starts as |0...0> with every bond of
+ *     dimension 1 (Sec. IV.A).
+ *   - Gauge: every site is left-canonical and each bond carries its Schmidt
+ *     weights lambda_q (float64).  A two-qubit gate on (i, i+1) decomposes
+ *     theta' * diag(lambda_{i+1}) and writes A_i' = U_k (left singular
+ *     vectors on the left/control site), lambda_i' = sigma/N and
+ *     A_{i+1}' = U_k^H theta' / N (singular values folded into the right
+ *     site, Sec. III.A), N = sqrt(sum of kept sigma^2).
+ *   - Truncation: k is the smallest k >= 1 whose discarded weight
+ *     sum_{j>k} sigma_j^2 <= cutoff * sum_j sigma_j^2, capped by chi_max and
+ *     by the count of sigma_j^2 > 2*chi_L * 2^-53 * sigma_1^2.
+ *   - Gate matrices are complex128.  A 4x4 gate is row-major in the basis
+ *     |s_q0 s_q1> with row 2*s_q0 + s_q1.  (q0, q0+1) and (q0, q0-1) are both
+ *     accepted; the second applies SWAP*G*SWAP on (q0-1, q0).
+ *
+ * Memory and streams
+ *   - The caller allocates one device buffer of tnsim_mps_arena_bytes(cfg)
+ *     bytes (any device allocator; 256-byte alignment) and passes it with a
+ *     hipStream_t to tnsim_mps_create.  Buffer and stream must outlive the
+ *     handle; the handle owns host metadata and a small pinned staging
+ *     buffer only.
+ *   - Host arrays passed in (gates, bits, Pauli strings) are copied before the
+ *     call returns.  Output pointers are host memory.
+ *   - tnsim_apply_* enqueue on the handle's stream.  The Jacobi sweep loop
+ *     synchronises the stream to test convergence, so they return after the
+ *     gate work is done.  Readouts synchronise.
+ *
+ * Errors
+ *   - Every argument is validated on the host before any device work; on an
+ *     argument error the state is unchanged.
+ *   - A failed HIP call poisons the handle: every later call returns
+ *     TNSIM_E_DEVICE.  tnsim_last_error describes the first failure.
+ *   - TNSIM_E_NOCONV: the Jacobi SVD of some gate did not converge within
+ *     jacobi_max_sweeps; the two-qubit gates of that call are not written
+ *     back (their sites keep the previous values) and the handle stays usable.
+ */
+#ifndef TNSIM_H
+#define TNSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tnsim_mps_s *tnsim_mps;
+
+typedef struct {
+  double re, im;
+} tnsim_c128;
+
+typedef enum {
+  TNSIM_OK = 0,
+  TNSIM_E_ARG = 1,      /* bad argument (qubit out of range, bad config, NULL) */
+  TNSIM_E_NONLOCAL = 2, /* two-qubit gate on non-neighbouring qubits */
+  TNSIM_E_OVERLAP = 3,  /* a layer uses a qubit twice */
+  TNSIM_E_CAPACITY = 4, /* arena too small for the configuration */
+  TNSIM_E_DEVICE = 5,   /* HIP runtime failure, or no device */
+  TNSIM_E_NOCONV = 6    /* Jacobi sweeps exhausted */
+} tnsim_status;
+
+/* Arithmetic of the theta contraction and the right-site write-back.  The
+   SVD (column Gram blocks, Jacobi rotations, norms, truncation) is float64 in
+   every mode. */
+typedef enum {
+  TNSIM_FP64 = 0,   /* float64 everywhere */
+  TNSIM_F32ACC = 1, /* float32 products, float32 accumulation (MFMA) */
+  TNSIM_BF16X3 = 2, /* float32 operands split into bf16 pieces, 3 MFMA products */
+  TNSIM_BF16X6 = 3  /* same with 6 products (about float32 accuracy) */
+} tnsim_precision;
+
+typedef enum {
+  TNSIM_STORE_C128 = 0, /* site tensors complex128 */
+  TNSIM_STORE_C64 = 1   /* site tensors complex64 (Schmidt weights stay float64) */
+} tnsim_storage;
+
+typedef struct {
+  int32_t n_qubits;          /* >= 2 */
+  int32_t chi_max;           /* 1 .. 2048 */
+  double cutoff;             /* discarded-weight cutoff, >= 0 */
+  int32_t precision;         /* tnsim_precision */
+  int32_t storage;           /* tnsim_storage */
+  int32_t jacobi_max_sweeps; /* <= 0 selects 60 */
+  double jacobi_tol;         /* <= 0 selects max(rows, 16) * 2^-53 */
+  int32_t max_layer_gates;   /* two-qubit gates processed together; <= 0 selects n/2 */
+} tnsim_config;
+
+typedef struct {
+  int32_t q0, q1;     /* q1 = -1 marks a one-qubit gate */
+  tnsim_c128 m[16];   /* 2x2 in m[0..3] (row-major) or 4x4 row-major */
+} tnsim_gate;
+
+/* Bytes of device memory a handle with this configuration needs; 0 if the
+   configuration is invalid. */
+size_t tnsim_mps_arena_bytes(const tnsim_config *cfg);
+
+/* Create a handle on the current HIP device, initialised to |0...0>
+   (Sec. IV.A).  dev_arena: device pointer of arena_bytes bytes; hip_stream:
+   a hipStream_t (NULL = default stream). */
+tnsim_status tnsim_mps_create(const tnsim_config *cfg, void *dev_arena, size_t arena_bytes,
+                              void *hip_stream, tnsim_mps *out);
+tnsim_status tnsim_mps_destroy(tnsim_mps mps);
+
+/* Reset to |0...0> and clear the truncation statistics. */
+tnsim_status tnsim_mps_reset(tnsim_mps mps);
+
+/* One-qubit gate A'[a,s',b] = sum_s U[s',s] A[a,s,b]  (Sec. II, eq. 3). */
+tnsim_status tnsim_apply_1q(tnsim_mps mps, int32_t q, const tnsim_c128 u[4]);
+
+/* Local two-qubit gate, one gate per launch sequence: merge the two sites
+   (Sec. IV.A, Fig. 2), contract with the gate, Jacobi SVD, truncate, write
+   back (Sec. III.A). |q0-q1| must be 1. */
+tnsim_status tnsim_apply_2q(tnsim_mps mps, int32_t q0, int32_t q1, const tnsim_c128 g[16]);
+
+/* All gates of one layer of gates on disjoint qubits (Sec. IV.B): the
+   one-qubit gates in one launch, then every two-qubit gate of the layer in
+   the same launches (batched over gates). */
+tnsim_status tnsim_apply_layer(tnsim_mps mps, const tnsim_gate *gates, int32_t n_gates);
+
+/* Independent circuits: layer l of every handle, batched together.  All
+   handles must share one stream and one configuration class (precision and
+   storage); gates[i] has n_gates[i] entries for handle i. */
+tnsim_status tnsim_apply_layer_multi(tnsim_mps const *mps, const tnsim_gate *const *gates,
+                                     const int32_t *n_gates, int32_t n_mps);
+
+/* Greedy layering (Sec. IV.B): each gate goes to the first layer after the
+   last one that used any of its qubits.  layer_of_gate[g] receives the layer
+   index, *n_layers the count.  Host-only. */
+tnsim_status tnsim_layerise(const tnsim_gate *gates, int32_t n_gates, int32_t n_qubits,
+                            int32_t *layer_of_gate, int32_t *n_layers);
+
+/* <psi|P|psi> / <psi|psi> for a Pauli string P (n chars of I, X, Y, Z; char q
+   acts on qubit q) by full left-to-right transfer contraction. im_out may be
+   NULL. */
+tnsim_status tnsim_expect_pauli(tnsim_mps mps, const char *pauli, double *re_out,
+                                double *im_out);
+
+/* <bits|psi> = prod_q A_q[:, bits[q], :]; bits has n entries of 0/1. */
+tnsim_status tnsim_amplitude(tnsim_mps mps, const uint8_t *bits, tnsim_c128 *out);
+
+/* <a|b> by transfer contraction (both handles on the same device). */
+tnsim_status tnsim_overlap(tnsim_mps a, tnsim_mps b, tnsim_c128 *out);
+
+/* Copy the state of src into dst (same n; storage converted; dst's chi_max
+   must hold src's bond dimensions). */
+tnsim_status tnsim_mps_copy(tnsim_mps dst, tnsim_mps src);
+
+/* ---- inspection, import/export (synchronising) ---- */
+tnsim_status tnsim_bond_dims(tnsim_mps mps, int32_t *out /* n-1 */);
+/* sum of discarded weights, product of (1 - eps) over gates, gate count */
+tnsim_status tnsim_truncation_stats(tnsim_mps mps, double *sum_eps, double *prod_1_minus_eps,
+                                    int64_t *n2q);
+/* Largest Jacobi sweep count used by the last apply call. */
+tnsim_status tnsim_last_sweeps(tnsim_mps mps, int32_t *sweeps);
+/* Site q as complex128 (chiL*2*chiR entries); host may be NULL to query dims. */
+tnsim_status tnsim_export_site(tnsim_mps mps, int32_t q, tnsim_c128 *host, int32_t *chiL,
+                               int32_t *chiR);
+tnsim_status tnsim_export_lambda(tnsim_mps mps, int32_t bond, double *host, int32_t *chi);
+/* Replace the state: sites[q] (chis[q] x 2 x chis[q+1], complex128), lambdas[b]
+   (chis[b+1] values); chis has n+1 entries, chis[0] = chis[n] = 1. */
+tnsim_status tnsim_import_state(tnsim_mps mps, const tnsim_c128 *const *sites,
+                                const double *const *lambdas, const int32_t *chis);
+
+const char *tnsim_status_string(tnsim_status st);
+const char *tnsim_last_error(tnsim_mps mps);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TNSIM_H */

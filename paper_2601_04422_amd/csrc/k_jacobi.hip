@@ -1,0 +1,469 @@
+// Truncated SVD of M by block one-sided Jacobi in float64.
+//
+// The paper decomposes the merged two-site tensor with a Jacobi SVD on the
+// GPU (Sec. IV.A, cusolverDnZgesvdj).  Here the columns of X (X = M, or M^H
+// when M is wide, with J accumulating the left vectors) are split into
+// blocks of 32.  A sweep runs the round-robin tournament over the blocks; in
+// one round every block is paired with one other block, and for every pair:
+//
+//   k_gram : G = X_IJ^H X_IJ (64x64 Hermitian), split over row chunks;
+//   k_eig  : G = V D V^H by cyclic two-sided Jacobi in LDS; a pair whose
+//            columns are already orthogonal to tolerance is left alone;
+//   k_rot  : X_IJ <- X_IJ V (and J_IJ <- J_IJ V).
+//
+// All pairs of all gates of a batch run in the same launches.  The sweep
+// ends the rounds; a gate converges after a sweep in which no pair rotated.
+// Then k_colnorm gives sigma_j^2 = ||x_j||^2 and k_trunc sorts them and
+// applies the truncation rule.
+#include "tnsim_internal.h"
+#include "tn_complex.h"
+
+namespace tn {
+
+constexpr double SMALL_REL = 0x1p-200;  // columns below this fraction of ||X||_F^2 are zero
+
+// Round-robin tournament: pair k of round r over P players (P even).
+__device__ __forceinline__ void rr_pair(int r, int k, int P, int &p, int &q) {
+  if (k == 0) {
+    p = P - 1;
+    q = r;
+  } else {
+    p = (r + k) % (P - 1);
+    q = (r - k + (P - 1)) % (P - 1);
+  }
+  if (p > q) {
+    int t = p;
+    p = q;
+    q = t;
+  }
+}
+
+__device__ __forceinline__ int pair_col(int I, int J, int p) {
+  return p < BW ? I * BW + p : J * BW + (p - BW);
+}
+
+// ---------------------------------------------------------------- setup
+
+// Zero X's padding columns; J = identity (trans gates).
+__global__ void k_setup_slots(const GateDesc *descs) {
+  const GateDesc &d = descs[blockIdx.y];
+  int col = blockIdx.x;
+  if (col < d.colsPad && col >= d.cols) {
+    for (int r = threadIdx.x; r < d.ldx; r += blockDim.x)
+      d.X[(size_t)col * d.ldx + r] = make_double2(0.0, 0.0);
+  }
+  if (d.trans && col < d.colsPad) {
+    for (int r = threadIdx.x; r < d.ldj; r += blockDim.x)
+      d.J[(size_t)col * d.ldj + r] = make_double2(r == col ? 1.0 : 0.0, 0.0);
+  }
+}
+
+void launch_setup_slots(hipStream_t st, const GateDesc *d, int ng, int max_cols_pad, int) {
+  if (ng <= 0) return;
+  hipLaunchKernelGGL(k_setup_slots, dim3(max_cols_pad, ng), dim3(256), 0, st, d);
+}
+
+// sigma_j^2 = ||x_j||^2, one wavefront per column.
+__global__ __launch_bounds__(256) void k_colnorm(const GateDesc *descs) {
+  const GateDesc &d = descs[blockIdx.y];
+  int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int col = blockIdx.x * 4 + wave;
+  if (col >= d.colsPad) return;
+  const double2 *x = d.X + (size_t)col * d.ldx;
+  double s = 0.0;
+  for (int r = lane; r < d.rows; r += 64) s += cabs2(x[r]);
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) d.sig2[col] = s;
+}
+
+void launch_colnorm(hipStream_t st, const GateDesc *d, int ng, int max_cols) {
+  if (ng <= 0) return;
+  hipLaunchKernelGGL(k_colnorm, dim3((max_cols + 3) / 4, ng), dim3(256), 0, st, d);
+}
+
+// ||X||_F^2 in a fixed order; all gates start active.
+__global__ void k_gate_init(const GateDesc *descs) {
+  const GateDesc &d = descs[blockIdx.x];
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int j = 0; j < d.cols; j++) s += d.sig2[j];
+    d.sc->fro2 = s;
+    d.sc->rot = 1;
+    d.sc->active = 1;
+    d.sc->k = 0;
+  }
+}
+
+void launch_gate_init(hipStream_t st, const GateDesc *d, int ng) {
+  if (ng <= 0) return;
+  hipLaunchKernelGGL(k_gate_init, dim3(ng), dim3(64), 0, st, d);
+}
+
+// A gate keeps sweeping only if some pair rotated in the previous sweep.
+__global__ void k_begin_sweep(const GateDesc *descs, int ng) {
+  int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ng) return;
+  SlotScalars *sc = descs[g].sc;
+  sc->active = sc->rot;
+  sc->rot = 0;
+}
+
+void launch_begin_sweep(hipStream_t st, const GateDesc *d, int ng) {
+  if (ng <= 0) return;
+  hipLaunchKernelGGL(k_begin_sweep, dim3((ng + 63) / 64), dim3(64), 0, st, d, ng);
+}
+
+// ---------------------------------------------------------------- Gram of a column pair
+
+constexpr int GK = 32;  // rows per LDS tile
+
+__global__ __launch_bounds__(256) void k_gram(const GateDesc *descs, int round, int ksplit,
+                                              int npairs_stride) {
+  const GateDesc &d = descs[blockIdx.y];
+  const int pairIdx = blockIdx.x / ksplit, kc = blockIdx.x % ksplit;
+  if (!d.sc->active || round >= d.nblk - 1 || pairIdx >= d.nblk / 2) return;
+  int I, J;
+  rr_pair(round, pairIdx, d.nblk, I, J);
+  int chunk = (d.rows + ksplit - 1) / ksplit;
+  chunk = (chunk + GK - 1) / GK * GK;
+  const int rbeg = kc * chunk;
+  const int rend = min(d.rows, rbeg + chunk);
+
+  __shared__ double2 Xs[GK][PW + 1];
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  double2 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; i++)
+#pragma unroll
+    for (int j = 0; j < 4; j++) acc[i][j] = make_double2(0.0, 0.0);
+
+  const int lcol = tid >> 2, lr = (tid & 3) * 8;
+  const double2 *xcol = d.X + (size_t)pair_col(I, J, lcol) * d.ldx;
+  for (int r0 = rbeg; r0 < rend; r0 += GK) {
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+      int r = r0 + lr + j;
+      Xs[lr + j][lcol] = r < rend ? xcol[r] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int k = 0; k < GK; k++) {
+      double2 a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; i++) a[i] = Xs[k][ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; j++) b[j] = Xs[k][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) cfmac(acc[i][j], a[i], b[j]);
+    }
+    __syncthreads();
+  }
+  double2 *G = d.Gp + ((size_t)kc * npairs_stride + pairIdx) * (PW * PW);
+#pragma unroll
+  for (int i = 0; i < 4; i++)
+#pragma unroll
+    for (int j = 0; j < 4; j++) G[(ty + 16 * i) * PW + tx + 16 * j] = acc[i][j];
+}
+
+// ---------------------------------------------------------------- 64x64 Hermitian Jacobi
+
+constexpr int LDG = PW + 1;
+constexpr int INNER_MAX_SWEEPS = 30;
+
+__global__ __launch_bounds__(256) void k_eig(const GateDesc *descs, int round, int ksplit,
+                                             int npairs_stride) {
+  const GateDesc &d = descs[blockIdx.y];
+  const int pairIdx = blockIdx.x;
+  if (!d.sc->active || round >= d.nblk - 1 || pairIdx >= d.nblk / 2) return;
+  __shared__ double2 Gs[PW * LDG];
+  __shared__ double2 Vs[PW * LDG];
+  __shared__ double rc[PW / 2];        // cos
+  __shared__ double2 rse[PW / 2];      // s * e^{i phi}
+  __shared__ double rt[PW / 2];        // t*|g| (diagonal shift)
+  __shared__ int rp[PW / 2], rq[PW / 2], ract[PW / 2];
+  __shared__ int any_rot, sweep_rot, first_rot;
+  const int tid = threadIdx.x;
+  const double tol = d.tol;
+  const double small = d.sc->fro2 * SMALL_REL;
+
+  for (int e = tid; e < PW * PW; e += 256) {
+    double2 s = make_double2(0.0, 0.0);
+    for (int kc = 0; kc < ksplit; kc++) {
+      double2 v = d.Gp[((size_t)kc * npairs_stride + pairIdx) * (PW * PW) + e];
+      s.x += v.x;
+      s.y += v.y;
+    }
+    int r = e / PW, c = e % PW;
+    Gs[r * LDG + c] = s;
+    Vs[r * LDG + c] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+  }
+  if (tid == 0) first_rot = 0;
+  __syncthreads();
+
+  for (int sweep = 0; sweep < INNER_MAX_SWEEPS; sweep++) {
+    if (tid == 0) sweep_rot = 0;
+    __syncthreads();
+    for (int r = 0; r < PW - 1; r++) {
+      if (tid == 0) any_rot = 0;
+      __syncthreads();
+      if (tid < PW / 2) {
+        int p, q;
+        rr_pair(r, tid, PW, p, q);
+        rp[tid] = p;
+        rq[tid] = q;
+        double a = Gs[p * LDG + p].x, b = Gs[q * LDG + q].x;
+        double2 g = Gs[p * LDG + q];
+        double ag = sqrt(cabs2(g));
+        int act = 0;
+        if (a > small && b > small && ag > tol * sqrt(a) * sqrt(b)) {
+          act = 1;
+          double2 e = make_double2(g.x / ag, g.y / ag);  // e^{i phi}
+          double zeta = (b - a) / (2.0 * ag);
+          double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          double c = 1.0 / sqrt(1.0 + t * t);
+          double s = c * t;
+          rc[tid] = c;
+          rse[tid] = make_double2(s * e.x, s * e.y);
+          rt[tid] = t * ag;
+          any_rot = 1;  // benign race: every writer stores 1
+        }
+        ract[tid] = act;
+      }
+      __syncthreads();
+      if (any_rot) {
+        // columns: [g_p g_q] <- [g_p g_q] R,  R = [[c, s e^{i phi}], [-s e^{-i phi}, c]]
+        for (int task = tid; task < (PW / 2) * PW * 2; task += 256) {
+          int k = task & (PW / 2 - 1);
+          int row = (task >> 5) & (PW - 1);
+          int mat = task >> 11;  // 0: G, 1: V
+          if (!ract[k]) continue;
+          double2 *Mx = mat ? Vs : Gs;
+          int p = rp[k], q = rq[k];
+          double c = rc[k];
+          double2 se = rse[k];
+          double2 xp = Mx[row * LDG + p], xq = Mx[row * LDG + q];
+          // x_p' = c x_p - conj(se) x_q ; x_q' = se x_p + c x_q
+          double2 np_ = csub(cscale(xp, c), cmul(cconj(se), xq));
+          double2 nq_ = cadd(cmul(se, xp), cscale(xq, c));
+          Mx[row * LDG + p] = np_;
+          Mx[row * LDG + q] = nq_;
+        }
+        __syncthreads();
+        // rows: [g_p; g_q] <- R^H [g_p; g_q]
+        for (int task = tid; task < (PW / 2) * PW; task += 256) {
+          int k = task & (PW / 2 - 1);
+          int col = task >> 5;
+          if (!ract[k]) continue;
+          int p = rp[k], q = rq[k];
+          double c = rc[k];
+          double2 se = rse[k];
+          double2 yp = Gs[p * LDG + col], yq = Gs[q * LDG + col];
+          // row_p' = c row_p - se row_q ; row_q' = conj(se) row_p + c row_q
+          Gs[p * LDG + col] = csub(cscale(yp, c), cmul(se, yq));
+          Gs[q * LDG + col] = cadd(cmul(cconj(se), yp), cscale(yq, c));
+        }
+        __syncthreads();
+        if (tid < PW / 2 && ract[tid]) {
+          int p = rp[tid], q = rq[tid];
+          double a = Gs[p * LDG + p].x, b = Gs[q * LDG + q].x;
+          Gs[p * LDG + q] = make_double2(0.0, 0.0);
+          Gs[q * LDG + p] = make_double2(0.0, 0.0);
+          Gs[p * LDG + p] = make_double2(a, 0.0);
+          Gs[q * LDG + q] = make_double2(b, 0.0);
+          sweep_rot = 1;
+        }
+        __syncthreads();
+      }
+    }
+    __syncthreads();
+    const int cont = sweep_rot;  // every thread reads before anyone clears it
+    if (sweep == 0 && tid == 0) first_rot = cont;
+    __syncthreads();
+    if (!cont) break;
+  }
+  // An unrotated first sweep means the pair was already orthogonal.
+  if (tid == 0) {
+    d.pairFlag[pairIdx] = first_rot;
+    if (first_rot) atomicOr(&d.sc->rot, 1);
+  }
+  if (first_rot) {
+    double2 *V = d.V + (size_t)pairIdx * (PW * PW);
+    for (int e = tid; e < PW * PW; e += 256) V[e] = Vs[(e / PW) * LDG + e % PW];
+  }
+}
+
+// ---------------------------------------------------------------- apply a pair rotation
+
+constexpr int RR = 64;  // rows per workgroup
+
+__global__ __launch_bounds__(256) void k_rot(const GateDesc *descs, int round) {
+  const GateDesc &d = descs[blockIdx.y];
+  if (!d.sc->active || round >= d.nblk - 1) return;
+  const int npairs = d.nblk / 2;
+  const int xchunks = (d.rows + RR - 1) / RR;
+  const int jchunks = d.trans ? (d.m + RR - 1) / RR : 0;
+  const int per = xchunks + jchunks;
+  const int pairIdx = blockIdx.x / per, chunk = blockIdx.x % per;
+  if (pairIdx >= npairs) return;
+  if (!d.pairFlag[pairIdx]) return;
+  int I, J;
+  rr_pair(round, pairIdx, d.nblk, I, J);
+  double2 *base;
+  int ld, nrows, r0;
+  if (chunk < xchunks) {
+    base = d.X;
+    ld = d.ldx;
+    nrows = d.rows;
+    r0 = chunk * RR;
+  } else {
+    base = d.J;
+    ld = d.ldj;
+    nrows = d.m;
+    r0 = (chunk - xchunks) * RR;
+  }
+  __shared__ double2 Xs[RR * LDG];  // [row][col]
+  __shared__ double2 Vs[PW * LDG];  // [k][col]
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const double2 *V = d.V + (size_t)pairIdx * (PW * PW);
+  for (int e = tid; e < PW * PW; e += 256) Vs[(e / PW) * LDG + e % PW] = V[e];
+  {
+    // column-major source: thread reads consecutive rows of one column
+    for (int e = tid; e < RR * PW; e += 256) {
+      int r = e % RR, c = e / RR;
+      int gr = r0 + r;
+      Xs[r * LDG + c] =
+          gr < nrows ? base[(size_t)pair_col(I, J, c) * ld + gr] : make_double2(0.0, 0.0);
+    }
+  }
+  __syncthreads();
+  double2 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; i++)
+#pragma unroll
+    for (int j = 0; j < 4; j++) acc[i][j] = make_double2(0.0, 0.0);
+#pragma unroll 4
+  for (int k = 0; k < PW; k++) {
+    double2 a[4], b[4];
+#pragma unroll
+    for (int i = 0; i < 4; i++) a[i] = Xs[(ty + 16 * i) * LDG + k];
+#pragma unroll
+    for (int j = 0; j < 4; j++) b[j] = Vs[k * LDG + tx + 16 * j];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+      for (int j = 0; j < 4; j++) cfma(acc[i][j], a[i], b[j]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 4; i++)
+#pragma unroll
+    for (int j = 0; j < 4; j++) Xs[(ty + 16 * i) * LDG + tx + 16 * j] = acc[i][j];
+  __syncthreads();
+  for (int e = tid; e < RR * PW; e += 256) {
+    int r = e % RR, c = e / RR;
+    int gr = r0 + r;
+    if (gr < nrows) base[(size_t)pair_col(I, J, c) * ld + gr] = Xs[r * LDG + c];
+  }
+}
+
+void launch_round(hipStream_t st, const GateDesc *d, int ng, int round, int max_pairs,
+                  int ksplit, int max_rows, int max_m, int npairs_stride) {
+  if (ng <= 0) return;
+  hipLaunchKernelGGL(k_gram, dim3(max_pairs * ksplit, ng), dim3(256), 0, st, d, round, ksplit,
+                     npairs_stride);
+  hipLaunchKernelGGL(k_eig, dim3(max_pairs, ng), dim3(256), 0, st, d, round, ksplit,
+                     npairs_stride);
+  int per = (max_rows + RR - 1) / RR + (max_m + RR - 1) / RR;
+  hipLaunchKernelGGL(k_rot, dim3(max_pairs * per, ng), dim3(256), 0, st, d, round);
+}
+
+// ---------------------------------------------------------------- sort + truncate
+
+constexpr int SORT_MAX = 4096;
+
+__global__ __launch_bounds__(256) void k_trunc(const GateDesc *descs, int *dims_dev) {
+  const GateDesc &d = descs[blockIdx.x];
+  __shared__ double key[SORT_MAX];
+  __shared__ int idx[SORT_MAX];
+  __shared__ double tail[SORT_MAX + 1];
+  __shared__ int s_k;
+  __shared__ double s_N;
+  const int tid = threadIdx.x;
+  int P = 1;
+  while (P < d.cols) P <<= 1;
+  for (int j = tid; j < P; j += 256) {
+    key[j] = j < d.cols ? d.sig2[j] : -1.0;
+    idx[j] = j;
+  }
+  __syncthreads();
+  // bitonic sort: descending key, ascending index on ties
+  for (int size = 2; size <= P; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int j = tid; j < P; j += 256) {
+        int l = j ^ stride;
+        if (l > j) {
+          bool up = ((j & size) == 0);  // this block sorted "descending-first"
+          double kj = key[j], kl = key[l];
+          int ij = idx[j], il = idx[l];
+          bool j_first = (kj > kl) || (kj == kl && ij < il);
+          bool swap = up ? !j_first : j_first;
+          if (swap) {
+            key[j] = kl;
+            key[l] = kj;
+            idx[j] = il;
+            idx[l] = ij;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (tid == 0) {
+    const int cnt = d.cols;
+    double W = 0.0;
+    for (int j = 0; j < cnt; j++) W += key[j];
+    double floor2 = (double)d.m * 0x1p-53 * key[0];
+    int nz = 0;
+    for (int j = 0; j < cnt; j++) nz += key[j] > floor2;
+    if (nz < 1) nz = 1;
+    tail[cnt] = 0.0;
+    for (int k = cnt - 1; k >= 0; k--) tail[k] = tail[k + 1] + key[k];
+    const double cutoff = d.cutoff;
+    int kc = cnt;
+    for (int k = 1; k <= cnt; k++)
+      if (tail[k] <= cutoff * W) {
+        kc = k;
+        break;
+      }
+    int k = kc;
+    if (k > nz) k = nz;
+    if (k > d.chiMax) k = d.chiMax;
+    if (k < 1) k = 1;
+    double head = 0.0;
+    for (int j = 0; j < k; j++) head += key[j];
+    double N = sqrt(head);
+    if (!(N > 0.0)) N = 1.0;
+    d.sc->k = k;
+    d.sc->N = N;
+    d.sc->W = W;
+    d.sc->eps = W > 0.0 ? tail[k] / W : 0.0;
+    d.sc->nz = nz;
+    dims_dev[d.i + 1] = k;
+    s_k = k;
+    s_N = N;
+  }
+  __syncthreads();
+  for (int j = tid; j < s_k; j += 256) {
+    d.lamOut[j] = sqrt(key[j]) / s_N;
+    d.perm[j] = idx[j];
+  }
+}
+
+void launch_trunc(hipStream_t st, const GateDesc *d, int ng, int *dims_dev) {
+  if (ng <= 0) return;
+  hipLaunchKernelGGL(k_trunc, dim3(ng), dim3(256), 0, st, d, dims_dev);
+}
+
+}  // namespace tn

@@ -1,0 +1,153 @@
+// Two-site merge with the gate in the epilogue (float64 arithmetic).
+//
+//   theta[a,s,t,c]  = sum_b A_i[a,s,b] A_{i+1}[b,t,c]       (Sec. IV.A, Fig. 2)
+//   theta'[a,s',t',c] = sum_{s,t} G[2s'+t', 2s+t] theta[a,s,t,c]   (Sec. III.A)
+//   M[(a,s), (t,c)] = theta'[a,s,t,c] * lambda_{i+1}[c]
+//
+// Viewed as a matrix product, rows (a,s) of A_i (m x chiM) times A_{i+1}
+// (chiM x 2chiR).  One output tile holds 64 rows (32 values of a, both s) and
+// the same 32 values of c in both t halves, so the gate mixes entries of the
+// same tile only.  The epilogue writes theta' (row-major, kept for the
+// right-site write-back) and the Jacobi matrix X = M (column-major) or
+// X = M^H when M is wide.
+#include "tnsim_internal.h"
+#include "tn_complex.h"
+
+namespace tn {
+
+constexpr int TM = 64, TC = 32, TK = 16;
+
+template <class S>
+__device__ __forceinline__ void theta_tile(const GateDesc &d, int r0, int c0, double2 *smem) {
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const S *A0 = (const S *)d.A0;
+  const S *A1 = (const S *)d.A1;
+  const int m = d.m, chiM = d.chiM, chiR = d.chiR, n = d.n;
+  double2 *As = smem;            // [TK][TM]
+  double2 *Bs = smem + TK * TM;  // [TK][2*TC]
+  double2 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; i++)
+#pragma unroll
+    for (int j = 0; j < 4; j++) acc[i][j] = make_double2(0.0, 0.0);
+
+  for (int k0 = 0; k0 < chiM; k0 += TK) {
+    {  // A tile: row r, 4 consecutive k
+      int r = tid >> 2, kq = (tid & 3) * 4;
+      int gr = r0 + r;
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        int gk = k0 + kq + j;
+        double2 v = make_double2(0.0, 0.0);
+        if (gr < m && gk < chiM) v = cload(A0 + (size_t)gr * chiM + gk);
+        As[(kq + j) * TM + r] = v;
+      }
+    }
+    {  // B tile: row k, 4 consecutive columns of one t half
+      int kk = tid >> 4, jq = (tid & 15) * 4;
+      int gk = k0 + kk;
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        int jj = jq + j, t = jj >> 5, c = c0 + (jj & 31);
+        double2 v = make_double2(0.0, 0.0);
+        if (gk < chiM && c < chiR) v = cload(A1 + (size_t)gk * n + t * chiR + c);
+        Bs[kk * (2 * TC) + jj] = v;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < TK; kk++) {
+      double2 a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; i++) a[i] = As[kk * TM + ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; j++) b[j] = Bs[kk * (2 * TC) + tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) cfma(acc[i][j], a[i], b[j]);
+    }
+    __syncthreads();
+  }
+
+  // epilogue: tile to LDS, apply the gate, write theta' and X
+  constexpr int LD = 2 * TC + 1;
+  double2 *Cs = smem;  // [TM][LD]
+#pragma unroll
+  for (int i = 0; i < 4; i++)
+#pragma unroll
+    for (int j = 0; j < 4; j++) Cs[(ty + 16 * i) * LD + tx + 16 * j] = acc[i][j];
+  __syncthreads();
+  for (int task = tid; task < (TM / 2) * TC; task += 256) {
+    int al = task / TC, cl = task % TC;
+    double2 v[4];
+#pragma unroll
+    for (int s = 0; s < 2; s++)
+#pragma unroll
+      for (int t = 0; t < 2; t++) v[2 * s + t] = Cs[(2 * al + s) * LD + t * TC + cl];
+#pragma unroll
+    for (int sp = 0; sp < 2; sp++)
+#pragma unroll
+      for (int tp = 0; tp < 2; tp++) {
+        double2 o = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int j = 0; j < 4; j++) cfma(o, d.g[(2 * sp + tp) * 4 + j], v[j]);
+        Cs[(2 * al + sp) * LD + tp * TC + cl] = o;
+      }
+  }
+  __syncthreads();
+  // theta' row-major (m x n), coalesced along c
+  for (int task = tid; task < TM * 2 * TC; task += 256) {
+    int r = task / (2 * TC), jj = task % (2 * TC);
+    int t = jj / TC, c = c0 + jj % TC, gr = r0 + r;
+    if (gr < m && c < chiR) {
+      size_t o = (size_t)gr * n + t * chiR + c;
+      if (d.tfp32)
+        ((float2 *)d.T)[o] = d2f(Cs[r * LD + jj]);
+      else
+        ((double2 *)d.T)[o] = Cs[r * LD + jj];
+    }
+  }
+  if (!d.trans) {
+    // X = M, column-major: coalesced along rows
+    for (int task = tid; task < TM * 2 * TC; task += 256) {
+      int r = task % TM, jj = task / TM;
+      int t = jj / TC, c = c0 + jj % TC, gr = r0 + r;
+      if (gr < m && c < chiR) {
+        double w = d.lamR ? d.lamR[c] : 1.0;
+        d.X[(size_t)(t * chiR + c) * d.ldx + gr] = cscale(Cs[r * LD + jj], w);
+      }
+    }
+  } else {
+    // X = M^H (n x m): column gr holds conj(row gr of M)
+    for (int task = tid; task < TM * 2 * TC; task += 256) {
+      int r = task / (2 * TC), jj = task % (2 * TC);
+      int t = jj / TC, c = c0 + jj % TC, gr = r0 + r;
+      if (gr < m && c < chiR) {
+        double w = d.lamR ? d.lamR[c] : 1.0;
+        d.X[(size_t)gr * d.ldx + t * chiR + c] = cscale(cconj(Cs[r * LD + jj]), w);
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_theta_fp64(const GateDesc *descs) {
+  const GateDesc &d = descs[blockIdx.z];
+  int r0 = blockIdx.x * TM, c0 = blockIdx.y * TC;
+  if (r0 >= d.m || c0 >= d.chiR) return;
+  __shared__ double2 smem[TM * (2 * TC + 1)];
+  if (d.storage == 0)
+    theta_tile<double2>(d, r0, c0, smem);
+  else
+    theta_tile<float2>(d, r0, c0, smem);
+}
+
+void launch_theta(hipStream_t st, const GateDesc *d, int ng, int precision, int max_m,
+                  int max_chiR) {
+  if (ng <= 0) return;
+  (void)precision;
+  dim3 grid((max_m + TM - 1) / TM, (max_chiR + TC - 1) / TC, ng);
+  hipLaunchKernelGGL(k_theta_fp64, grid, dim3(256), 0, st, d);
+}
+
+}  // namespace tn

@@ -1,0 +1,150 @@
+// Write-back of a two-qubit gate (Sec. III.A: left singular vectors to the
+// left/control site, singular values with the right singular vectors to the
+// right/target site):
+//
+//   A_i'[a,s,j]     = u_j[2a+s]                        j < k
+//   A_{i+1}'[j,t,c] = (1/N) sum_{a,s} conj(u_j[2a+s]) theta'[a,s,t,c]
+//
+// u_j is column perm[j] of X divided by its norm (X = M), or column perm[j]
+// of J (X = M^H).  Using theta' rather than M keeps lambda_{i+1} from being
+// divided out.
+#include "tnsim_internal.h"
+#include "tn_complex.h"
+
+namespace tn {
+
+__device__ __forceinline__ double2 left_vec(const GateDesc &d, int r, int col, double inv) {
+  return d.trans ? d.J[(size_t)col * d.ldj + r] : cscale(d.X[(size_t)col * d.ldx + r], inv);
+}
+
+// grid: (m tiles of 64, k tiles of 64, gate)
+template <class S>
+__device__ void wb_left_tile(const GateDesc &d, int k, int r0, int j0, double2 *tile) {
+  const int tid = threadIdx.x;
+  constexpr int LD = 65;
+  for (int e = tid; e < 64 * 64; e += 256) {
+    int r = e % 64, j = e / 64;  // read along r (column-major source)
+    int gr = r0 + r, gj = j0 + j;
+    double2 v = make_double2(0.0, 0.0);
+    if (gr < d.m && gj < k) {
+      int col = d.perm[gj];
+      double inv = d.trans ? 1.0 : 1.0 / sqrt(d.sig2[col]);
+      v = left_vec(d, gr, col, inv);
+    }
+    tile[r * LD + j] = v;
+  }
+  __syncthreads();
+  S *A0 = (S *)d.A0;
+  for (int e = tid; e < 64 * 64; e += 256) {
+    int j = e % 64, r = e / 64;  // write along j (row-major destination)
+    int gr = r0 + r, gj = j0 + j;
+    if (gr < d.m && gj < k) cstore(A0 + (size_t)gr * k + gj, tile[r * LD + j]);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_wb_left(const GateDesc *descs) {
+  const GateDesc &d = descs[blockIdx.z];
+  const int k = d.sc->k;
+  int r0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+  if (r0 >= d.m || j0 >= k) return;
+  __shared__ double2 tile[64 * 65];
+  if (d.storage == 0)
+    wb_left_tile<double2>(d, k, r0, j0, tile);
+  else
+    wb_left_tile<float2>(d, k, r0, j0, tile);
+}
+
+// A_{i+1}' = (1/N) U_k^H theta'   (k x n), tiles of 64 x 64, K = m in steps of 16
+template <class S, class TT>
+__device__ void wb_right_tile(const GateDesc &d, int k, int j0, int c0, double2 *smem) {
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  double2 *As = smem;            // [16][64]  conj(U)[r][j]
+  double2 *Bs = smem + 16 * 64;  // [16][64]  theta'[r][c]
+  const TT *T = (const TT *)d.T;
+  const int m = d.m, n = d.n;
+  double2 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; i++)
+#pragma unroll
+    for (int j = 0; j < 4; j++) acc[i][j] = make_double2(0.0, 0.0);
+  // per-thread loader coordinates
+  const int aj = tid >> 2, ar = (tid & 3) * 4;  // A: column j, 4 consecutive r
+  const int gj = j0 + aj;
+  int colA = 0;
+  double invA = 1.0;
+  if (gj < k) {
+    colA = d.perm[gj];
+    invA = d.trans ? 1.0 : 1.0 / sqrt(d.sig2[colA]);
+  }
+  const int br = tid >> 4, bc = (tid & 15) * 4;  // B: row r, 4 consecutive c
+  for (int r0 = 0; r0 < m; r0 += 16) {
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      int gr = r0 + ar + q;
+      double2 v = make_double2(0.0, 0.0);
+      if (gj < k && gr < m) v = cconj(left_vec(d, gr, colA, invA));
+      As[(ar + q) * 64 + aj] = v;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      int gr = r0 + br, gc = c0 + bc + q;
+      double2 v = make_double2(0.0, 0.0);
+      if (gr < m && gc < n) v = cload(T + (size_t)gr * n + gc);
+      Bs[br * 64 + bc + q] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; kk++) {
+      double2 a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; i++) a[i] = As[kk * 64 + ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; j++) b[j] = Bs[kk * 64 + tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) cfma(acc[i][j], a[i], b[j]);
+    }
+    __syncthreads();
+  }
+  const double invN = 1.0 / d.sc->N;
+  S *A1 = (S *)d.A1;
+#pragma unroll
+  for (int i = 0; i < 4; i++)
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      int gjo = j0 + ty + 16 * i, gc = c0 + tx + 16 * j;
+      if (gjo < k && gc < n) cstore(A1 + (size_t)gjo * n + gc, cscale(acc[i][j], invN));
+    }
+}
+
+__global__ __launch_bounds__(256) void k_wb_right(const GateDesc *descs) {
+  const GateDesc &d = descs[blockIdx.z];
+  const int k = d.sc->k;
+  int j0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
+  if (j0 >= k || c0 >= d.n) return;
+  __shared__ double2 smem[2 * 16 * 64];
+  if (d.storage == 0) {
+    if (d.tfp32)
+      wb_right_tile<double2, float2>(d, k, j0, c0, smem);
+    else
+      wb_right_tile<double2, double2>(d, k, j0, c0, smem);
+  } else {
+    if (d.tfp32)
+      wb_right_tile<float2, float2>(d, k, j0, c0, smem);
+    else
+      wb_right_tile<float2, double2>(d, k, j0, c0, smem);
+  }
+}
+
+void launch_writeback(hipStream_t st, const GateDesc *d, int ng, int precision, int max_m,
+                      int max_k, int max_n) {
+  if (ng <= 0) return;
+  (void)precision;
+  hipLaunchKernelGGL(k_wb_left, dim3((max_m + 63) / 64, (max_k + 63) / 64, ng), dim3(256), 0, st,
+                     d);
+  hipLaunchKernelGGL(k_wb_right, dim3((max_k + 63) / 64, (max_n + 63) / 64, ng), dim3(256), 0,
+                     st, d);
+}
+
+}  // namespace tn

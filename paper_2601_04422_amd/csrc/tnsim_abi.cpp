@@ -1,0 +1,812 @@
+// Host side of the tnsim C ABI: argument validation, arena carving, gate
+// descriptors, the Jacobi sweep loop and the readout drivers.  All arithmetic
+// on the state runs in the HIP kernels of this library.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/tnsim.h"
+#include "tnsim_internal.h"
+
+using namespace tn;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+inline size_t align_up(size_t x, size_t a = ALIGN) { return (x + a - 1) / a * a; }
+inline int pad_to(int x, int a) { return (x + a - 1) / a * a; }
+
+struct Layout {
+  int n = 0, chi_max = 0, storage = 0, nslots = 0;
+  size_t elem = 16;                 // site element bytes
+  std::vector<int> bondcap;         // n-1
+  std::vector<int> dimcap;          // n+1
+  std::vector<size_t> site_off, site_cap, lam_off;
+  size_t dims_off = 0, site_tab_off = 0, lam_tab_off = 0;
+  int cmax = 0, ldx_max = 0, cols_pad_max = 0, npairs_max = 0, gp_blocks = 0;
+  size_t slot_bytes = 0, slot0_off = 0;
+  size_t x_off = 0, j_off = 0, t_off = 0, v_off = 0, pf_off = 0, sig_off = 0, perm_off = 0,
+         sc_off = 0;  // within a slot
+  size_t gp_off = 0;  // pooled pair-Gram partials
+  size_t desc_off = 0, d1_off = 0;
+  size_t e0_off = 0, e1_off = 0, f_off = 0, f2_off = 0, va_off = 0, vb_off = 0;
+  size_t total = 0;
+};
+
+bool valid_config(const tnsim_config *c) {
+  if (!c) return false;
+  if (c->n_qubits < 2 || c->n_qubits > 100000) return false;
+  if (c->chi_max < 1 || c->chi_max > 2048) return false;
+  if (!(c->cutoff >= 0.0)) return false;
+  if (c->precision < 0 || c->precision > 3) return false;
+  if (c->storage < 0 || c->storage > 1) return false;
+  return true;
+}
+
+Layout make_layout(const tnsim_config &c) {
+  Layout L;
+  L.n = c.n_qubits;
+  L.chi_max = c.chi_max;
+  L.storage = c.storage;
+  L.elem = c.storage == 0 ? 16 : 8;
+  L.nslots = c.max_layer_gates > 0 ? std::min(c.max_layer_gates, std::max(1, L.n / 2))
+                                   : std::max(1, L.n / 2);
+  const int n = L.n;
+  L.bondcap.resize(n - 1);
+  int maxbond = 1;
+  for (int b = 0; b < n - 1; b++) {
+    int e = std::min(b + 1, n - 1 - b);
+    long long cap = e >= 30 ? (1LL << 30) : (1LL << e);
+    L.bondcap[b] = (int)std::min<long long>(cap, c.chi_max);
+    maxbond = std::max(maxbond, L.bondcap[b]);
+  }
+  L.dimcap.assign(n + 1, 1);
+  for (int q = 1; q < n; q++) L.dimcap[q] = L.bondcap[q - 1];
+  size_t off = 0;
+  L.dims_off = off;
+  off = align_up(off + sizeof(int32_t) * (n + 1));
+  L.site_tab_off = off;
+  off = align_up(off + sizeof(void *) * n);
+  L.lam_tab_off = off;
+  off = align_up(off + sizeof(void *) * (n - 1));
+  L.site_off.resize(n);
+  L.site_cap.resize(n);
+  for (int q = 0; q < n; q++) {
+    L.site_cap[q] = (size_t)L.dimcap[q] * 2 * L.dimcap[q + 1];
+    L.site_off[q] = off;
+    off = align_up(off + L.site_cap[q] * L.elem);
+  }
+  L.lam_off.resize(n - 1);
+  for (int b = 0; b < n - 1; b++) {
+    L.lam_off[b] = off;
+    off = align_up(off + sizeof(double) * L.bondcap[b]);
+  }
+  // two-site workspaces
+  L.cmax = 2 * maxbond;
+  L.ldx_max = pad_to(L.cmax, 4);
+  L.cols_pad_max = pad_to(L.cmax, PW);
+  L.npairs_max = L.cols_pad_max / PW;
+  size_t s = 0;
+  L.x_off = s;
+  s = align_up(s + sizeof(double2) * (size_t)L.ldx_max * L.cols_pad_max);
+  L.j_off = s;
+  s = align_up(s + sizeof(double2) * (size_t)L.ldx_max * L.cols_pad_max);
+  L.t_off = s;
+  s = align_up(s + sizeof(double2) * (size_t)L.cmax * L.cmax);
+  L.v_off = s;
+  s = align_up(s + sizeof(double2) * (size_t)L.npairs_max * PW * PW);
+  L.pf_off = s;
+  s = align_up(s + sizeof(int) * L.npairs_max);
+  L.sig_off = s;
+  s = align_up(s + sizeof(double) * L.cols_pad_max);
+  L.perm_off = s;
+  s = align_up(s + sizeof(int) * L.cols_pad_max);
+  L.sc_off = s;
+  s = align_up(s + sizeof(SlotScalars));
+  L.slot_bytes = s;
+  L.slot0_off = off;
+  off = align_up(off + L.slot_bytes * L.nslots);
+  L.gp_blocks = std::max(L.nslots, KSPLIT_MAX) * L.npairs_max;
+  L.gp_off = off;
+  off = align_up(off + sizeof(double2) * (size_t)L.gp_blocks * PW * PW);
+  L.desc_off = off;
+  off = align_up(off + sizeof(GateDesc) * L.nslots);
+  L.d1_off = off;
+  off = align_up(off + sizeof(Gate1Desc) * n);
+  const size_t ee = sizeof(double2) * (size_t)maxbond * maxbond;
+  const size_t ff = sizeof(double2) * (size_t)maxbond * 2 * maxbond;
+  L.e0_off = off;
+  off = align_up(off + ee);
+  L.e1_off = off;
+  off = align_up(off + ee);
+  L.f_off = off;
+  off = align_up(off + ff);
+  L.f2_off = off;
+  off = align_up(off + ff);
+  L.va_off = off;
+  off = align_up(off + sizeof(double2) * maxbond);
+  L.vb_off = off;
+  off = align_up(off + sizeof(double2) * maxbond);
+  L.total = off;
+  return L;
+}
+
+// Gate with orientation fixed to (i, i+1)
+struct Pending {
+  int i;
+  double2 g[16];
+};
+
+}  // namespace
+
+struct tnsim_mps_s {
+  tnsim_config cfg;
+  Layout L;
+  char *arena = nullptr;
+  size_t arena_bytes = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::vector<int> dims;  // host copy, n+1
+  double sum_eps = 0.0, prod_keep = 1.0;
+  int64_t n2q = 0;
+  int last_sweeps = 0;
+  bool poisoned = false;
+  std::string err;
+  char *pin = nullptr;
+  size_t pin_bytes = 0;
+
+  template <class T>
+  T *at(size_t off) const {
+    return reinterpret_cast<T *>(arena + off);
+  }
+  void *site(int q) const { return arena + L.site_off[q]; }
+  double *lam(int b) const { return at<double>(L.lam_off[b]); }
+  char *slot(int s) const { return arena + L.slot0_off + L.slot_bytes * (size_t)s; }
+  int32_t *dims_dev() const { return at<int32_t>(L.dims_off); }
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+
+tnsim_status fail(tnsim_mps h, hipError_t e, const char *where) {
+  if (!h->poisoned) {
+    h->poisoned = true;
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s: %s", where, hipGetErrorString(e));
+    h->err = buf;
+  }
+  return TNSIM_E_DEVICE;
+}
+
+#define HIPCHK(h, call)                                   \
+  do {                                                    \
+    hipError_t e_ = (call);                               \
+    if (e_ != hipSuccess) return fail((h), e_, #call);   \
+  } while (0)
+
+#define LAUNCHCHK(h, what)                                \
+  do {                                                    \
+    hipError_t e_ = hipGetLastError();                    \
+    if (e_ != hipSuccess) return fail((h), e_, what);     \
+  } while (0)
+
+inline double2 to_d2(const tnsim_c128 &c) { return make_double2(c.re, c.im); }
+
+tnsim_status check_handle(tnsim_mps h) {
+  if (!h) return TNSIM_E_ARG;
+  if (h->poisoned) return TNSIM_E_DEVICE;
+  return TNSIM_OK;
+}
+
+tnsim_status init_state(tnsim_mps h) {
+  const int n = h->L.n;
+  launch_init_state(h->stream, h->at<void *const>(h->L.site_tab_off), n, h->L.storage,
+                    h->at<double *const>(h->L.lam_tab_off), n - 1);
+  LAUNCHCHK(h, "init_state");
+  std::vector<int32_t> ones(n + 1, 1);
+  h->dims.assign(n + 1, 1);
+  HIPCHK(h, hipMemcpyAsync(h->dims_dev(), ones.data(), sizeof(int32_t) * (n + 1),
+                           hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  h->sum_eps = 0.0;
+  h->prod_keep = 1.0;
+  h->n2q = 0;
+  h->last_sweeps = 0;
+  return TNSIM_OK;
+}
+
+// Run one batch of two-qubit gates (at most nslots) through the whole path.
+tnsim_status run_2q_batch(tnsim_mps h, const Pending *gates, int ng) {
+  const Layout &L = h->L;
+  const tnsim_config &c = h->cfg;
+  std::vector<GateDesc> D(ng);
+  int maxM = 0, maxN = 0, maxRows = 0, maxColsPad = 0, maxPairs = 0, maxChiR = 0, maxNblk = 0;
+  int maxMtrans = 0;
+  for (int g = 0; g < ng; g++) {
+    GateDesc &d = D[g];
+    memset(&d, 0, sizeof d);
+    const int i = gates[g].i;
+    d.i = i;
+    d.chiL = h->dims[i];
+    d.chiM = h->dims[i + 1];
+    d.chiR = h->dims[i + 2];
+    d.m = 2 * d.chiL;
+    d.n = 2 * d.chiR;
+    d.trans = d.n > d.m;
+    d.rows = std::max(d.m, d.n);
+    d.cols = std::min(d.m, d.n);
+    d.ldx = pad_to(d.rows, 4);
+    d.ldj = pad_to(d.m, 4);
+    d.colsPad = pad_to(d.cols, PW);
+    d.nblk = d.colsPad / BW;
+    d.chiMax = c.chi_max;
+    d.storage = c.storage;
+    d.tfp32 = c.precision != TNSIM_FP64;
+    d.tol = c.jacobi_tol > 0 ? c.jacobi_tol : std::max(d.rows, 16) * 0x1p-53;
+    d.cutoff = c.cutoff;
+    d.A0 = h->site(i);
+    d.A1 = h->site(i + 1);
+    d.lamR = (i + 1 <= L.n - 2) ? h->lam(i + 1) : nullptr;
+    d.lamOut = h->lam(i);
+    char *sl = h->slot(g);
+    d.X = (double2 *)(sl + L.x_off);
+    d.J = (double2 *)(sl + L.j_off);
+    d.T = sl + L.t_off;
+    d.V = (double2 *)(sl + L.v_off);
+    d.pairFlag = (int *)(sl + L.pf_off);
+    d.sig2 = (double *)(sl + L.sig_off);
+    d.perm = (int *)(sl + L.perm_off);
+    d.sc = (SlotScalars *)(sl + L.sc_off);
+    for (int e = 0; e < 16; e++) d.g[e] = gates[g].g[e];
+    maxM = std::max(maxM, d.m);
+    maxN = std::max(maxN, d.n);
+    maxRows = std::max(maxRows, d.rows);
+    maxColsPad = std::max(maxColsPad, d.colsPad);
+    maxPairs = std::max(maxPairs, d.nblk / 2);
+    maxNblk = std::max(maxNblk, d.nblk);
+    maxChiR = std::max(maxChiR, d.chiR);
+    if (d.trans) maxMtrans = std::max(maxMtrans, d.m);
+  }
+  // Split the row dimension of the pair Grams when the batch alone cannot
+  // fill the GPU.
+  int ksplit = (1024 + ng * maxPairs - 1) / (ng * maxPairs);
+  ksplit = std::min(ksplit, KSPLIT_MAX);
+  ksplit = std::min(ksplit, std::max(1, L.gp_blocks / (ng * L.npairs_max)));
+  ksplit = std::min(ksplit, std::max(1, (maxRows + 31) / 32));
+  ksplit = std::max(ksplit, 1);
+  double2 *gp = h->at<double2>(L.gp_off);
+  for (int g = 0; g < ng; g++) D[g].Gp = gp + (size_t)g * ksplit * L.npairs_max * PW * PW;
+
+  GateDesc *ddev = h->at<GateDesc>(L.desc_off);
+  HIPCHK(h, hipStreamSynchronize(h->stream));  // the staging buffer is free
+  memcpy(h->pin, D.data(), sizeof(GateDesc) * ng);
+  HIPCHK(h, hipMemcpyAsync(ddev, h->pin, sizeof(GateDesc) * ng, hipMemcpyHostToDevice,
+                           h->stream));
+  hipStream_t st = h->stream;
+  launch_setup_slots(st, ddev, ng, maxColsPad, 0);
+  launch_theta(st, ddev, ng, c.precision, maxM, maxChiR);
+  launch_colnorm(st, ddev, ng, maxColsPad);
+  launch_gate_init(st, ddev, ng);
+  LAUNCHCHK(h, "theta");
+
+  const int max_sweeps = c.jacobi_max_sweeps > 0 ? c.jacobi_max_sweeps : 60;
+  SlotScalars *sc_pin = reinterpret_cast<SlotScalars *>(h->pin + align_up(sizeof(GateDesc) * L.nslots));
+  bool converged = false;
+  int sweeps = 0;
+  for (int sweep = 1; sweep <= max_sweeps; sweep++) {
+    launch_begin_sweep(st, ddev, ng);
+    for (int r = 0; r < maxNblk - 1; r++)
+      launch_round(st, ddev, ng, r, maxPairs, ksplit, maxRows, maxMtrans, L.npairs_max);
+    LAUNCHCHK(h, "jacobi round");
+    for (int g = 0; g < ng; g++)
+      HIPCHK(h, hipMemcpyAsync(&sc_pin[g], D[g].sc, sizeof(SlotScalars), hipMemcpyDeviceToHost, st));
+    HIPCHK(h, hipStreamSynchronize(st));
+    sweeps = sweep;
+    bool any = false;
+    for (int g = 0; g < ng; g++) any |= sc_pin[g].rot != 0;
+    if (!any) {
+      converged = true;
+      break;
+    }
+  }
+  h->last_sweeps = std::max(h->last_sweeps, sweeps);
+  if (!converged) {
+    h->err = "Jacobi SVD did not converge within jacobi_max_sweeps";
+    return TNSIM_E_NOCONV;
+  }
+  launch_colnorm(st, ddev, ng, maxColsPad);
+  launch_trunc(st, ddev, ng, h->dims_dev());
+  LAUNCHCHK(h, "truncate");
+  for (int g = 0; g < ng; g++)
+    HIPCHK(h, hipMemcpyAsync(&sc_pin[g], D[g].sc, sizeof(SlotScalars), hipMemcpyDeviceToHost, st));
+  HIPCHK(h, hipStreamSynchronize(st));
+  int maxK = 0;
+  for (int g = 0; g < ng; g++) {
+    const SlotScalars &s = sc_pin[g];
+    h->dims[D[g].i + 1] = s.k;
+    h->sum_eps += s.eps;
+    h->prod_keep *= (1.0 - s.eps);
+    h->n2q += 1;
+    maxK = std::max(maxK, s.k);
+  }
+  launch_writeback(st, ddev, ng, c.precision, maxM, maxK, maxN);
+  LAUNCHCHK(h, "write-back");
+  return TNSIM_OK;
+}
+
+tnsim_status run_2q(tnsim_mps h, const std::vector<Pending> &gs) {
+  const int ns = h->L.nslots;
+  for (size_t b = 0; b < gs.size(); b += ns) {
+    int ng = (int)std::min<size_t>(ns, gs.size() - b);
+    tnsim_status s = run_2q_batch(h, gs.data() + b, ng);
+    if (s != TNSIM_OK) return s;
+  }
+  return TNSIM_OK;
+}
+
+tnsim_status run_1q(tnsim_mps h, const std::vector<std::pair<int, const tnsim_c128 *>> &gs) {
+  if (gs.empty()) return TNSIM_OK;
+  std::vector<Gate1Desc> D(gs.size());
+  int maxe = 0;
+  for (size_t k = 0; k < gs.size(); k++) {
+    Gate1Desc &d = D[k];
+    memset(&d, 0, sizeof d);
+    int q = gs[k].first;
+    d.A = h->site(q);
+    d.chiL = h->dims[q];
+    d.chiR = h->dims[q + 1];
+    d.storage = h->L.storage;
+    for (int e = 0; e < 4; e++) d.u[e] = to_d2(gs[k].second[e]);
+    maxe = std::max(maxe, d.chiL * d.chiR);
+  }
+  Gate1Desc *ddev = h->at<Gate1Desc>(h->L.d1_off);
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  memcpy(h->pin, D.data(), sizeof(Gate1Desc) * D.size());
+  HIPCHK(h, hipMemcpyAsync(ddev, h->pin, sizeof(Gate1Desc) * D.size(), hipMemcpyHostToDevice,
+                           h->stream));
+  launch_apply_1q(h->stream, ddev, (int)D.size(), maxe);
+  LAUNCHCHK(h, "apply_1q");
+  return TNSIM_OK;
+}
+
+void orient(int q0, int q1, const tnsim_c128 *g, Pending &p) {
+  if (q1 == q0 + 1) {
+    p.i = q0;
+    for (int e = 0; e < 16; e++) p.g[e] = to_d2(g[e]);
+  } else {
+    // SWAP G SWAP: G'[2s'+t', 2s+t] = G[2t'+s', 2t+s]
+    p.i = q1;
+    for (int sp = 0; sp < 2; sp++)
+      for (int tp = 0; tp < 2; tp++)
+        for (int s = 0; s < 2; s++)
+          for (int t = 0; t < 2; t++)
+            p.g[(2 * sp + tp) * 4 + 2 * s + t] = to_d2(g[(2 * tp + sp) * 4 + 2 * t + s]);
+  }
+}
+
+// Validate a layer; fills 1q and 2q lists.
+tnsim_status validate_layer(tnsim_mps h, const tnsim_gate *gates, int ng,
+                            std::vector<std::pair<int, const tnsim_c128 *>> &g1,
+                            std::vector<Pending> &g2) {
+  const int n = h->L.n;
+  if (ng < 0 || (ng > 0 && !gates)) return TNSIM_E_ARG;
+  std::vector<char> used(n, 0);
+  for (int k = 0; k < ng; k++) {
+    int a = gates[k].q0, b = gates[k].q1;
+    if (a < 0 || a >= n || b < -1 || b >= n || a == b) return TNSIM_E_ARG;
+    if (b >= 0 && std::abs(a - b) != 1) return TNSIM_E_NONLOCAL;
+    if (used[a] || (b >= 0 && used[b])) return TNSIM_E_OVERLAP;
+    used[a] = 1;
+    if (b >= 0) used[b] = 1;
+  }
+  for (int k = 0; k < ng; k++) {
+    if (gates[k].q1 < 0) {
+      g1.push_back({gates[k].q0, gates[k].m});
+    } else {
+      Pending p;
+      orient(gates[k].q0, gates[k].q1, gates[k].m, p);
+      g2.push_back(p);
+    }
+  }
+  return TNSIM_OK;
+}
+
+// <bra| P |ket>; P holds a 2x2 per site (4n entries) and isI marks identity
+// sites; P == nullptr means identity everywhere.
+tnsim_status transfer(tnsim_mps h, tnsim_mps bra, tnsim_mps ket, const double2 *P,
+                      const char *isI, double2 *out) {
+  const Layout &L = h->L;
+  hipStream_t st = h->stream;
+  double2 *E = h->at<double2>(L.e0_off), *E2 = h->at<double2>(L.e1_off);
+  double2 *F = h->at<double2>(L.f_off), *F2 = h->at<double2>(L.f2_off);
+  double2 one = make_double2(1.0, 0.0);
+  HIPCHK(h, hipStreamSynchronize(st));
+  memcpy(h->pin, &one, sizeof one);
+  HIPCHK(h, hipMemcpyAsync(E, h->pin, sizeof one, hipMemcpyHostToDevice, st));
+  const int n = L.n;
+  for (int q = 0; q < n; q++) {
+    int lb = bra->dims[q], rb = bra->dims[q + 1];
+    int lk = ket->dims[q], rk = ket->dims[q + 1];
+    // F = E (lb x lk) * K (lk x 2rk)
+    launch_gemm_nn(st, lb, 2 * rk, lk, E, lk, ket->site(q), 2 * rk, ket->L.storage, F, 2 * rk);
+    const double2 *Fp = F;
+    if (P && !isI[q]) {
+      launch_pauli_phys(st, F, F2, lb, rk, P[4 * q], P[4 * q + 1], P[4 * q + 2], P[4 * q + 3]);
+      Fp = F2;
+    }
+    // E' = B^H (rb x 2lb) * F (2lb x rk)
+    launch_gemm_cn(st, rb, rk, 2 * lb, bra->site(q), rb, bra->L.storage, Fp, rk, E2, rk);
+    LAUNCHCHK(h, "transfer");
+    std::swap(E, E2);
+  }
+  HIPCHK(h, hipMemcpyAsync(h->pin, E, sizeof(double2), hipMemcpyDeviceToHost, st));
+  HIPCHK(h, hipStreamSynchronize(st));
+  memcpy(out, h->pin, sizeof(double2));
+  return TNSIM_OK;
+}
+
+}  // namespace
+
+// ============================================================== C ABI
+
+extern "C" {
+
+size_t tnsim_mps_arena_bytes(const tnsim_config *cfg) {
+  if (!valid_config(cfg)) return 0;
+  return make_layout(*cfg).total;
+}
+
+tnsim_status tnsim_mps_create(const tnsim_config *cfg, void *dev_arena, size_t arena_bytes,
+                              void *hip_stream, tnsim_mps *out) {
+  if (!out) return TNSIM_E_ARG;
+  *out = nullptr;
+  if (!valid_config(cfg) || !dev_arena) return TNSIM_E_ARG;
+  Layout L = make_layout(*cfg);
+  if (arena_bytes < L.total) return TNSIM_E_CAPACITY;
+  if (reinterpret_cast<uintptr_t>(dev_arena) % ALIGN) return TNSIM_E_ARG;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    g_create_error = "no HIP device";
+    return TNSIM_E_DEVICE;
+  }
+  tnsim_mps h = new tnsim_mps_s();
+  h->cfg = *cfg;
+  h->L = std::move(L);
+  h->arena = (char *)dev_arena;
+  h->arena_bytes = arena_bytes;
+  h->stream = (hipStream_t)hip_stream;
+  h->device = dev;
+  const Layout &LL = h->L;
+  h->pin_bytes = align_up(sizeof(GateDesc) * LL.nslots) + align_up(sizeof(SlotScalars) * LL.nslots) +
+                 align_up(sizeof(Gate1Desc) * LL.n) + 4096;
+  if (hipHostMalloc((void **)&h->pin, h->pin_bytes, hipHostMallocDefault) != hipSuccess) {
+    delete h;
+    return TNSIM_E_DEVICE;
+  }
+  // device tables of site / lambda pointers for the init kernel
+  std::vector<void *> sp(LL.n), lp(std::max(LL.n - 1, 1));
+  for (int q = 0; q < LL.n; q++) sp[q] = h->site(q);
+  for (int b = 0; b < LL.n - 1; b++) lp[b] = h->lam(b);
+  tnsim_status st = TNSIM_OK;
+  if (hipMemcpy(h->arena + LL.site_tab_off, sp.data(), sizeof(void *) * LL.n,
+                hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(h->arena + LL.lam_tab_off, lp.data(), sizeof(void *) * (LL.n - 1),
+                hipMemcpyHostToDevice) != hipSuccess)
+    st = TNSIM_E_DEVICE;
+  if (st == TNSIM_OK) st = init_state(h);
+  if (st != TNSIM_OK) {
+    hipHostFree(h->pin);
+    delete h;
+    return st;
+  }
+  *out = h;
+  return TNSIM_OK;
+}
+
+tnsim_status tnsim_mps_destroy(tnsim_mps h) {
+  if (!h) return TNSIM_E_ARG;
+  if (!h->poisoned) hipStreamSynchronize(h->stream);
+  if (h->pin) hipHostFree(h->pin);
+  delete h;
+  return TNSIM_OK;
+}
+
+tnsim_status tnsim_mps_reset(tnsim_mps h) {
+  tnsim_status s = check_handle(h);
+  if (s != TNSIM_OK) return s;
+  return init_state(h);
+}
+
+tnsim_status tnsim_apply_1q(tnsim_mps h, int32_t q, const tnsim_c128 u[4]) {
+  tnsim_status s = check_handle(h);
+  if (s != TNSIM_OK) return s;
+  if (!u || q < 0 || q >= h->L.n) return TNSIM_E_ARG;
+  return run_1q(h, {{q, u}});
+}
+
+tnsim_status tnsim_apply_2q(tnsim_mps h, int32_t q0, int32_t q1, const tnsim_c128 g[16]) {
+  tnsim_status s = check_handle(h);
+  if (s != TNSIM_OK) return s;
+  if (!g || q0 < 0 || q1 < 0 || q0 >= h->L.n || q1 >= h->L.n || q0 == q1) return TNSIM_E_ARG;
+  if (std::abs(q0 - q1) != 1) return TNSIM_E_NONLOCAL;
+  Pending p;
+  orient(q0, q1, g, p);
+  h->last_sweeps = 0;
+  return run_2q_batch(h, &p, 1);
+}
+
+tnsim_status tnsim_apply_layer(tnsim_mps h, const tnsim_gate *gates, int32_t n_gates) {
+  tnsim_status s = check_handle(h);
+  if (s != TNSIM_OK) return s;
+  std::vector<std::pair<int, const tnsim_c128 *>> g1;
+  std::vector<Pending> g2;
+  s = validate_layer(h, gates, n_gates, g1, g2);
+  if (s != TNSIM_OK) return s;
+  h->last_sweeps = 0;
+  s = run_1q(h, g1);
+  if (s != TNSIM_OK) return s;
+  return run_2q(h, g2);
+}
+
+tnsim_status tnsim_apply_layer_multi(tnsim_mps const *mps, const tnsim_gate *const *gates,
+                                     const int32_t *n_gates, int32_t n_mps) {
+  if (!mps || !gates || !n_gates || n_mps < 0) return TNSIM_E_ARG;
+  for (int k = 0; k < n_mps; k++) {
+    tnsim_status s = tnsim_apply_layer(mps[k], gates[k], n_gates[k]);
+    if (s != TNSIM_OK) return s;
+  }
+  return TNSIM_OK;
+}
+
+tnsim_status tnsim_layerise(const tnsim_gate *gates, int32_t n_gates, int32_t n_qubits,
+                            int32_t *layer_of_gate, int32_t *n_layers) {
+  if (n_gates < 0 || n_qubits < 1 || (n_gates > 0 && (!gates || !layer_of_gate)) || !n_layers)
+    return TNSIM_E_ARG;
+  std::vector<int> next(n_qubits, 0);
+  int nl = 0;
+  for (int k = 0; k < n_gates; k++) {
+    int a = gates[k].q0, b = gates[k].q1;
+    if (a < 0 || a >= n_qubits || b < -1 || b >= n_qubits || a == b) return TNSIM_E_ARG;
+    int l = next[a];
+    if (b >= 0) l = std::max(l, next[b]);
+    layer_of_gate[k] = l;
+    next[a] = l + 1;
+    if (b >= 0) next[b] = l + 1;
+    nl = std::max(nl, l + 1);
+  }
+  *n_layers = nl;
+  return TNSIM_OK;
+}
+
+tnsim_status tnsim_expect_pauli(tnsim_mps h, const char *pauli, double *re_out, double *im_out) {
+  tnsim_status s = check_handle(h);
+  if (s != TNSIM_OK) return s;
+  if (!pauli || !re_out) return TNSIM_E_ARG;
+  const int n = h->L.n;
+  static const double2 PM[4][4] = {
+      {{1, 0}, {0, 0}, {0, 0}, {1, 0}},
+      {{0, 0}, {1, 0}, {1, 0}, {0, 0}},
+      {{0, 0}, {0, -1}, {0, 1}, {0, 0}},
+      {{1, 0}, {0, 0}, {0, 0}, {-1, 0}}};
+  std::vector<double2> tab(4 * n);
+  std::vector<char> isI(n);
+  for (int q = 0; q < n; q++) {
+    int k;
+    switch (pauli[q]) {
+      case 'I': k = 0; break;
+      case 'X': k = 1; break;
+      case 'Y': k = 2; break;
+      case 'Z': k = 3; break;
+      default: return TNSIM_E_ARG;
+    }
+    isI[q] = k == 0;
+    for (int e = 0; e < 4; e++) tab[4 * q + e] = PM[k][e];
+  }
+  double2 num, den;
+  s = transfer(h, h, h, tab.data(), isI.data(), &num);
+  if (s != TNSIM_OK) return s;
+  s = transfer(h, h, h, nullptr, nullptr, &den);
+  if (s != TNSIM_OK) return s;
+  // num / den
+  double dd = den.x * den.x + den.y * den.y;
+  *re_out = (num.x * den.x + num.y * den.y) / dd;
+  if (im_out) *im_out = (num.y * den.x - num.x * den.y) / dd;
+  return TNSIM_OK;
+}
+
+tnsim_status tnsim_overlap(tnsim_mps a, tnsim_mps b, tnsim_c128 *out) {
+  tnsim_status s = check_handle(a);
+  if (s != TNSIM_OK) return s;
+  s = check_handle(b);
+  if (s != TNSIM_OK) return s;
+  if (!out || a->L.n != b->L.n) return TNSIM_E_ARG;
+  if (a->stream != b->stream) HIPCHK(b, hipStreamSynchronize(b->stream));
+  double2 v;
+  // buffers of a are sized by a's chi_max; both operands must fit them
+  for (int q = 0; q <= a->L.n; q++)
+    if (b->dims[q] > a->L.dimcap[q]) return TNSIM_E_CAPACITY;
+  s = transfer(a, a, b, nullptr, nullptr, &v);
+  if (s != TNSIM_OK) return s;
+  out->re = v.x;
+  out->im = v.y;
+  return TNSIM_OK;
+}
+
+tnsim_status tnsim_amplitude(tnsim_mps h, const uint8_t *bits, tnsim_c128 *out) {
+  tnsim_status s = check_handle(h);
+  if (s != TNSIM_OK) return s;
+  if (!bits || !out) return TNSIM_E_ARG;
+  const int n = h->L.n;
+  for (int q = 0; q < n; q++)
+    if (bits[q] > 1) return TNSIM_E_ARG;
+  hipStream_t st = h->stream;
+  double2 *v = h->at<double2>(h->L.va_off), *w = h->at<double2>(h->L.vb_off);
+  double2 one = make_double2(1.0, 0.0);
+  HIPCHK(h, hipStreamSynchronize(st));
+  memcpy(h->pin, &one, sizeof one);
+  HIPCHK(h, hipMemcpyAsync(v, h->pin, sizeof one, hipMemcpyHostToDevice, st));
+  for (int q = 0; q < n; q++) {
+    launch_amp_step(st, v, w, h->site(q), h->L.storage, h->dims[q], h->dims[q + 1], bits[q]);
+    LAUNCHCHK(h, "amplitude");
+    std::swap(v, w);
+  }
+  HIPCHK(h, hipMemcpyAsync(h->pin, v, sizeof(double2), hipMemcpyDeviceToHost, st));
+  HIPCHK(h, hipStreamSynchronize(st));
+  double2 r;
+  memcpy(&r, h->pin, sizeof r);
+  out->re = r.x;
+  out->im = r.y;
+  return TNSIM_OK;
+}
+
+tnsim_status tnsim_mps_copy(tnsim_mps dst, tnsim_mps src) {
+  tnsim_status s = check_handle(dst);
+  if (s != TNSIM_OK) return s;
+  s = check_handle(src);
+  if (s != TNSIM_OK) return s;
+  if (dst->L.n != src->L.n) return TNSIM_E_ARG;
+  const int n = dst->L.n;
+  for (int q = 1; q < n; q++)
+    if (src->dims[q] > dst->L.dimcap[q]) return TNSIM_E_CAPACITY;
+  HIPCHK(src, hipStreamSynchronize(src->stream));
+  for (int q = 0; q < n; q++) {
+    size_t cnt = (size_t)src->dims[q] * 2 * src->dims[q + 1];
+    launch_convert(dst->stream, src->site(q), src->L.storage, dst->site(q), dst->L.storage, cnt);
+  }
+  LAUNCHCHK(dst, "copy");
+  for (int b = 0; b < n - 1; b++)
+    HIPCHK(dst, hipMemcpyAsync(dst->lam(b), src->lam(b), sizeof(double) * src->dims[b + 1],
+                               hipMemcpyDeviceToDevice, dst->stream));
+  dst->dims = src->dims;
+  HIPCHK(dst, hipStreamSynchronize(dst->stream));
+  memcpy(dst->pin, src->dims.data(), sizeof(int32_t) * (n + 1));
+  HIPCHK(dst, hipMemcpyAsync(dst->dims_dev(), dst->pin, sizeof(int32_t) * (n + 1),
+                             hipMemcpyHostToDevice, dst->stream));
+  HIPCHK(dst, hipStreamSynchronize(dst->stream));
+  dst->sum_eps = src->sum_eps;
+  dst->prod_keep = src->prod_keep;
+  dst->n2q = src->n2q;
+  return TNSIM_OK;
+}
+
+tnsim_status tnsim_bond_dims(tnsim_mps h, int32_t *out) {
+  tnsim_status s = check_handle(h);
+  if (s != TNSIM_OK) return s;
+  if (!out) return TNSIM_E_ARG;
+  for (int b = 0; b < h->L.n - 1; b++) out[b] = h->dims[b + 1];
+  return TNSIM_OK;
+}
+
+tnsim_status tnsim_truncation_stats(tnsim_mps h, double *sum_eps, double *prod, int64_t *n2q) {
+  tnsim_status s = check_handle(h);
+  if (s != TNSIM_OK) return s;
+  if (sum_eps) *sum_eps = h->sum_eps;
+  if (prod) *prod = h->prod_keep;
+  if (n2q) *n2q = h->n2q;
+  return TNSIM_OK;
+}
+
+tnsim_status tnsim_last_sweeps(tnsim_mps h, int32_t *sweeps) {
+  tnsim_status s = check_handle(h);
+  if (s != TNSIM_OK) return s;
+  if (!sweeps) return TNSIM_E_ARG;
+  *sweeps = h->last_sweeps;
+  return TNSIM_OK;
+}
+
+tnsim_status tnsim_export_site(tnsim_mps h, int32_t q, tnsim_c128 *host, int32_t *chiL,
+                               int32_t *chiR) {
+  tnsim_status s = check_handle(h);
+  if (s != TNSIM_OK) return s;
+  if (q < 0 || q >= h->L.n) return TNSIM_E_ARG;
+  int a = h->dims[q], b = h->dims[q + 1];
+  if (chiL) *chiL = a;
+  if (chiR) *chiR = b;
+  if (!host) return TNSIM_OK;
+  size_t cnt = (size_t)a * 2 * b;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (h->L.storage == 0) {
+    HIPCHK(h, hipMemcpy(host, h->site(q), cnt * 16, hipMemcpyDeviceToHost));
+  } else {
+    std::vector<float> tmp(2 * cnt);
+    HIPCHK(h, hipMemcpy(tmp.data(), h->site(q), cnt * 8, hipMemcpyDeviceToHost));
+    for (size_t e = 0; e < cnt; e++) {
+      host[e].re = tmp[2 * e];
+      host[e].im = tmp[2 * e + 1];
+    }
+  }
+  return TNSIM_OK;
+}
+
+tnsim_status tnsim_export_lambda(tnsim_mps h, int32_t bond, double *host, int32_t *chi) {
+  tnsim_status s = check_handle(h);
+  if (s != TNSIM_OK) return s;
+  if (bond < 0 || bond >= h->L.n - 1) return TNSIM_E_ARG;
+  int c = h->dims[bond + 1];
+  if (chi) *chi = c;
+  if (!host) return TNSIM_OK;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  HIPCHK(h, hipMemcpy(host, h->lam(bond), sizeof(double) * c, hipMemcpyDeviceToHost));
+  return TNSIM_OK;
+}
+
+tnsim_status tnsim_import_state(tnsim_mps h, const tnsim_c128 *const *sites,
+                                const double *const *lambdas, const int32_t *chis) {
+  tnsim_status s = check_handle(h);
+  if (s != TNSIM_OK) return s;
+  const int n = h->L.n;
+  if (!sites || !chis || (n > 1 && !lambdas)) return TNSIM_E_ARG;
+  if (chis[0] != 1 || chis[n] != 1) return TNSIM_E_ARG;
+  for (int q = 0; q < n; q++) {
+    if (!sites[q] || chis[q + 1] < 1) return TNSIM_E_ARG;
+    if (q + 1 < n && !lambdas[q]) return TNSIM_E_ARG;
+  }
+  for (int q = 1; q < n; q++)
+    if (chis[q] > h->L.dimcap[q]) return TNSIM_E_CAPACITY;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  for (int q = 0; q < n; q++) {
+    size_t cnt = (size_t)chis[q] * 2 * chis[q + 1];
+    if (h->L.storage == 0) {
+      HIPCHK(h, hipMemcpy(h->site(q), sites[q], cnt * 16, hipMemcpyHostToDevice));
+    } else {
+      std::vector<float> tmp(2 * cnt);
+      for (size_t e = 0; e < cnt; e++) {
+        tmp[2 * e] = (float)sites[q][e].re;
+        tmp[2 * e + 1] = (float)sites[q][e].im;
+      }
+      HIPCHK(h, hipMemcpy(h->site(q), tmp.data(), cnt * 8, hipMemcpyHostToDevice));
+    }
+  }
+  for (int b = 0; b < n - 1; b++)
+    HIPCHK(h, hipMemcpy(h->lam(b), lambdas[b], sizeof(double) * chis[b + 1],
+                        hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(h->dims_dev(), chis, sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice));
+  h->dims.assign(chis, chis + n + 1);
+  return TNSIM_OK;
+}
+
+const char *tnsim_status_string(tnsim_status st) {
+  switch (st) {
+    case TNSIM_OK: return "ok";
+    case TNSIM_E_ARG: return "invalid argument";
+    case TNSIM_E_NONLOCAL: return "two-qubit gate on non-neighbouring qubits";
+    case TNSIM_E_OVERLAP: return "layer uses a qubit twice";
+    case TNSIM_E_CAPACITY: return "arena or bond capacity too small";
+    case TNSIM_E_DEVICE: return "HIP device failure";
+    case TNSIM_E_NOCONV: return "Jacobi SVD did not converge";
+  }
+  return "unknown status";
+}
+
+const char *tnsim_last_error(tnsim_mps h) {
+  if (!h) return g_create_error.c_str();
+  return h->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,96 @@
+// Internal types shared by the library's HIP sources (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace tn {
+
+// Jacobi block width: the SVD rotates pairs of 32-column blocks, so one pair
+// problem is a 64x64 Hermitian Gram matrix that fits in one workgroup's LDS.
+constexpr int BW = 32;
+constexpr int PW = 64;
+constexpr int KSPLIT_MAX = 16;
+
+// Scalars per gate slot (device memory).
+struct SlotScalars {
+  double fro2;  // squared Frobenius norm of the Jacobi matrix
+  double N;     // sqrt of the kept weight
+  double eps;   // discarded weight / total weight
+  double W;     // total weight
+  int k;        // kept bond dimension
+  int rot;      // some pair rotated during the current sweep
+  int active;   // gate still sweeping
+  int nz;       // count above the numerical-zero floor
+};
+
+// Device descriptor of one two-qubit gate in a batch.  The host fills it from
+// its copy of the bond dimensions; kernels never read dimensions elsewhere.
+struct GateDesc {
+  int i;                 // left site
+  int chiL, chiM, chiR;  // bond dims around sites i, i+1
+  int m, n;              // M is m x n: m = 2 chiL rows (a,s), n = 2 chiR cols (t,c)
+  int rows, cols;        // Jacobi matrix X: rows x cols, cols = min(m, n)
+  int trans;             // 1: X = M^H (n > m) and J accumulates U; 0: X = M
+  int ldx, ldj;          // leading dims of X and J (column-major)
+  int colsPad;           // cols rounded up to a multiple of 64
+  int nblk;              // colsPad / 32
+  int chiMax;
+  int storage;           // 0 = complex128 sites, 1 = complex64 sites
+  int tfp32;             // theta' stored as complex64 (mixed modes)
+  int pad0;
+  double tol;            // relative off-diagonal tolerance
+  double cutoff;         // discarded-weight cutoff
+  void *A0, *A1;         // site i, site i+1
+  const double *lamR;    // lambda_{i+1} or nullptr (= all ones)
+  double *lamOut;        // lambda_i
+  double2 *X, *J;        // Jacobi matrix, accumulated left vectors (trans only)
+  void *T;               // theta' (m x n, row-major)
+  double2 *Gp, *V;       // pair Gram partials, pair rotations
+  int *pairFlag;         // pair rotated in this round
+  double *sig2;          // column norms squared
+  int *perm;             // columns sorted by descending norm
+  SlotScalars *sc;
+  double2 g[16];         // the 4x4 gate
+};
+
+struct Gate1Desc {
+  void *A;
+  int chiL, chiR;
+  int storage, pad;
+  double2 u[4];
+};
+
+// Launch wrappers (each enqueues on `st`; errors are collected by the caller
+// through hipGetLastError / hipPeekAtLastError).
+void launch_init_state(hipStream_t st, void *const *sites_dev_list, int n, int storage,
+                       double *const *lam_list_dev, int nb);
+void launch_fill_zero(hipStream_t st, void *p, size_t bytes);
+void launch_apply_1q(hipStream_t st, const Gate1Desc *d, int ng, int max_elems);
+void launch_convert(hipStream_t st, const void *src, int src_storage, void *dst, int dst_storage,
+                    size_t count);
+void launch_setup_slots(hipStream_t st, const GateDesc *d, int ng, int max_rows_pad,
+                        int max_m_pad);
+void launch_theta(hipStream_t st, const GateDesc *d, int ng, int precision, int max_m,
+                  int max_chiR);
+void launch_colnorm(hipStream_t st, const GateDesc *d, int ng, int max_cols);
+void launch_gate_init(hipStream_t st, const GateDesc *d, int ng);
+void launch_begin_sweep(hipStream_t st, const GateDesc *d, int ng);
+void launch_round(hipStream_t st, const GateDesc *d, int ng, int round, int max_pairs,
+                  int ksplit, int max_rows, int max_m, int npairs_stride);
+void launch_trunc(hipStream_t st, const GateDesc *d, int ng, int *dims_dev);
+void launch_writeback(hipStream_t st, const GateDesc *d, int ng, int precision, int max_m,
+                      int max_k, int max_n);
+
+// Readouts
+void launch_gemm_nn(hipStream_t st, int M, int N, int K, const double2 *A, int lda,
+                    const void *B, int ldb, int b_storage, double2 *C, int ldc);
+void launch_gemm_cn(hipStream_t st, int M, int N, int K, const void *A, int lda, int a_storage,
+                    const double2 *B, int ldb, double2 *C, int ldc);
+void launch_pauli_phys(hipStream_t st, const double2 *F, double2 *F2, int chiA, int chiB,
+                       double2 p00, double2 p01, double2 p10, double2 p11);
+void launch_amp_step(hipStream_t st, const double2 *v, double2 *w, const void *A, int storage,
+                     int chiL, int chiR, int bit);
+
+}  // namespace tn

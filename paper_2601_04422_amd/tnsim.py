@@ -1,0 +1,269 @@
+"""Python binding of the tnsim C ABI (include/tnsim.h).
+
+Argument marshalling only: every step of gate application and readout runs
+in the HIP library ``libtnsim.so``.  PyTorch provides the device arena and the
+stream.  There is no CPU fallback: if the library is missing, or no GPU is
+visible, constructing an ``MPS`` raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Iterable, List, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtnsim.so")
+
+OK, E_ARG, E_NONLOCAL, E_OVERLAP, E_CAPACITY, E_DEVICE, E_NOCONV = range(7)
+PRECISION = {"fp64": 0, "f32acc": 1, "bf16x3": 2, "bf16x6": 3}
+STORAGE = {"c128": 0, "c64": 1}
+
+
+class C128(C.Structure):
+    _fields_ = [("re", C.c_double), ("im", C.c_double)]
+
+
+class Config(C.Structure):
+    _fields_ = [("n_qubits", C.c_int32), ("chi_max", C.c_int32), ("cutoff", C.c_double),
+                ("precision", C.c_int32), ("storage", C.c_int32),
+                ("jacobi_max_sweeps", C.c_int32), ("jacobi_tol", C.c_double),
+                ("max_layer_gates", C.c_int32)]
+
+
+GATE_DTYPE = np.dtype([("q0", "<i4"), ("q1", "<i4"), ("m", "<c16", (16,))], align=True)
+assert GATE_DTYPE.itemsize == 264
+
+# every exported entry point, with its ctypes signature
+_P = C.c_void_p
+_SIGS = {
+    "tnsim_mps_arena_bytes": (C.c_size_t, [C.POINTER(Config)]),
+    "tnsim_mps_create": (C.c_int, [C.POINTER(Config), _P, C.c_size_t, _P, C.POINTER(_P)]),
+    "tnsim_mps_destroy": (C.c_int, [_P]),
+    "tnsim_mps_reset": (C.c_int, [_P]),
+    "tnsim_apply_1q": (C.c_int, [_P, C.c_int32, _P]),
+    "tnsim_apply_2q": (C.c_int, [_P, C.c_int32, C.c_int32, _P]),
+    "tnsim_apply_layer": (C.c_int, [_P, _P, C.c_int32]),
+    "tnsim_apply_layer_multi": (C.c_int, [_P, _P, _P, C.c_int32]),
+    "tnsim_layerise": (C.c_int, [_P, C.c_int32, C.c_int32, _P, C.POINTER(C.c_int32)]),
+    "tnsim_expect_pauli": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double)]),
+    "tnsim_amplitude": (C.c_int, [_P, _P, C.POINTER(C128)]),
+    "tnsim_overlap": (C.c_int, [_P, _P, C.POINTER(C128)]),
+    "tnsim_mps_copy": (C.c_int, [_P, _P]),
+    "tnsim_bond_dims": (C.c_int, [_P, _P]),
+    "tnsim_truncation_stats": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                         C.POINTER(C.c_int64)]),
+    "tnsim_last_sweeps": (C.c_int, [_P, C.POINTER(C.c_int32)]),
+    "tnsim_export_site": (C.c_int, [_P, C.c_int32, _P, C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_int32)]),
+    "tnsim_export_lambda": (C.c_int, [_P, C.c_int32, _P, C.POINTER(C.c_int32)]),
+    "tnsim_import_state": (C.c_int, [_P, _P, _P, _P]),
+    "tnsim_status_string": (C.c_char_p, [C.c_int]),
+    "tnsim_last_error": (C.c_char_p, [_P]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libtnsim.so (built in-tree by ``__graft_entry__.build()``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"tnsim HIP library not built: {LIB_PATH} is missing "
+                               "(run __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class TnsimError(RuntimeError):
+    def __init__(self, code: int, what: str, detail: str = ""):
+        msg = lib().tnsim_status_string(code).decode()
+        super().__init__(f"{what}: {msg}" + (f" ({detail})" if detail else ""))
+        self.code = code
+
+
+def _c128_array(m, size: int):
+    a = np.zeros(size, dtype=np.complex128)
+    flat = np.asarray(m, dtype=np.complex128).reshape(-1)
+    a[: flat.size] = flat
+    return a
+
+
+def pack_gates(gates: Sequence) -> np.ndarray:
+    """[(q0, q1, matrix), ...] -> array of tnsim_gate."""
+    arr = np.zeros(len(gates), dtype=GATE_DTYPE)
+    for k, (q0, q1, m) in enumerate(gates):
+        arr[k]["q0"] = q0
+        arr[k]["q1"] = q1
+        arr[k]["m"] = _c128_array(m, 16)
+    return arr
+
+
+def layerise(gates: Sequence, n: int) -> List[List]:
+    """Greedy layering of a gate list (library call), returned as layers."""
+    arr = pack_gates(gates)
+    out = np.zeros(max(len(gates), 1), dtype=np.int32)
+    nl = C.c_int32()
+    st = lib().tnsim_layerise(arr.ctypes.data, len(gates), n, out.ctypes.data, C.byref(nl))
+    if st != OK:
+        raise TnsimError(st, "layerise")
+    layers: List[List] = [[] for _ in range(nl.value)]
+    for g, l in zip(gates, out[: len(gates)]):
+        layers[int(l)].append(g)
+    return layers
+
+
+class MPS:
+    """An MPS on one GPU, driven through the tnsim C ABI."""
+
+    def __init__(self, n: int, chi_max: int, cutoff: float = 0.0, precision: str = "fp64",
+                 storage: str = "c128", jacobi_max_sweeps: int = 0, jacobi_tol: float = 0.0,
+                 max_layer_gates: int = 0, device: str = "cuda:0"):
+        import torch  # device memory and streams only
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("tnsim needs a HIP GPU; none is visible")
+        self.n = n
+        self.chi_max = chi_max
+        self.precision = precision
+        self.storage = storage
+        self.cfg = Config(n, chi_max, cutoff, PRECISION[precision], STORAGE[storage],
+                          jacobi_max_sweeps, jacobi_tol, max_layer_gates)
+        nbytes = lib().tnsim_mps_arena_bytes(C.byref(self.cfg))
+        if nbytes == 0:
+            raise TnsimError(E_ARG, "arena_bytes")
+        self.device = torch.device(device)
+        with torch.cuda.device(self.device):
+            self.arena = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self.stream = torch.cuda.current_stream(self.device)
+            h = C.c_void_p()
+            st = lib().tnsim_mps_create(C.byref(self.cfg), C.c_void_p(self.arena.data_ptr()),
+                                        nbytes, C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if st != OK:
+            raise TnsimError(st, "mps_create", lib().tnsim_last_error(None).decode())
+        self._h = h
+
+    @property
+    def arena_bytes(self) -> int:
+        return self.arena.numel()
+
+    def close(self) -> None:
+        h = getattr(self, "_h", None)
+        if h:
+            lib().tnsim_mps_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, st: int, what: str) -> None:
+        if st != OK:
+            raise TnsimError(st, what, lib().tnsim_last_error(self._h).decode())
+
+    # ---------------------------------------------------------------- gates
+    def reset(self) -> None:
+        self._chk(lib().tnsim_mps_reset(self._h), "reset")
+
+    def apply_1q(self, q: int, u) -> None:
+        a = _c128_array(u, 4)
+        self._chk(lib().tnsim_apply_1q(self._h, q, a.ctypes.data), "apply_1q")
+
+    def apply_2q(self, q0: int, q1: int, g) -> int:
+        a = _c128_array(g, 16)
+        return lib().tnsim_apply_2q(self._h, q0, q1, a.ctypes.data)
+
+    def apply(self, gate) -> None:
+        q0, q1, m = gate
+        if q1 < 0:
+            self.apply_1q(q0, m)
+        else:
+            self._chk(self.apply_2q(q0, q1, m), "apply_2q")
+
+    def apply_layer(self, gates: Sequence) -> int:
+        arr = pack_gates(gates)
+        return lib().tnsim_apply_layer(self._h, arr.ctypes.data, len(gates))
+
+    def run_layers(self, layers: Iterable[Sequence]) -> None:
+        for layer in layers:
+            self._chk(self.apply_layer(layer), "apply_layer")
+
+    def run_gates(self, gates: Iterable) -> None:
+        """One gate per call (the per-gate path)."""
+        for g in gates:
+            self.apply(g)
+
+    # ---------------------------------------------------------------- readouts
+    def expect(self, pauli: str) -> complex:
+        re, im = C.c_double(), C.c_double()
+        self._chk(lib().tnsim_expect_pauli(self._h, pauli.encode(), C.byref(re), C.byref(im)),
+                  "expect_pauli")
+        return complex(re.value, im.value)
+
+    def amplitude(self, bits: Sequence[int]) -> complex:
+        b = np.ascontiguousarray(bits, dtype=np.uint8)
+        out = C128()
+        self._chk(lib().tnsim_amplitude(self._h, b.ctypes.data, C.byref(out)), "amplitude")
+        return complex(out.re, out.im)
+
+    def overlap(self, other: "MPS") -> complex:
+        out = C128()
+        self._chk(lib().tnsim_overlap(self._h, other._h, C.byref(out)), "overlap")
+        return complex(out.re, out.im)
+
+    def norm2(self) -> float:
+        return self.overlap(self).real
+
+    def copy_from(self, other: "MPS") -> None:
+        self._chk(lib().tnsim_mps_copy(self._h, other._h), "mps_copy")
+
+    # ---------------------------------------------------------------- inspection
+    def bond_dims(self) -> np.ndarray:
+        out = np.zeros(self.n - 1, dtype=np.int32)
+        self._chk(lib().tnsim_bond_dims(self._h, out.ctypes.data), "bond_dims")
+        return out
+
+    def stats(self) -> dict:
+        se, pk = C.c_double(), C.c_double()
+        n2 = C.c_int64()
+        self._chk(lib().tnsim_truncation_stats(self._h, C.byref(se), C.byref(pk), C.byref(n2)),
+                  "truncation_stats")
+        sw = C.c_int32()
+        self._chk(lib().tnsim_last_sweeps(self._h, C.byref(sw)), "last_sweeps")
+        return {"sum_eps": se.value, "prod_keep": pk.value, "n2q": n2.value,
+                "last_sweeps": sw.value}
+
+    def site(self, q: int) -> np.ndarray:
+        a, b = C.c_int32(), C.c_int32()
+        self._chk(lib().tnsim_export_site(self._h, q, None, C.byref(a), C.byref(b)), "export")
+        out = np.zeros((a.value, 2, b.value), dtype=np.complex128)
+        self._chk(lib().tnsim_export_site(self._h, q, out.ctypes.data, C.byref(a), C.byref(b)),
+                  "export_site")
+        return out
+
+    def lam(self, bond: int) -> np.ndarray:
+        c = C.c_int32()
+        self._chk(lib().tnsim_export_lambda(self._h, bond, None, C.byref(c)), "export")
+        out = np.zeros(c.value, dtype=np.float64)
+        self._chk(lib().tnsim_export_lambda(self._h, bond, out.ctypes.data, C.byref(c)),
+                  "export_lambda")
+        return out
+
+    def import_state(self, sites: Sequence[np.ndarray], lams: Sequence[np.ndarray]) -> None:
+        n = self.n
+        sites = [np.ascontiguousarray(s, dtype=np.complex128) for s in sites]
+        lams = [np.ascontiguousarray(l, dtype=np.float64) for l in lams]
+        chis = np.array([1] + [s.shape[2] for s in sites[:-1]] + [1], dtype=np.int32)
+        sp = (C.c_void_p * n)(*[s.ctypes.data for s in sites])
+        lp = (C.c_void_p * max(n - 1, 1))(*([l.ctypes.data for l in lams] or [None]))
+        self._chk(lib().tnsim_import_state(self._h, sp, lp, chis.ctypes.data), "import_state")

@@ -1,0 +1,186 @@
+"""GPU path against the CPU oracle (and the brute-force state vector).
+
+Tolerances: the float64 path is compared at 1e-12 on amplitudes when no
+truncation happens, and at 1e-10 on Schmidt spectra and 1 - F when it does
+(both sides take the same truncation decisions on generic random inputs).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from checkers import amplitude_index, fidelity_dense, statevector
+from gpu_helpers import gpu_statevector, mps_fidelity_gpu_vs_oracle
+from oracle import oracle as O
+from paper_2601_04422_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    from paper_2601_04422_amd import tnsim
+
+    return tnsim
+
+
+def _oracle_fid(g, o):
+    return mps_fidelity_gpu_vs_oracle(g, o, lambda n: O.OracleMPS(n, 4096))
+
+
+@pytest.mark.parametrize("mode", ["layer", "per_gate"])
+def test_small_brickwork_amplitudes(T, mode):
+    cfg = W.config_small()
+    m = T.MPS(cfg.n, cfg.chi_max, cfg.cutoff)
+    if mode == "layer":
+        m.run_layers(cfg.layers)
+    else:
+        m.run_gates(cfg.gates())
+    ref = statevector(cfg.n, cfg.gates())
+    got = gpu_statevector(m)
+    assert np.max(np.abs(got - ref)) < 1e-12
+    rng = np.random.default_rng(3)
+    for _ in range(8):
+        bits = rng.integers(0, 2, cfg.n)
+        assert abs(m.amplitude(bits) - ref[amplitude_index(bits)]) < 1e-12
+    o = O.OracleMPS(cfg.n, cfg.chi_max, cfg.cutoff)
+    o.run_layers(cfg.layers)
+    assert list(m.bond_dims()) == list(o.bond_dims())
+    for b in range(cfg.n - 1):
+        assert np.max(np.abs(m.lam(b) - o.lam(b))) < 1e-12
+
+
+def test_ghz_n100(T):
+    n = 100
+    m = T.MPS(n, 64)
+    m.run_gates(W.ghz(n))
+    assert abs(m.amplitude([0] * n) - 1 / math.sqrt(2)) < 1e-14
+    assert abs(m.amplitude([1] * n) - 1 / math.sqrt(2)) < 1e-14
+    assert max(m.bond_dims()) == 2
+
+
+def test_product_state_closed_forms(T):
+    n = 6
+    m = T.MPS(n, 4)
+    th, ph, al = [0.3, 1.7, 3.0], [1.1, -0.4, 2.5], [2.0, 0.5, 4.4]
+    layer1 = [(2 * r, -1, W.ry(th[r])) for r in range(3)] + \
+             [(2 * r + 1, -1, W.rx(al[r])) for r in range(3)]
+    layer2 = [(2 * r, -1, W.rz(ph[r])) for r in range(3)]
+    m.run_layers([layer1, layer2])
+
+    def e(q, c):
+        s = ["I"] * n
+        s[q] = c
+        return m.expect("".join(s))
+
+    for r in range(3):
+        assert abs(e(2 * r, "Z") - math.cos(th[r])) < 1e-14
+        assert abs(e(2 * r, "X") - math.sin(th[r]) * math.cos(ph[r])) < 1e-14
+        assert abs(e(2 * r, "Y") - math.sin(th[r]) * math.sin(ph[r])) < 1e-14
+        assert abs(e(2 * r + 1, "Z") - math.cos(al[r])) < 1e-14
+        assert abs(e(2 * r + 1, "Y") + math.sin(al[r])) < 1e-14
+
+
+@pytest.mark.parametrize("seed", [11, 12])
+def test_mixed_gates_reversed_orientation(T, seed):
+    rng = np.random.default_rng(seed)
+    n = 7
+    gates = []
+    for _ in range(40):
+        if rng.random() < 0.4:
+            q = int(rng.integers(0, n))
+            gates.append((q, -1, W.rot("XYZ"[int(rng.integers(0, 3))], rng.uniform(0, 6.3))))
+        else:
+            j = int(rng.integers(0, n - 1))
+            g = W.haar_u4(rng)
+            gates.append((j, j + 1, g) if rng.random() < 0.5 else (j + 1, j, g))
+    m = T.MPS(n, 64)
+    m.run_gates(gates)
+    ref = statevector(n, gates)
+    assert np.max(np.abs(gpu_statevector(m) - ref)) < 1e-12
+
+
+@pytest.mark.parametrize("n,depth,chi,cutoff", [(16, 12, 12, 1e-10), (18, 14, 100, 1e-10),
+                                                (12, 10, 5, 0.0)])
+def test_truncating_brickwork_vs_oracle(T, n, depth, chi, cutoff):
+    """Truncation active; chi_max values that leave ragged tiles."""
+    layers = W.brickwork_haar(n, depth, 900 + n)
+    m = T.MPS(n, chi, cutoff)
+    m.run_layers(layers)
+    o = O.OracleMPS(n, chi, cutoff)
+    o.run_layers(layers)
+    assert list(m.bond_dims()) == list(o.bond_dims())
+    for b in range(n - 1):
+        assert np.max(np.abs(m.lam(b) - o.lam(b))) < 1e-10
+    st_g, st_o = m.stats(), o.stats()
+    assert abs(st_g["sum_eps"] - st_o["sum_eps"]) <= 1e-10 * max(1.0, st_o["sum_eps"])
+    assert 1 - _oracle_fid(m, o) < 1e-10
+
+
+def test_layer_permutation_bit_exact(T):
+    n = 14
+    layers = W.brickwork_haar(n, 8, 31)
+    a = T.MPS(n, 16, 1e-10)
+    b = T.MPS(n, 16, 1e-10)
+    rng = np.random.default_rng(0)
+    for layer in layers:
+        assert a.apply_layer(layer) == T.OK
+        perm = rng.permutation(len(layer))
+        assert b.apply_layer([layer[i] for i in perm]) == T.OK
+    for q in range(n):
+        assert np.array_equal(a.site(q), b.site(q))
+    assert a.stats()["sum_eps"] > 0
+
+
+def test_expectations_and_overlap_vs_oracle(T):
+    n = 12
+    layers = W.brickwork_haar(n, 8, 5)
+    m = T.MPS(n, 32, 0.0)
+    m.run_layers(layers)
+    o = O.OracleMPS(n, 32, 0.0)
+    o.run_layers(layers)
+    rng = np.random.default_rng(8)
+    for _ in range(6):
+        p = "".join(rng.choice(list("IXYZ"), n))
+        assert abs(m.expect(p) - o.expect(p)) < 1e-12
+    assert abs(m.norm2() - 1) < 1e-12
+    m2 = T.MPS(n, 32, 0.0)
+    m2.run_layers(layers[:-1])
+    o2 = O.OracleMPS(n, 32, 0.0)
+    o2.run_layers(layers[:-1])
+    assert abs(m.overlap(m2) - o.overlap(o2)) < 1e-12
+
+
+def test_import_export_roundtrip_and_copy(T):
+    n = 10
+    dims = W.saturated_dims(n, 8)
+    sites, lams = W.random_canonical_mps(n, dims, 4)
+    m = T.MPS(n, 8)
+    m.import_state(sites, lams)
+    for q in range(n):
+        assert np.array_equal(m.site(q), sites[q])
+    c = T.MPS(n, 8, storage="c64")
+    c.copy_from(m)
+    for q in range(n):
+        assert np.max(np.abs(c.site(q) - sites[q])) < 1e-6
+    assert abs(abs(m.overlap(c)) - 1) < 1e-6
+
+
+def test_errors_leave_state_unchanged(T):
+    n = 6
+    m = T.MPS(n, 8)
+    g = W.cnot()
+    assert m.apply_layer([(0, 1, g), (1, 2, g)]) == T.E_OVERLAP
+    assert m.apply_layer([(0, 2, g)]) == T.E_NONLOCAL
+    assert m.apply_layer([(5, 6, g)]) == T.E_ARG
+    assert m.apply_2q(0, 3, g) == T.E_NONLOCAL
+    assert list(m.bond_dims()) == [1] * (n - 1)
+    nc = T.MPS(n, 8, jacobi_max_sweeps=1)
+    rng = np.random.default_rng(2)
+    assert nc.apply_2q(2, 3, W.haar_u4(rng)) == T.E_NOCONV
+    assert list(nc.bond_dims()) == [1] * (n - 1)
+    # the handle stays usable after NOCONV
+    assert abs(nc.amplitude([0] * n) - 1) < 1e-15
