@@ -1,0 +1,247 @@
+"""Benchmark: two-qubit gates/s at chi = 1024 on one GPU.
+
+Workload: the n=100 circuit of layers "Rx(a), Rz(b) on every qubit, then CNOT
+on alternating bonds" at chi_max = 1024, cutoff 1e-12.  Layers 0..P-1 (P = 20
+by default) are run untimed with the float64 path to reach saturation (bonds
+in the bulk at chi = 1024); that state is the shared starting point of
+
+* the batched mixed path: every gate of a layer in one launch sequence, theta
+  contraction and right-site write-back in split-bf16 (or the chosen
+  precision), complex64 site storage, float64 Jacobi SVD;
+* the per-gate float64 path: one gate per launch sequence, complex128.
+
+A step is one circuit layer (both one-qubit sublayers and the CNOT
+sublayer).  ``value`` counts the CNOTs whose three bonds were all 1024 when
+applied, over the wall time of the timed steps (inputs already on the GPU).
+The per-result error is 1 - F between the two paths' final states.
+
+``cpu_baseline`` times the CPU oracle on one two-qubit gate of the same size
+(2048 x 2048 Jacobi SVD) from a seeded random left-canonical input.
+
+One JSON line is printed on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "2q gates/s at χ=1024, batched mixed vs per-gate FP64, fidelity err≤1e-6"
+FP64_PEAK_TFLOPS = 78.6
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--prep-layers", type=int, default=20)
+    ap.add_argument("--precision", default="bf16x6", choices=["fp64", "f32acc", "bf16x3", "bf16x6"])
+    ap.add_argument("--storage", default="c64", choices=["c128", "c64"])
+    ap.add_argument("--chi", type=int, default=1024)
+    ap.add_argument("--no-pergate", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=16)
+    return ap.parse_args()
+
+
+def circuit_layers(n_layers):
+    from paper_2601_04422_amd import workloads as W
+
+    sub = W.config_chi1024(n_layers).layers  # 3 sublayers per circuit layer
+    return [sub[3 * l: 3 * l + 3] for l in range(n_layers)]
+
+
+def count_full(m, cnot_layer, chi):
+    d = [1] + list(m.bond_dims()) + [1]
+    return sum(1 for (q0, q1, _) in cnot_layer if d[q0] == chi and d[q0 + 1] == chi and d[q0 + 2] == chi)
+
+
+def run_layer_batched(m, layer):
+    for sub in layer:
+        st = m.apply_layer(sub)
+        if st != 0:
+            raise RuntimeError(f"apply_layer failed with status {st}")
+
+
+def run_layer_pergate(m, layer):
+    for sub in layer:
+        m.run_gates(sub)
+
+
+def cpu_baseline(threads, chi):
+    """Oracle time for one chi x chi x chi two-qubit gate (seeded random input)."""
+    from oracle import oracle as O
+    from paper_2601_04422_amd import workloads as W
+
+    O.set_threads(threads)
+    rng = np.random.default_rng(77)
+    dims = [1, chi, chi, chi, 1]
+    sites = [rng.standard_normal((1, 2, chi)) + 0j,
+             W.random_isometry(rng, 2 * chi, chi).reshape(chi, 2, chi),
+             W.random_isometry(rng, 2 * chi, chi).reshape(chi, 2, chi),
+             rng.standard_normal((chi, 2, 1)) + 0j]
+    lams = [W.schmidt_profile(rng, chi) for _ in range(3)]
+    m = O.OracleMPS(4, chi, 1e-12)
+    m.set_state(sites, lams)
+    g = W.cnot() @ np.kron(W.rz(0.7) @ W.rx(1.3), W.rz(2.1) @ W.rx(0.4))
+    t0 = time.perf_counter()
+    st = m.apply_2q(1, 2, g)
+    dt = time.perf_counter() - t0
+    if st != 0:
+        raise RuntimeError(f"oracle gate failed: {st}")
+    s = m.stats()
+    return {"value": 1.0 / dt, "unit": "2q gates/s", "cores": O.threads(), "kind": "oracle",
+            "sample": f"1 two-qubit gate at chiL=chiM=chiR={chi} (M is {2*chi}x{2*chi}, "
+                      f"Jacobi {s['last_sweeps']} sweeps, kept {s['last_k']}) on a seeded random "
+                      f"left-canonical input; {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2601_04422_amd import tnsim as T
+
+    n, chi = 100, args.chi
+    P, Wu, K = args.prep_layers, args.warmup, args.steps
+    layers = circuit_layers(P + Wu + K)
+
+    # --- preparation (untimed): float64 batched path up to saturation
+    ref = T.MPS(n, chi, 1e-12, precision="fp64", storage="c128")
+    t0 = time.perf_counter()
+    for l in range(P):
+        run_layer_batched(ref, layers[l])
+        log(f"prep layer {l}: max chi {int(max(ref.bond_dims()))} "
+            f"({time.perf_counter() - t0:.1f} s)")
+    torch.cuda.synchronize()
+    prep_s = time.perf_counter() - t0
+
+    # --- batched mixed path from the snapshot
+    mix = T.MPS(n, chi, 1e-12, precision=args.precision, storage=args.storage)
+    mix.copy_from(ref)
+    for l in range(P, P + Wu):
+        run_layer_batched(mix, layers[l])
+        log(f"mixed warmup layer {l}")
+    torch.cuda.synchronize()
+    mix.profile(True)
+    full = 0
+    total2q = 0
+    per_layer = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for l in range(P + Wu, P + Wu + K):
+        tl = time.perf_counter()
+        full += count_full(mix, layers[l][2], chi)
+        total2q += len(layers[l][2])
+        run_layer_batched(mix, layers[l])
+        per_layer.append(time.perf_counter() - tl)
+        log(f"mixed layer {l}: {per_layer[-1]:.2f} s")
+    torch.cuda.synchronize()
+    mix_s = time.perf_counter() - t0
+    prof = mix.profile_read()
+    mix.profile(False)
+    mix_sweeps = mix.sweep_stats()
+
+    # --- per-gate float64 path from the same snapshot, same layers
+    pergate = None
+    fid_err = None
+    if not args.no_pergate:
+        for l in range(P, P + Wu):
+            run_layer_pergate(ref, layers[l])
+            log(f"per-gate warmup layer {l}")
+        torch.cuda.synchronize()
+        ref.profile(True)
+        pfull = 0
+        t0 = time.perf_counter()
+        for l in range(P + Wu, P + Wu + K):
+            tl = time.perf_counter()
+            pfull += count_full(ref, layers[l][2], chi)
+            run_layer_pergate(ref, layers[l])
+            log(f"per-gate layer {l}: {time.perf_counter() - tl:.2f} s")
+        torch.cuda.synchronize()
+        pg_s = time.perf_counter() - t0
+        pprof = ref.profile_read()
+        psweeps = ref.sweep_stats()
+        ref.profile(False)
+        pergate = {"value": pfull / pg_s, "unit": "2q gates/s", "ms_per_step": 1e3 * pg_s / K,
+                   "dtype": "f64", "storage": "c128", "jacobi_sweeps": psweeps,
+                   "kernel_ms": {k: round(v["ms"], 3) for k, v in pprof.items() if v["launches"]}}
+        ov = ref.overlap(mix)
+        fid = abs(ov) ** 2 / (ref.norm2() * mix.norm2())
+        fid_err = 1.0 - fid
+
+    # --- roofline of the dominant kernel of the batched path
+    dom = max(prof, key=lambda k: prof[k]["ms"])
+    d = prof[dom]
+    if d["flops"] > 0:
+        achieved = d["flops"] / (d["ms"] * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None, "kernel": dom,
+                "launches": d["launches"], "avg_launch_ms": d["ms"] / max(d["launches"], 1),
+                "flops_per_launch": d["flops"] / max(d["launches"], 1)}
+    else:
+        achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
+                "launches": d["launches"], "avg_launch_ms": d["ms"] / max(d["launches"], 1)}
+
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline: oracle on one gate ...")
+        cpu = cpu_baseline(args.cpu_threads, chi)
+
+    value = full / mix_s
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "2q gates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wu,
+        "ms_per_step": 1e3 * mix_s / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": f"{args.precision} contraction, f64 svd",
+        "data": "synthetic",
+        "config": {"workload": f"n=100 circuit, layers of Rx,Rz on every qubit then CNOT on "
+                               f"alternating bonds; chi_max={chi}, cutoff 1e-12; layers 0-{P-1} "
+                               f"untimed (f64), {Wu} warmup + {K} timed layers",
+                   "n_qubits": n, "chi_max": chi, "cutoff": 1e-12, "storage": args.storage,
+                   "precision": args.precision, "timed_2q_gates": total2q,
+                   "timed_gates_at_full_chi": full, "parallelism": "single gpu"},
+        "all_2q_gates_per_s": total2q / mix_s,
+        "pergate_fp64": pergate,
+        "speedup_vs_pergate": (value / pergate["value"]) if pergate and pergate["value"] else None,
+        "fidelity_err_vs_fp64": fid_err,
+        "jacobi_sweeps": mix_sweeps,
+        "prep_s": prep_s,
+        "layer_s": [round(x, 3) for x in per_layer],
+        "kernel_ms": {k: round(v["ms"], 3) for k, v in prof.items() if v["launches"]},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -163,6 +163,10 @@ tnsim_status tnsim_truncation_stats(tnsim_mps mps, double *sum_eps, double *prod
                                     int64_t *n2q);
 /* Largest Jacobi sweep count used by the last apply call. */
 tnsim_status tnsim_last_sweeps(tnsim_mps mps, int32_t *sweeps);
+/* Jacobi sweep counts per two-qubit gate, summed since creation or the
+   last tnsim_profile(mps, 1). */
+tnsim_status tnsim_sweep_stats(tnsim_mps mps, int64_t *gates, int64_t *sweeps_sum,
+                               int32_t *sweeps_max);
 /* Site q as complex128 (chiL*2*chiR entries); host may be NULL to query dims. */
 tnsim_status tnsim_export_site(tnsim_mps mps, int32_t q, tnsim_c128 *host, int32_t *chiL,
                                int32_t *chiR);
@@ -171,6 +175,35 @@ tnsim_status tnsim_export_lambda(tnsim_mps mps, int32_t bond, double *host, int3
    (chis[b+1] values); chis has n+1 entries, chis[0] = chis[n] = 1. */
 tnsim_status tnsim_import_state(tnsim_mps mps, const tnsim_c128 *const *sites,
                                 const double *const *lambdas, const int32_t *chis);
+
+/* ---- profiling (for measurement; off by default) ----
+   When enabled, every kernel launch of the handle is bracketed by HIP events
+   on the handle's stream and the Jacobi kernels count the work they actually
+   do.  Enabling clears the totals. */
+typedef enum {
+  TNSIM_K_THETA = 0, /* two-site merge + gate epilogue */
+  TNSIM_K_GRAM,      /* pair Gram blocks */
+  TNSIM_K_EIG,       /* 64x64 Hermitian Jacobi */
+  TNSIM_K_ROT,       /* pair rotations */
+  TNSIM_K_COLNORM,   /* column norms */
+  TNSIM_K_TRUNC,     /* sort + truncation rule */
+  TNSIM_K_WB_LEFT,   /* left-site write-back */
+  TNSIM_K_WB_RIGHT,  /* right-site write-back */
+  TNSIM_K_1Q,        /* one-qubit gates */
+  TNSIM_K_OTHER,     /* setup, sweep control */
+  TNSIM_K_COUNT
+} tnsim_kernel_class;
+
+typedef struct {
+  double ms;        /* summed event time of the launches */
+  int64_t launches; /* launch count */
+  double flops;     /* algorithmic real flops of those launches */
+  double bytes;     /* algorithmic bytes moved (operands read + results written) */
+} tnsim_kernel_stat;
+
+tnsim_status tnsim_profile(tnsim_mps mps, int32_t enable);
+/* out has TNSIM_K_COUNT entries (synchronising). */
+tnsim_status tnsim_profile_read(tnsim_mps mps, tnsim_kernel_stat *out);
 
 const char *tnsim_status_string(tnsim_status st);
 const char *tnsim_last_error(tnsim_mps mps);

@@ -238,13 +238,16 @@ static int jacobi_columns(cplx *X, int rows, int cols, double tol, int max_sweep
   if (cols < 2) return 0;
   int P = cols + (cols & 1);
   int npairs = P / 2;
-  /* Columns below 2^-200 of the matrix's squared Frobenius norm are zero for
-     every purpose of the method (far under the numerical-zero floor); pairs
-     holding one are not rotated, which keeps denormals out of the rotation. */
+  /* A column whose squared norm is below (rows * 2^-53)^2 of the matrix's
+     squared Frobenius norm is rounding noise: far under the numerical-zero
+     floor of the truncation, so its direction never reaches the result.
+     Pairs holding one are not rotated; this keeps rank-deficient matrices
+     (whose noise columns would otherwise keep rotating among themselves) and
+     denormals out of the sweeps. */
   double fro2 = 0.0;
   for (size_t i = 0; i < (size_t)rows * cols; i++)
     fro2 += creal(X[i]) * creal(X[i]) + cimag(X[i]) * cimag(X[i]);
-  const double small = fro2 * 0x1p-200;
+  const double small = fro2 * (rows * OM_EPS) * (rows * OM_EPS);
   for (int sweep = 1; sweep <= max_sweeps; sweep++) {
     int rotated = 0;
     for (int r = 0; r < P - 1; r++) {

@@ -15,12 +15,20 @@
 // ends the rounds; a gate converges after a sweep in which no pair rotated.
 // Then k_colnorm gives sigma_j^2 = ||x_j||^2 and k_trunc sorts them and
 // applies the truncation rule.
+#include <cstdlib>
+
 #include "tnsim_internal.h"
 #include "tn_complex.h"
 
 namespace tn {
 
-constexpr double SMALL_REL = 0x1p-200;  // columns below this fraction of ||X||_F^2 are zero
+// A column whose squared norm is below (rows * 2^-53)^2 ||X||_F^2 is rounding
+// noise (far under the truncation's numerical-zero floor); pairs holding one
+// are not rotated.
+__device__ __forceinline__ double small_norm2(const GateDesc &d) {
+  const double r = d.rows * 0x1p-53;
+  return d.sc->fro2 * r * r;
+}
 
 // Round-robin tournament: pair k of round r over P players (P even).
 __device__ __forceinline__ void rr_pair(int r, int k, int P, int &p, int &q) {
@@ -160,6 +168,10 @@ __global__ __launch_bounds__(256) void k_gram(const GateDesc *descs, int round, 
     }
     __syncthreads();
   }
+  if (tid == 0 && d.ctr && rend > rbeg) {
+    atomicAdd(&d.ctr[CTR_GRAM_FLOP], 8ull * (rend - rbeg) * PW * PW);
+    atomicAdd(&d.ctr[CTR_GRAM_BYTE], 16ull * (rend - rbeg) * PW + 16ull * PW * PW);
+  }
   double2 *G = d.Gp + ((size_t)kc * npairs_stride + pairIdx) * (PW * PW);
 #pragma unroll
   for (int i = 0; i < 4; i++)
@@ -167,11 +179,94 @@ __global__ __launch_bounds__(256) void k_gram(const GateDesc *descs, int round, 
     for (int j = 0; j < 4; j++) G[(ty + 16 * i) * PW + tx + 16 * j] = acc[i][j];
 }
 
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4_t mfma64(double a, double b, d4_t c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Same pair Gram on float64 matrix cores (v_mfma_f64_16x16x4): wavefront w
+// owns the 32x32 quarter (rows 32*(w/2), columns 32*(w%2)) of G as 2x2 tiles.
+__global__ __launch_bounds__(256) void k_gram_mfma(const GateDesc *descs, int round, int ksplit,
+                                                   int npairs_stride) {
+  const GateDesc &d = descs[blockIdx.y];
+  const int pairIdx = blockIdx.x / ksplit, kc = blockIdx.x % ksplit;
+  if (!d.sc->active || round >= d.nblk - 1 || pairIdx >= d.nblk / 2) return;
+  int I, J;
+  rr_pair(round, pairIdx, d.nblk, I, J);
+  int chunk = (d.rows + ksplit - 1) / ksplit;
+  chunk = (chunk + GK - 1) / GK * GK;
+  const int rbeg = kc * chunk;
+  const int rend = min(d.rows, rbeg + chunk);
+
+  __shared__ double2 Xs[GK][PW + 1];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wp = (wave >> 1) * 32, wq = (wave & 1) * 32, l16 = lane & 15, lg = lane >> 4;
+  d4_t accR[2][2], accI[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; i++)
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
+      accR[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+      accI[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+    }
+  const int lcol = tid >> 2, lr = (tid & 3) * 8;
+  const double2 *xcol = d.X + (size_t)pair_col(I, J, lcol) * d.ldx;
+  for (int r0 = rbeg; r0 < rend; r0 += GK) {
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+      int r = r0 + lr + j;
+      Xs[lr + j][lcol] = r < rend ? xcol[r] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GK; kk += 4) {
+      const int row = kk + lg;
+      double2 xa[2], xb[2];
+#pragma unroll
+      for (int t = 0; t < 2; t++) {
+        xa[t] = Xs[row][wp + t * 16 + l16];
+        xb[t] = Xs[row][wq + t * 16 + l16];
+      }
+      // G_pq = sum_r conj(x_rp) x_rq
+#pragma unroll
+      for (int ti = 0; ti < 2; ti++)
+#pragma unroll
+        for (int tj = 0; tj < 2; tj++) {
+          accR[ti][tj] = mfma64(xa[ti].x, xb[tj].x, accR[ti][tj]);
+          accR[ti][tj] = mfma64(xa[ti].y, xb[tj].y, accR[ti][tj]);
+          accI[ti][tj] = mfma64(xa[ti].x, xb[tj].y, accI[ti][tj]);
+          accI[ti][tj] = mfma64(-xa[ti].y, xb[tj].x, accI[ti][tj]);
+        }
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && d.ctr && rend > rbeg) {
+    atomicAdd(&d.ctr[CTR_GRAM_FLOP], 8ull * (rend - rbeg) * PW * PW);
+    atomicAdd(&d.ctr[CTR_GRAM_BYTE], 16ull * (rend - rbeg) * PW + 16ull * PW * PW);
+  }
+  double2 *G = d.Gp + ((size_t)kc * npairs_stride + pairIdx) * (PW * PW);
+#pragma unroll
+  for (int ti = 0; ti < 2; ti++)
+#pragma unroll
+    for (int tj = 0; tj < 2; tj++)
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        int p = wp + ti * 16 + 4 * lg + e, q = wq + tj * 16 + l16;
+        G[p * PW + q] = make_double2(accR[ti][tj][e], accI[ti][tj][e]);
+      }
+}
+
 // ---------------------------------------------------------------- 64x64 Hermitian Jacobi
 
 constexpr int LDG = PW + 1;
-constexpr int INNER_MAX_SWEEPS = 30;
 
+// Cyclic two-sided Jacobi on the pair Gram G (64x64, in LDS) with the
+// rotations accumulated in V.  A round applies the 32 disjoint rotations of
+// the round-robin pairing at once: G <- R^H G R, V <- V R.  Entries of G are
+// updated as 2x2 blocks (rows of one pair x columns of another), so every
+// entry is read and written once per round.  At most `inner_sweeps` sweeps;
+// the outer sweeps finish what a capped inner solve leaves.
 __global__ __launch_bounds__(256) void k_eig(const GateDesc *descs, int round, int ksplit,
                                              int npairs_stride) {
   const GateDesc &d = descs[blockIdx.y];
@@ -179,14 +274,15 @@ __global__ __launch_bounds__(256) void k_eig(const GateDesc *descs, int round, i
   if (!d.sc->active || round >= d.nblk - 1 || pairIdx >= d.nblk / 2) return;
   __shared__ double2 Gs[PW * LDG];
   __shared__ double2 Vs[PW * LDG];
-  __shared__ double rc[PW / 2];        // cos
-  __shared__ double2 rse[PW / 2];      // s * e^{i phi}
-  __shared__ double rt[PW / 2];        // t*|g| (diagonal shift)
+  __shared__ double rc[PW / 2];    // cos
+  __shared__ double2 rse[PW / 2];  // s * e^{i phi}
+  __shared__ double rdp[PW / 2], rdq[PW / 2];  // new diagonal entries
   __shared__ int rp[PW / 2], rq[PW / 2], ract[PW / 2];
   __shared__ int any_rot, sweep_rot, first_rot;
   const int tid = threadIdx.x;
   const double tol = d.tol;
-  const double small = d.sc->fro2 * SMALL_REL;
+  const double small = small_norm2(d);
+  unsigned nrot_local = 0;  // rotations applied by this thread (profiling)
 
   for (int e = tid; e < PW * PW; e += 256) {
     double2 s = make_double2(0.0, 0.0);
@@ -202,7 +298,7 @@ __global__ __launch_bounds__(256) void k_eig(const GateDesc *descs, int round, i
   if (tid == 0) first_rot = 0;
   __syncthreads();
 
-  for (int sweep = 0; sweep < INNER_MAX_SWEEPS; sweep++) {
+  for (int sweep = 0; sweep < d.innerSweeps; sweep++) {
     if (tid == 0) sweep_rot = 0;
     __syncthreads();
     for (int r = 0; r < PW - 1; r++) {
@@ -217,63 +313,76 @@ __global__ __launch_bounds__(256) void k_eig(const GateDesc *descs, int round, i
         double2 g = Gs[p * LDG + q];
         double ag = sqrt(cabs2(g));
         int act = 0;
+        double c = 1.0;
+        double2 se = make_double2(0.0, 0.0);
         if (a > small && b > small && ag > tol * sqrt(a) * sqrt(b)) {
           act = 1;
           double2 e = make_double2(g.x / ag, g.y / ag);  // e^{i phi}
           double zeta = (b - a) / (2.0 * ag);
           double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          double c = 1.0 / sqrt(1.0 + t * t);
-          double s = c * t;
-          rc[tid] = c;
-          rse[tid] = make_double2(s * e.x, s * e.y);
-          rt[tid] = t * ag;
+          c = 1.0 / sqrt(1.0 + t * t);
+          double sn = c * t;
+          se = make_double2(sn * e.x, sn * e.y);
+          rdp[tid] = a - t * ag;
+          rdq[tid] = b + t * ag;
           any_rot = 1;  // benign race: every writer stores 1
+          nrot_local++;
         }
+        rc[tid] = c;
+        rse[tid] = se;
         ract[tid] = act;
       }
       __syncthreads();
       if (any_rot) {
-        // columns: [g_p g_q] <- [g_p g_q] R,  R = [[c, s e^{i phi}], [-s e^{-i phi}, c]]
-        for (int task = tid; task < (PW / 2) * PW * 2; task += 256) {
-          int k = task & (PW / 2 - 1);
-          int row = (task >> 5) & (PW - 1);
-          int mat = task >> 11;  // 0: G, 1: V
-          if (!ract[k]) continue;
-          double2 *Mx = mat ? Vs : Gs;
-          int p = rp[k], q = rq[k];
-          double c = rc[k];
-          double2 se = rse[k];
-          double2 xp = Mx[row * LDG + p], xq = Mx[row * LDG + q];
-          // x_p' = c x_p - conj(se) x_q ; x_q' = se x_p + c x_q
-          double2 np_ = csub(cscale(xp, c), cmul(cconj(se), xq));
-          double2 nq_ = cadd(cmul(se, xp), cscale(xq, c));
-          Mx[row * LDG + p] = np_;
-          Mx[row * LDG + q] = nq_;
+        // R = [[c, s e^{i phi}], [-s e^{-i phi}, c]] on columns (p, q);
+        // block (row pair i, column pair j): B <- R_i^H B R_j
+        for (int task = tid; task < (PW / 2) * (PW / 2); task += 256) {
+          const int i = task >> 5, j = task & 31;
+          if (!ract[i] && !ract[j]) continue;
+          const int pi = rp[i], qi = rq[i], pj = rp[j], qj = rq[j];
+          double2 b00 = Gs[pi * LDG + pj], b01 = Gs[pi * LDG + qj];
+          double2 b10 = Gs[qi * LDG + pj], b11 = Gs[qi * LDG + qj];
+          if (ract[j]) {  // columns: [x_p x_q] R
+            const double c = rc[j];
+            const double2 se = rse[j], sec = cconj(se);
+            double2 n00 = csub(cscale(b00, c), cmul(sec, b01));
+            double2 n01 = cadd(cmul(se, b00), cscale(b01, c));
+            double2 n10 = csub(cscale(b10, c), cmul(sec, b11));
+            double2 n11 = cadd(cmul(se, b10), cscale(b11, c));
+            b00 = n00; b01 = n01; b10 = n10; b11 = n11;
+          }
+          if (ract[i]) {  // rows: R^H [row_p; row_q]
+            const double c = rc[i];
+            const double2 se = rse[i], sec = cconj(se);
+            double2 n00 = csub(cscale(b00, c), cmul(se, b10));
+            double2 n01 = csub(cscale(b01, c), cmul(se, b11));
+            double2 n10 = cadd(cmul(sec, b00), cscale(b10, c));
+            double2 n11 = cadd(cmul(sec, b01), cscale(b11, c));
+            b00 = n00; b01 = n01; b10 = n10; b11 = n11;
+          }
+          if (i == j && ract[i]) {  // the annihilated pair: exact values
+            b00 = make_double2(rdp[i], 0.0);
+            b11 = make_double2(rdq[i], 0.0);
+            b01 = make_double2(0.0, 0.0);
+            b10 = make_double2(0.0, 0.0);
+          }
+          Gs[pi * LDG + pj] = b00;
+          Gs[pi * LDG + qj] = b01;
+          Gs[qi * LDG + pj] = b10;
+          Gs[qi * LDG + qj] = b11;
         }
-        __syncthreads();
-        // rows: [g_p; g_q] <- R^H [g_p; g_q]
-        for (int task = tid; task < (PW / 2) * PW; task += 256) {
-          int k = task & (PW / 2 - 1);
-          int col = task >> 5;
-          if (!ract[k]) continue;
-          int p = rp[k], q = rq[k];
-          double c = rc[k];
-          double2 se = rse[k];
-          double2 yp = Gs[p * LDG + col], yq = Gs[q * LDG + col];
-          // row_p' = c row_p - se row_q ; row_q' = conj(se) row_p + c row_q
-          Gs[p * LDG + col] = csub(cscale(yp, c), cmul(se, yq));
-          Gs[q * LDG + col] = cadd(cmul(cconj(se), yp), cscale(yq, c));
+        // V <- V R (columns)
+        for (int task = tid; task < PW * (PW / 2); task += 256) {
+          const int j = task & 31, row = task >> 5;
+          if (!ract[j]) continue;
+          const int pj = rp[j], qj = rq[j];
+          const double c = rc[j];
+          const double2 se = rse[j];
+          double2 xp = Vs[row * LDG + pj], xq = Vs[row * LDG + qj];
+          Vs[row * LDG + pj] = csub(cscale(xp, c), cmul(cconj(se), xq));
+          Vs[row * LDG + qj] = cadd(cmul(se, xp), cscale(xq, c));
         }
-        __syncthreads();
-        if (tid < PW / 2 && ract[tid]) {
-          int p = rp[tid], q = rq[tid];
-          double a = Gs[p * LDG + p].x, b = Gs[q * LDG + q].x;
-          Gs[p * LDG + q] = make_double2(0.0, 0.0);
-          Gs[q * LDG + p] = make_double2(0.0, 0.0);
-          Gs[p * LDG + p] = make_double2(a, 0.0);
-          Gs[q * LDG + q] = make_double2(b, 0.0);
-          sweep_rot = 1;
-        }
+        if (tid == 0) sweep_rot = 1;
         __syncthreads();
       }
     }
@@ -282,6 +391,12 @@ __global__ __launch_bounds__(256) void k_eig(const GateDesc *descs, int round, i
     if (sweep == 0 && tid == 0) first_rot = cont;
     __syncthreads();
     if (!cont) break;
+  }
+  if (d.ctr && tid < 64) {
+    // fold the per-thread counts of the first wavefront, one atomic per pair
+    unsigned v = nrot_local;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (tid == 0 && v) atomicAdd(&d.ctr[CTR_EIG_ROT], (unsigned long long)v);
   }
   // An unrotated first sweep means the pair was already orthogonal.
   if (tid == 0) {
@@ -337,6 +452,11 @@ __global__ __launch_bounds__(256) void k_rot(const GateDesc *descs, int round) {
           gr < nrows ? base[(size_t)pair_col(I, J, c) * ld + gr] : make_double2(0.0, 0.0);
     }
   }
+  if (tid == 0 && d.ctr) {
+    unsigned long long nr = (unsigned long long)min(RR, nrows - r0);
+    atomicAdd(&d.ctr[CTR_ROT_FLOP], 8ull * nr * PW * PW);
+    atomicAdd(&d.ctr[CTR_ROT_BYTE], 32ull * nr * PW + 16ull * PW * PW);
+  }
   __syncthreads();
   double2 acc[4][4];
 #pragma unroll
@@ -368,15 +488,131 @@ __global__ __launch_bounds__(256) void k_rot(const GateDesc *descs, int round) {
   }
 }
 
-void launch_round(hipStream_t st, const GateDesc *d, int ng, int round, int max_pairs,
-                  int ksplit, int max_rows, int max_m, int npairs_stride) {
+// Same pair rotation on float64 matrix cores.
+__global__ __launch_bounds__(256) void k_rot_mfma(const GateDesc *descs, int round) {
+  const GateDesc &d = descs[blockIdx.y];
+  if (!d.sc->active || round >= d.nblk - 1) return;
+  const int npairs = d.nblk / 2;
+  const int xchunks = (d.rows + RR - 1) / RR;
+  const int jchunks = d.trans ? (d.m + RR - 1) / RR : 0;
+  const int per = xchunks + jchunks;
+  const int pairIdx = blockIdx.x / per, chunk = blockIdx.x % per;
+  if (pairIdx >= npairs) return;
+  if (!d.pairFlag[pairIdx]) return;
+  int I, J;
+  rr_pair(round, pairIdx, d.nblk, I, J);
+  double2 *base;
+  int ld, nrows, r0;
+  if (chunk < xchunks) {
+    base = d.X;
+    ld = d.ldx;
+    nrows = d.rows;
+    r0 = chunk * RR;
+  } else {
+    base = d.J;
+    ld = d.ldj;
+    nrows = d.m;
+    r0 = (chunk - xchunks) * RR;
+  }
+  __shared__ double2 Xs[RR * LDG];  // [row][col]
+  __shared__ double2 Vs[PW * LDG];  // [k][col]
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32, l16 = lane & 15, lg = lane >> 4;
+  const double2 *V = d.V + (size_t)pairIdx * (PW * PW);
+  for (int e = tid; e < PW * PW; e += 256) Vs[(e / PW) * LDG + e % PW] = V[e];
+  for (int e = tid; e < RR * PW; e += 256) {
+    int r = e % RR, c = e / RR;
+    int gr = r0 + r;
+    Xs[r * LDG + c] =
+        gr < nrows ? base[(size_t)pair_col(I, J, c) * ld + gr] : make_double2(0.0, 0.0);
+  }
+  if (tid == 0 && d.ctr) {
+    unsigned long long nr = (unsigned long long)min(RR, nrows - r0);
+    atomicAdd(&d.ctr[CTR_ROT_FLOP], 8ull * nr * PW * PW);
+    atomicAdd(&d.ctr[CTR_ROT_BYTE], 32ull * nr * PW + 16ull * PW * PW);
+  }
+  __syncthreads();
+  d4_t accR[2][2], accI[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; i++)
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
+      accR[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+      accI[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+    }
+#pragma unroll 4
+  for (int k0 = 0; k0 < PW; k0 += 4) {
+    const int k = k0 + lg;
+    double2 xa[2], vb[2];
+#pragma unroll
+    for (int t = 0; t < 2; t++) {
+      xa[t] = Xs[(wr + t * 16 + l16) * LDG + k];
+      vb[t] = Vs[k * LDG + wc + t * 16 + l16];
+    }
+#pragma unroll
+    for (int ti = 0; ti < 2; ti++)
+#pragma unroll
+      for (int tj = 0; tj < 2; tj++) {
+        accR[ti][tj] = mfma64(xa[ti].x, vb[tj].x, accR[ti][tj]);
+        accR[ti][tj] = mfma64(-xa[ti].y, vb[tj].y, accR[ti][tj]);
+        accI[ti][tj] = mfma64(xa[ti].x, vb[tj].y, accI[ti][tj]);
+        accI[ti][tj] = mfma64(xa[ti].y, vb[tj].x, accI[ti][tj]);
+      }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int ti = 0; ti < 2; ti++)
+#pragma unroll
+    for (int tj = 0; tj < 2; tj++)
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        int r = wr + ti * 16 + 4 * lg + e, c = wc + tj * 16 + l16;
+        Xs[r * LDG + c] = make_double2(accR[ti][tj][e], accI[ti][tj][e]);
+      }
+  __syncthreads();
+  for (int e = tid; e < RR * PW; e += 256) {
+    int r = e % RR, c = e / RR;
+    int gr = r0 + r;
+    if (gr < nrows) base[(size_t)pair_col(I, J, c) * ld + gr] = Xs[r * LDG + c];
+  }
+}
+
+int g_jacobi_mfma = -1;  // -1: read TNSIM_JACOBI_KERNELS once
+
+static bool use_mfma() {
+  if (g_jacobi_mfma < 0) {
+    const char *e = getenv("TNSIM_JACOBI_KERNELS");
+    g_jacobi_mfma = (e && e[0] == 'v') ? 0 : 1;  // "valu" selects the vector-ALU kernels
+  }
+  return g_jacobi_mfma != 0;
+}
+
+void launch_gram(hipStream_t st, const GateDesc *d, int ng, int round, int max_pairs,
+                 int ksplit, int npairs_stride) {
   if (ng <= 0) return;
-  hipLaunchKernelGGL(k_gram, dim3(max_pairs * ksplit, ng), dim3(256), 0, st, d, round, ksplit,
-                     npairs_stride);
+  if (use_mfma())
+    hipLaunchKernelGGL(k_gram_mfma, dim3(max_pairs * ksplit, ng), dim3(256), 0, st, d, round,
+                       ksplit, npairs_stride);
+  else
+    hipLaunchKernelGGL(k_gram, dim3(max_pairs * ksplit, ng), dim3(256), 0, st, d, round, ksplit,
+                       npairs_stride);
+}
+
+void launch_eig(hipStream_t st, const GateDesc *d, int ng, int round, int max_pairs, int ksplit,
+                int npairs_stride) {
+  if (ng <= 0) return;
   hipLaunchKernelGGL(k_eig, dim3(max_pairs, ng), dim3(256), 0, st, d, round, ksplit,
                      npairs_stride);
+}
+
+void launch_rot(hipStream_t st, const GateDesc *d, int ng, int round, int max_pairs,
+                int max_rows, int max_m) {
+  if (ng <= 0) return;
   int per = (max_rows + RR - 1) / RR + (max_m + RR - 1) / RR;
-  hipLaunchKernelGGL(k_rot, dim3(max_pairs * per, ng), dim3(256), 0, st, d, round);
+  if (use_mfma())
+    hipLaunchKernelGGL(k_rot_mfma, dim3(max_pairs * per, ng), dim3(256), 0, st, d, round);
+  else
+    hipLaunchKernelGGL(k_rot, dim3(max_pairs * per, ng), dim3(256), 0, st, d, round);
 }
 
 // ---------------------------------------------------------------- sort + truncate

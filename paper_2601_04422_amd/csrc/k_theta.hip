@@ -12,10 +12,70 @@
 // X = M^H when M is wide.
 #include "tnsim_internal.h"
 #include "tn_complex.h"
+#include "tn_mfma.h"
 
 namespace tn {
 
 constexpr int TM = 64, TC = 32, TK = 16;
+
+// Shared epilogue: Cs holds the merged tile theta (64 rows x 2*32 columns,
+// row stride 2*TC+1); apply the gate, write theta' and the Jacobi matrix X.
+__device__ void theta_epilogue(const GateDesc &d, int r0, int c0, double2 *Cs) {
+  constexpr int LD = 2 * TC + 1;
+  const int tid = threadIdx.x;
+  const int m = d.m, chiR = d.chiR, n = d.n;
+  for (int task = tid; task < (TM / 2) * TC; task += 256) {
+    int al = task / TC, cl = task % TC;
+    double2 v[4];
+#pragma unroll
+    for (int s = 0; s < 2; s++)
+#pragma unroll
+      for (int t = 0; t < 2; t++) v[2 * s + t] = Cs[(2 * al + s) * LD + t * TC + cl];
+#pragma unroll
+    for (int sp = 0; sp < 2; sp++)
+#pragma unroll
+      for (int tp = 0; tp < 2; tp++) {
+        double2 o = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int j = 0; j < 4; j++) cfma(o, d.g[(2 * sp + tp) * 4 + j], v[j]);
+        Cs[(2 * al + sp) * LD + tp * TC + cl] = o;
+      }
+  }
+  __syncthreads();
+  // theta' row-major (m x n), coalesced along c
+  for (int task = tid; task < TM * 2 * TC; task += 256) {
+    int r = task / (2 * TC), jj = task % (2 * TC);
+    int t = jj / TC, c = c0 + jj % TC, gr = r0 + r;
+    if (gr < m && c < chiR) {
+      size_t o = (size_t)gr * n + t * chiR + c;
+      if (d.tfp32)
+        ((float2 *)d.T)[o] = d2f(Cs[r * LD + jj]);
+      else
+        ((double2 *)d.T)[o] = Cs[r * LD + jj];
+    }
+  }
+  if (!d.trans) {
+    // X = M, column-major: coalesced along rows
+    for (int task = tid; task < TM * 2 * TC; task += 256) {
+      int r = task % TM, jj = task / TM;
+      int t = jj / TC, c = c0 + jj % TC, gr = r0 + r;
+      if (gr < m && c < chiR) {
+        double w = d.lamR ? d.lamR[c] : 1.0;
+        d.X[(size_t)(t * chiR + c) * d.ldx + gr] = cscale(Cs[r * LD + jj], w);
+      }
+    }
+  } else {
+    // X = M^H (n x m): column gr holds conj(row gr of M)
+    for (int task = tid; task < TM * 2 * TC; task += 256) {
+      int r = task / (2 * TC), jj = task % (2 * TC);
+      int t = jj / TC, c = c0 + jj % TC, gr = r0 + r;
+      if (gr < m && c < chiR) {
+        double w = d.lamR ? d.lamR[c] : 1.0;
+        d.X[(size_t)gr * d.ldx + t * chiR + c] = cscale(cconj(Cs[r * LD + jj]), w);
+      }
+    }
+  }
+}
 
 template <class S>
 __device__ __forceinline__ void theta_tile(const GateDesc &d, int r0, int c0, double2 *smem) {
@@ -70,7 +130,7 @@ __device__ __forceinline__ void theta_tile(const GateDesc &d, int r0, int c0, do
     __syncthreads();
   }
 
-  // epilogue: tile to LDS, apply the gate, write theta' and X
+  // epilogue: tile to LDS, then the shared gate/weight epilogue
   constexpr int LD = 2 * TC + 1;
   double2 *Cs = smem;  // [TM][LD]
 #pragma unroll
@@ -78,57 +138,7 @@ __device__ __forceinline__ void theta_tile(const GateDesc &d, int r0, int c0, do
 #pragma unroll
     for (int j = 0; j < 4; j++) Cs[(ty + 16 * i) * LD + tx + 16 * j] = acc[i][j];
   __syncthreads();
-  for (int task = tid; task < (TM / 2) * TC; task += 256) {
-    int al = task / TC, cl = task % TC;
-    double2 v[4];
-#pragma unroll
-    for (int s = 0; s < 2; s++)
-#pragma unroll
-      for (int t = 0; t < 2; t++) v[2 * s + t] = Cs[(2 * al + s) * LD + t * TC + cl];
-#pragma unroll
-    for (int sp = 0; sp < 2; sp++)
-#pragma unroll
-      for (int tp = 0; tp < 2; tp++) {
-        double2 o = make_double2(0.0, 0.0);
-#pragma unroll
-        for (int j = 0; j < 4; j++) cfma(o, d.g[(2 * sp + tp) * 4 + j], v[j]);
-        Cs[(2 * al + sp) * LD + tp * TC + cl] = o;
-      }
-  }
-  __syncthreads();
-  // theta' row-major (m x n), coalesced along c
-  for (int task = tid; task < TM * 2 * TC; task += 256) {
-    int r = task / (2 * TC), jj = task % (2 * TC);
-    int t = jj / TC, c = c0 + jj % TC, gr = r0 + r;
-    if (gr < m && c < chiR) {
-      size_t o = (size_t)gr * n + t * chiR + c;
-      if (d.tfp32)
-        ((float2 *)d.T)[o] = d2f(Cs[r * LD + jj]);
-      else
-        ((double2 *)d.T)[o] = Cs[r * LD + jj];
-    }
-  }
-  if (!d.trans) {
-    // X = M, column-major: coalesced along rows
-    for (int task = tid; task < TM * 2 * TC; task += 256) {
-      int r = task % TM, jj = task / TM;
-      int t = jj / TC, c = c0 + jj % TC, gr = r0 + r;
-      if (gr < m && c < chiR) {
-        double w = d.lamR ? d.lamR[c] : 1.0;
-        d.X[(size_t)(t * chiR + c) * d.ldx + gr] = cscale(Cs[r * LD + jj], w);
-      }
-    }
-  } else {
-    // X = M^H (n x m): column gr holds conj(row gr of M)
-    for (int task = tid; task < TM * 2 * TC; task += 256) {
-      int r = task / (2 * TC), jj = task % (2 * TC);
-      int t = jj / TC, c = c0 + jj % TC, gr = r0 + r;
-      if (gr < m && c < chiR) {
-        double w = d.lamR ? d.lamR[c] : 1.0;
-        d.X[(size_t)gr * d.ldx + t * chiR + c] = cscale(cconj(Cs[r * LD + jj]), w);
-      }
-    }
-  }
+  theta_epilogue(d, r0, c0, Cs);
 }
 
 __global__ __launch_bounds__(256) void k_theta_fp64(const GateDesc *descs) {
@@ -142,10 +152,95 @@ __global__ __launch_bounds__(256) void k_theta_fp64(const GateDesc *descs) {
     theta_tile<float2>(d, r0, c0, smem);
 }
 
+// Same tile and epilogue on matrix cores: operands rounded to complex64 and
+// multiplied in the selected split mode with float32 accumulation.
+template <int MODE, class S>
+__device__ void theta_tile_mfma(const GateDesc &d, int r0, int c0, double2 *smem) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const S *A0 = (const S *)d.A0;
+  const S *A1 = (const S *)d.A1;
+  const int m = d.m, chiM = d.chiM, chiR = d.chiR, n = d.n;
+  float2 *Af = reinterpret_cast<float2 *>(smem);  // [64][TILE_LD]
+  float2 *Bf = Af + 64 * TILE_LD;                 // [64][TILE_LD]
+  f32x4_t accR[2][2], accI[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; i++)
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
+      accR[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+      accI[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    }
+  for (int k0 = 0; k0 < chiM; k0 += TILE_K) {
+    {  // A: row r, 4 consecutive k
+      int r = tid >> 2, kq = (tid & 3) * 4, gr = r0 + r;
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        int gk = k0 + kq + j;
+        double2 v = make_double2(0.0, 0.0);
+        if (gr < m && gk < chiM) v = cload(A0 + (size_t)gr * chiM + gk);
+        Af[r * TILE_LD + kq + j] = d2f(v);
+      }
+    }
+    {  // B^T: column jj (t half, c), 4 consecutive columns of one k row
+      int kk = tid >> 4, jq = (tid & 15) * 4, gk = k0 + kk;
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        int jj = jq + j, t = jj >> 5, c = c0 + (jj & 31);
+        double2 v = make_double2(0.0, 0.0);
+        if (gk < chiM && c < chiR) v = cload(A1 + (size_t)gk * n + t * chiR + c);
+        Bf[jj * TILE_LD + kk] = d2f(v);
+      }
+    }
+    __syncthreads();
+    cmma_step<MODE>(Af, Bf, wave, lane, accR, accI);
+    __syncthreads();
+  }
+  constexpr int LD = 2 * TC + 1;
+  double2 *Cs = smem;
+#pragma unroll
+  for (int ti = 0; ti < 2; ti++)
+#pragma unroll
+    for (int tj = 0; tj < 2; tj++)
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        int row, col;
+        cmma_coord(wave, lane, ti, tj, e, row, col);
+        Cs[row * LD + col] = make_double2((double)accR[ti][tj][e], (double)accI[ti][tj][e]);
+      }
+  __syncthreads();
+  theta_epilogue(d, r0, c0, Cs);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_theta_mfma(const GateDesc *descs) {
+  const GateDesc &d = descs[blockIdx.z];
+  int r0 = blockIdx.x * TM, c0 = blockIdx.y * TC;
+  if (r0 >= d.m || c0 >= d.chiR) return;
+  __shared__ double2 smem[TM * (2 * TC + 1)];
+  if (d.storage == 0)
+    theta_tile_mfma<MODE, double2>(d, r0, c0, smem);
+  else
+    theta_tile_mfma<MODE, float2>(d, r0, c0, smem);
+}
+
+void launch_theta_mfma(hipStream_t st, const GateDesc *d, int ng, int precision, int max_m,
+                       int max_chiR) {
+  dim3 grid((max_m + TM - 1) / TM, (max_chiR + TC - 1) / TC, ng);
+  if (precision == MODE_F32)
+    hipLaunchKernelGGL(k_theta_mfma<MODE_F32>, grid, dim3(256), 0, st, d);
+  else if (precision == MODE_BF16X3)
+    hipLaunchKernelGGL(k_theta_mfma<MODE_BF16X3>, grid, dim3(256), 0, st, d);
+  else
+    hipLaunchKernelGGL(k_theta_mfma<MODE_BF16X6>, grid, dim3(256), 0, st, d);
+}
+
 void launch_theta(hipStream_t st, const GateDesc *d, int ng, int precision, int max_m,
                   int max_chiR) {
   if (ng <= 0) return;
-  (void)precision;
+  if (precision != 0) {
+    launch_theta_mfma(st, d, ng, precision, max_m, max_chiR);
+    return;
+  }
   dim3 grid((max_m + TM - 1) / TM, (max_chiR + TC - 1) / TC, ng);
   hipLaunchKernelGGL(k_theta_fp64, grid, dim3(256), 0, st, d);
 }

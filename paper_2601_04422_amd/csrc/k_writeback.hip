@@ -10,6 +10,7 @@
 // divided out.
 #include "tnsim_internal.h"
 #include "tn_complex.h"
+#include "tn_mfma.h"
 
 namespace tn {
 
@@ -137,14 +138,96 @@ __global__ __launch_bounds__(256) void k_wb_right(const GateDesc *descs) {
   }
 }
 
-void launch_writeback(hipStream_t st, const GateDesc *d, int ng, int precision, int max_m,
-                      int max_k, int max_n) {
+void launch_wb_left(hipStream_t st, const GateDesc *d, int ng, int max_m, int max_k) {
   if (ng <= 0) return;
-  (void)precision;
   hipLaunchKernelGGL(k_wb_left, dim3((max_m + 63) / 64, (max_k + 63) / 64, ng), dim3(256), 0, st,
                      d);
-  hipLaunchKernelGGL(k_wb_right, dim3((max_k + 63) / 64, (max_n + 63) / 64, ng), dim3(256), 0,
-                     st, d);
+}
+
+// A_{i+1}' = (1/N) U_k^H theta' on matrix cores (theta' stored complex64).
+template <int MODE, class S>
+__device__ void wb_right_tile_mfma(const GateDesc &d, int k, int j0, int c0, float2 *Af,
+                                   float2 *Bf) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const float2 *T = (const float2 *)d.T;
+  const int m = d.m, n = d.n;
+  f32x4_t accR[2][2], accI[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; i++)
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
+      accR[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+      accI[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    }
+  const int aj = tid >> 2, ar = (tid & 3) * 4, gj = j0 + aj;
+  int colA = 0;
+  double invA = 1.0;
+  if (gj < k) {
+    colA = d.perm[gj];
+    invA = d.trans ? 1.0 : 1.0 / sqrt(d.sig2[colA]);
+  }
+  const int bk = tid >> 4, bc = (tid & 15) * 4;
+  for (int r0 = 0; r0 < m; r0 += TILE_K) {
+#pragma unroll
+    for (int q = 0; q < 4; q++) {  // A[j][r] = conj(u_j[r])
+      int gr = r0 + ar + q;
+      double2 v = make_double2(0.0, 0.0);
+      if (gj < k && gr < m) v = cconj(left_vec(d, gr, colA, invA));
+      Af[aj * TILE_LD + ar + q] = d2f(v);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++) {  // B^T[c][r] = theta'[r][c]
+      int gr = r0 + bk, gc = c0 + bc + q;
+      float2 v = make_float2(0.f, 0.f);
+      if (gr < m && gc < n) v = T[(size_t)gr * n + gc];
+      Bf[(bc + q) * TILE_LD + bk] = v;
+    }
+    __syncthreads();
+    cmma_step<MODE>(Af, Bf, wave, lane, accR, accI);
+    __syncthreads();
+  }
+  const double invN = 1.0 / d.sc->N;
+  S *A1 = (S *)d.A1;
+#pragma unroll
+  for (int ti = 0; ti < 2; ti++)
+#pragma unroll
+    for (int tj = 0; tj < 2; tj++)
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        int row, col;
+        cmma_coord(wave, lane, ti, tj, e, row, col);
+        int gjo = j0 + row, gc = c0 + col;
+        if (gjo < k && gc < n)
+          cstore(A1 + (size_t)gjo * n + gc,
+                 make_double2((double)accR[ti][tj][e] * invN, (double)accI[ti][tj][e] * invN));
+      }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_wb_right_mfma(const GateDesc *descs) {
+  const GateDesc &d = descs[blockIdx.z];
+  const int k = d.sc->k;
+  int j0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
+  if (j0 >= k || c0 >= d.n) return;
+  __shared__ float2 Af[64 * TILE_LD], Bf[64 * TILE_LD];
+  if (d.storage == 0)
+    wb_right_tile_mfma<MODE, double2>(d, k, j0, c0, Af, Bf);
+  else
+    wb_right_tile_mfma<MODE, float2>(d, k, j0, c0, Af, Bf);
+}
+
+void launch_wb_right(hipStream_t st, const GateDesc *d, int ng, int precision, int max_k,
+                     int max_n) {
+  if (ng <= 0) return;
+  dim3 grid((max_k + 63) / 64, (max_n + 63) / 64, ng);
+  if (precision == 0)
+    hipLaunchKernelGGL(k_wb_right, grid, dim3(256), 0, st, d);
+  else if (precision == MODE_F32)
+    hipLaunchKernelGGL(k_wb_right_mfma<MODE_F32>, grid, dim3(256), 0, st, d);
+  else if (precision == MODE_BF16X3)
+    hipLaunchKernelGGL(k_wb_right_mfma<MODE_BF16X3>, grid, dim3(256), 0, st, d);
+  else
+    hipLaunchKernelGGL(k_wb_right_mfma<MODE_BF16X6>, grid, dim3(256), 0, st, d);
 }
 
 }  // namespace tn

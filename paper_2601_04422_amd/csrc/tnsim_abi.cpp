@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -33,7 +34,7 @@ struct Layout {
   size_t x_off = 0, j_off = 0, t_off = 0, v_off = 0, pf_off = 0, sig_off = 0, perm_off = 0,
          sc_off = 0;  // within a slot
   size_t gp_off = 0;  // pooled pair-Gram partials
-  size_t desc_off = 0, d1_off = 0;
+  size_t desc_off = 0, d1_off = 0, ctr_off = 0;
   size_t e0_off = 0, e1_off = 0, f_off = 0, f2_off = 0, va_off = 0, vb_off = 0;
   size_t total = 0;
 };
@@ -118,6 +119,8 @@ Layout make_layout(const tnsim_config &c) {
   off = align_up(off + sizeof(GateDesc) * L.nslots);
   L.d1_off = off;
   off = align_up(off + sizeof(Gate1Desc) * n);
+  L.ctr_off = off;
+  off = align_up(off + sizeof(unsigned long long) * CTR_COUNT);
   const size_t ee = sizeof(double2) * (size_t)maxbond * maxbond;
   const size_t ff = sizeof(double2) * (size_t)maxbond * 2 * maxbond;
   L.e0_off = off;
@@ -159,6 +162,19 @@ struct tnsim_mps_s {
   std::string err;
   char *pin = nullptr;
   size_t pin_bytes = 0;
+  // profiling
+  struct Rec {
+    int cls;
+    hipEvent_t a, b;
+    double flops, bytes;
+  };
+  bool prof = false;
+  int inner_sweeps = 2;
+  int64_t sw_gates = 0, sw_sum = 0;
+  int sw_max = 0;
+  std::vector<hipEvent_t> evpool;
+  std::vector<Rec> pending;
+  tnsim_kernel_stat kstat[TNSIM_K_COUNT] = {};
 
   template <class T>
   T *at(size_t off) const {
@@ -202,6 +218,53 @@ tnsim_status check_handle(tnsim_mps h) {
   if (!h) return TNSIM_E_ARG;
   if (h->poisoned) return TNSIM_E_DEVICE;
   return TNSIM_OK;
+}
+
+// ---- profiling helpers: events bracket each launch when enabled
+hipEvent_t ev_get(tnsim_mps h) {
+  if (!h->evpool.empty()) {
+    hipEvent_t e = h->evpool.back();
+    h->evpool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+struct ProfScope {
+  tnsim_mps h;
+  int cls;
+  double flops, bytes;
+  hipEvent_t a = nullptr;
+  ProfScope(tnsim_mps h_, int cls_, double fl = 0.0, double by = 0.0)
+      : h(h_), cls(cls_), flops(fl), bytes(by) {
+    if (h->prof) {
+      a = ev_get(h);
+      if (a) hipEventRecord(a, h->stream);
+    }
+  }
+  ~ProfScope() {
+    if (!h->prof || !a) return;
+    hipEvent_t b = ev_get(h);
+    if (!b) return;
+    hipEventRecord(b, h->stream);
+    h->pending.push_back({cls, a, b, flops, bytes});
+  }
+};
+
+// After a stream synchronisation: fold finished event pairs into the totals.
+void prof_drain(tnsim_mps h) {
+  for (auto &r : h->pending) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) h->kstat[r.cls].ms += ms;
+    h->kstat[r.cls].launches += 1;
+    h->kstat[r.cls].flops += r.flops;
+    h->kstat[r.cls].bytes += r.bytes;
+    h->evpool.push_back(r.a);
+    h->evpool.push_back(r.b);
+  }
+  h->pending.clear();
 }
 
 tnsim_status init_state(tnsim_mps h) {
@@ -248,6 +311,7 @@ tnsim_status run_2q_batch(tnsim_mps h, const Pending *gates, int ng) {
     d.chiMax = c.chi_max;
     d.storage = c.storage;
     d.tfp32 = c.precision != TNSIM_FP64;
+    d.innerSweeps = h->inner_sweeps;
     d.tol = c.jacobi_tol > 0 ? c.jacobi_tol : std::max(d.rows, 16) * 0x1p-53;
     d.cutoff = c.cutoff;
     d.A0 = h->site(i);
@@ -283,59 +347,129 @@ tnsim_status run_2q_batch(tnsim_mps h, const Pending *gates, int ng) {
   double2 *gp = h->at<double2>(L.gp_off);
   for (int g = 0; g < ng; g++) D[g].Gp = gp + (size_t)g * ksplit * L.npairs_max * PW * PW;
 
+  unsigned long long *ctr = h->prof ? h->at<unsigned long long>(L.ctr_off) : nullptr;
+  double theta_flop = 0.0, theta_byte = 0.0, colnorm_byte = 0.0;
+  for (int g = 0; g < ng; g++) {
+    D[g].ctr = ctr;
+    const GateDesc &d = D[g];
+    const double eb = c.storage == 0 ? 16.0 : 8.0, tb = d.tfp32 ? 8.0 : 16.0;
+    theta_flop += 8.0 * d.m * d.chiM * d.n + 32.0 * d.m * d.n;
+    theta_byte += eb * ((double)d.m * d.chiM + (double)d.chiM * d.n) + (tb + 16.0) * d.m * d.n;
+    colnorm_byte += 16.0 * d.rows * d.cols;
+  }
+
   GateDesc *ddev = h->at<GateDesc>(L.desc_off);
   HIPCHK(h, hipStreamSynchronize(h->stream));  // the staging buffer is free
+  prof_drain(h);
   memcpy(h->pin, D.data(), sizeof(GateDesc) * ng);
   HIPCHK(h, hipMemcpyAsync(ddev, h->pin, sizeof(GateDesc) * ng, hipMemcpyHostToDevice,
                            h->stream));
   hipStream_t st = h->stream;
-  launch_setup_slots(st, ddev, ng, maxColsPad, 0);
-  launch_theta(st, ddev, ng, c.precision, maxM, maxChiR);
-  launch_colnorm(st, ddev, ng, maxColsPad);
-  launch_gate_init(st, ddev, ng);
+  {
+    ProfScope p(h, TNSIM_K_OTHER);
+    launch_setup_slots(st, ddev, ng, maxColsPad, 0);
+  }
+  {
+    ProfScope p(h, TNSIM_K_THETA, theta_flop, theta_byte);
+    launch_theta(st, ddev, ng, c.precision, maxM, maxChiR);
+  }
+  {
+    ProfScope p(h, TNSIM_K_COLNORM, 0.0, colnorm_byte);
+    launch_colnorm(st, ddev, ng, maxColsPad);
+  }
+  {
+    ProfScope p(h, TNSIM_K_OTHER);
+    launch_gate_init(st, ddev, ng);
+  }
   LAUNCHCHK(h, "theta");
 
   const int max_sweeps = c.jacobi_max_sweeps > 0 ? c.jacobi_max_sweeps : 60;
   SlotScalars *sc_pin = reinterpret_cast<SlotScalars *>(h->pin + align_up(sizeof(GateDesc) * L.nslots));
   bool converged = false;
   int sweeps = 0;
+  std::vector<int> done_at(ng, 0);
   for (int sweep = 1; sweep <= max_sweeps; sweep++) {
-    launch_begin_sweep(st, ddev, ng);
-    for (int r = 0; r < maxNblk - 1; r++)
-      launch_round(st, ddev, ng, r, maxPairs, ksplit, maxRows, maxMtrans, L.npairs_max);
+    {
+      ProfScope p(h, TNSIM_K_OTHER);
+      launch_begin_sweep(st, ddev, ng);
+    }
+    for (int r = 0; r < maxNblk - 1; r++) {
+      {
+        ProfScope p(h, TNSIM_K_GRAM);
+        launch_gram(st, ddev, ng, r, maxPairs, ksplit, L.npairs_max);
+      }
+      {
+        ProfScope p(h, TNSIM_K_EIG);
+        launch_eig(st, ddev, ng, r, maxPairs, ksplit, L.npairs_max);
+      }
+      {
+        ProfScope p(h, TNSIM_K_ROT);
+        launch_rot(st, ddev, ng, r, maxPairs, maxRows, maxMtrans);
+      }
+    }
     LAUNCHCHK(h, "jacobi round");
     for (int g = 0; g < ng; g++)
       HIPCHK(h, hipMemcpyAsync(&sc_pin[g], D[g].sc, sizeof(SlotScalars), hipMemcpyDeviceToHost, st));
     HIPCHK(h, hipStreamSynchronize(st));
+    prof_drain(h);
     sweeps = sweep;
     bool any = false;
-    for (int g = 0; g < ng; g++) any |= sc_pin[g].rot != 0;
+    for (int g = 0; g < ng; g++) {
+      any |= sc_pin[g].rot != 0;
+      if (!sc_pin[g].rot && !done_at[g]) done_at[g] = sweep;
+    }
     if (!any) {
       converged = true;
       break;
     }
   }
   h->last_sweeps = std::max(h->last_sweeps, sweeps);
+  for (int g = 0; g < ng; g++) {
+    int sw = done_at[g] ? done_at[g] : sweeps;
+    h->sw_gates += 1;
+    h->sw_sum += sw;
+    h->sw_max = std::max(h->sw_max, sw);
+  }
   if (!converged) {
     h->err = "Jacobi SVD did not converge within jacobi_max_sweeps";
     return TNSIM_E_NOCONV;
   }
-  launch_colnorm(st, ddev, ng, maxColsPad);
-  launch_trunc(st, ddev, ng, h->dims_dev());
+  {
+    ProfScope p(h, TNSIM_K_COLNORM, 0.0, colnorm_byte);
+    launch_colnorm(st, ddev, ng, maxColsPad);
+  }
+  {
+    ProfScope p(h, TNSIM_K_TRUNC);
+    launch_trunc(st, ddev, ng, h->dims_dev());
+  }
   LAUNCHCHK(h, "truncate");
   for (int g = 0; g < ng; g++)
     HIPCHK(h, hipMemcpyAsync(&sc_pin[g], D[g].sc, sizeof(SlotScalars), hipMemcpyDeviceToHost, st));
   HIPCHK(h, hipStreamSynchronize(st));
+  prof_drain(h);
   int maxK = 0;
+  double wbl_byte = 0.0, wbr_flop = 0.0, wbr_byte = 0.0;
   for (int g = 0; g < ng; g++) {
-    const SlotScalars &s = sc_pin[g];
-    h->dims[D[g].i + 1] = s.k;
-    h->sum_eps += s.eps;
-    h->prod_keep *= (1.0 - s.eps);
+    const SlotScalars &sv = sc_pin[g];
+    const GateDesc &d = D[g];
+    h->dims[d.i + 1] = sv.k;
+    h->sum_eps += sv.eps;
+    h->prod_keep *= (1.0 - sv.eps);
     h->n2q += 1;
-    maxK = std::max(maxK, s.k);
+    maxK = std::max(maxK, sv.k);
+    const double eb = c.storage == 0 ? 16.0 : 8.0, tb = d.tfp32 ? 8.0 : 16.0;
+    wbl_byte += (16.0 + eb) * d.m * sv.k;
+    wbr_flop += 8.0 * sv.k * d.m * d.n;
+    wbr_byte += 16.0 * d.m * sv.k + tb * (double)d.m * d.n + eb * (double)sv.k * d.n;
   }
-  launch_writeback(st, ddev, ng, c.precision, maxM, maxK, maxN);
+  {
+    ProfScope p(h, TNSIM_K_WB_LEFT, 0.0, wbl_byte);
+    launch_wb_left(st, ddev, ng, maxM, maxK);
+  }
+  {
+    ProfScope p(h, TNSIM_K_WB_RIGHT, wbr_flop, wbr_byte);
+    launch_wb_right(st, ddev, ng, c.precision, maxK, maxN);
+  }
   LAUNCHCHK(h, "write-back");
   return TNSIM_OK;
 }
@@ -367,10 +501,16 @@ tnsim_status run_1q(tnsim_mps h, const std::vector<std::pair<int, const tnsim_c1
   }
   Gate1Desc *ddev = h->at<Gate1Desc>(h->L.d1_off);
   HIPCHK(h, hipStreamSynchronize(h->stream));
+  prof_drain(h);
   memcpy(h->pin, D.data(), sizeof(Gate1Desc) * D.size());
   HIPCHK(h, hipMemcpyAsync(ddev, h->pin, sizeof(Gate1Desc) * D.size(), hipMemcpyHostToDevice,
                            h->stream));
-  launch_apply_1q(h->stream, ddev, (int)D.size(), maxe);
+  double by = 0.0;
+  for (auto &d : D) by += 2.0 * (h->L.storage == 0 ? 16.0 : 8.0) * 2.0 * d.chiL * d.chiR;
+  {
+    ProfScope p(h, TNSIM_K_1Q, 0.0, by);
+    launch_apply_1q(h->stream, ddev, (int)D.size(), maxe);
+  }
   LAUNCHCHK(h, "apply_1q");
   return TNSIM_OK;
 }
@@ -482,6 +622,10 @@ tnsim_status tnsim_mps_create(const tnsim_config *cfg, void *dev_arena, size_t a
   h->arena_bytes = arena_bytes;
   h->stream = (hipStream_t)hip_stream;
   h->device = dev;
+  if (const char *e = getenv("TNSIM_INNER_SWEEPS")) {
+    int v = atoi(e);
+    if (v >= 1 && v <= 60) h->inner_sweeps = v;
+  }
   const Layout &LL = h->L;
   h->pin_bytes = align_up(sizeof(GateDesc) * LL.nslots) + align_up(sizeof(SlotScalars) * LL.nslots) +
                  align_up(sizeof(Gate1Desc) * LL.n) + 4096;
@@ -512,6 +656,8 @@ tnsim_status tnsim_mps_create(const tnsim_config *cfg, void *dev_arena, size_t a
 tnsim_status tnsim_mps_destroy(tnsim_mps h) {
   if (!h) return TNSIM_E_ARG;
   if (!h->poisoned) hipStreamSynchronize(h->stream);
+  prof_drain(h);
+  for (hipEvent_t e : h->evpool) hipEventDestroy(e);
   if (h->pin) hipHostFree(h->pin);
   delete h;
   return TNSIM_OK;
@@ -720,6 +866,16 @@ tnsim_status tnsim_last_sweeps(tnsim_mps h, int32_t *sweeps) {
   return TNSIM_OK;
 }
 
+tnsim_status tnsim_sweep_stats(tnsim_mps h, int64_t *gates, int64_t *sweeps_sum,
+                               int32_t *sweeps_max) {
+  tnsim_status s = check_handle(h);
+  if (s != TNSIM_OK) return s;
+  if (gates) *gates = h->sw_gates;
+  if (sweeps_sum) *sweeps_sum = h->sw_sum;
+  if (sweeps_max) *sweeps_max = h->sw_max;
+  return TNSIM_OK;
+}
+
 tnsim_status tnsim_export_site(tnsim_mps h, int32_t q, tnsim_c128 *host, int32_t *chiL,
                                int32_t *chiR) {
   tnsim_status s = check_handle(h);
@@ -788,6 +944,44 @@ tnsim_status tnsim_import_state(tnsim_mps h, const tnsim_c128 *const *sites,
                         hipMemcpyHostToDevice));
   HIPCHK(h, hipMemcpy(h->dims_dev(), chis, sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice));
   h->dims.assign(chis, chis + n + 1);
+  return TNSIM_OK;
+}
+
+tnsim_status tnsim_profile(tnsim_mps h, int32_t enable) {
+  tnsim_status s = check_handle(h);
+  if (s != TNSIM_OK) return s;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  prof_drain(h);
+  if (enable) {
+    for (auto &k : h->kstat) k = tnsim_kernel_stat{0.0, 0, 0.0, 0.0};
+    h->sw_gates = h->sw_sum = 0;
+    h->sw_max = 0;
+    launch_fill_zero(h->stream, h->at<void>(h->L.ctr_off),
+                     align_up(sizeof(unsigned long long) * CTR_COUNT, 16));
+    LAUNCHCHK(h, "profile");
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+  }
+  h->prof = enable != 0;
+  return TNSIM_OK;
+}
+
+tnsim_status tnsim_profile_read(tnsim_mps h, tnsim_kernel_stat *out) {
+  tnsim_status s = check_handle(h);
+  if (s != TNSIM_OK) return s;
+  if (!out) return TNSIM_E_ARG;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  prof_drain(h);
+  unsigned long long ctr[CTR_COUNT];
+  HIPCHK(h, hipMemcpy(ctr, h->at<void>(h->L.ctr_off), sizeof ctr, hipMemcpyDeviceToHost));
+  for (int k = 0; k < TNSIM_K_COUNT; k++) out[k] = h->kstat[k];
+  out[TNSIM_K_GRAM].flops = (double)ctr[CTR_GRAM_FLOP];
+  out[TNSIM_K_GRAM].bytes = (double)ctr[CTR_GRAM_BYTE];
+  // one 2x2 rotation updates two columns and two rows of G and two columns of
+  // V (64 entries each); an entry update is 2 complex multiply-adds = 16 flops
+  out[TNSIM_K_EIG].flops = (double)ctr[CTR_EIG_ROT] * 6.0 * PW * 16.0;
+  out[TNSIM_K_EIG].bytes = 0.0;
+  out[TNSIM_K_ROT].flops = (double)ctr[CTR_ROT_FLOP];
+  out[TNSIM_K_ROT].bytes = (double)ctr[CTR_ROT_BYTE];
   return TNSIM_OK;
 }
 

@@ -39,7 +39,7 @@ struct GateDesc {
   int chiMax;
   int storage;           // 0 = complex128 sites, 1 = complex64 sites
   int tfp32;             // theta' stored as complex64 (mixed modes)
-  int pad0;
+  int innerSweeps;       // sweep cap of the 64x64 pair solve
   double tol;            // relative off-diagonal tolerance
   double cutoff;         // discarded-weight cutoff
   void *A0, *A1;         // site i, site i+1
@@ -52,8 +52,13 @@ struct GateDesc {
   double *sig2;          // column norms squared
   int *perm;             // columns sorted by descending norm
   SlotScalars *sc;
-  double2 g[16];         // the 4x4 gate
+  unsigned long long *ctr;  // work counters (see CTR_*), may be nullptr
+  double2 g[16];            // the 4x4 gate
 };
+
+// Device work counters, accumulated by the Jacobi kernels (one atomic per
+// workgroup): algorithmic flops and bytes of what each launch really did.
+enum { CTR_GRAM_FLOP = 0, CTR_GRAM_BYTE, CTR_EIG_ROT, CTR_ROT_FLOP, CTR_ROT_BYTE, CTR_COUNT };
 
 struct Gate1Desc {
   void *A;
@@ -77,11 +82,16 @@ void launch_theta(hipStream_t st, const GateDesc *d, int ng, int precision, int 
 void launch_colnorm(hipStream_t st, const GateDesc *d, int ng, int max_cols);
 void launch_gate_init(hipStream_t st, const GateDesc *d, int ng);
 void launch_begin_sweep(hipStream_t st, const GateDesc *d, int ng);
-void launch_round(hipStream_t st, const GateDesc *d, int ng, int round, int max_pairs,
-                  int ksplit, int max_rows, int max_m, int npairs_stride);
+void launch_gram(hipStream_t st, const GateDesc *d, int ng, int round, int max_pairs,
+                 int ksplit, int npairs_stride);
+void launch_eig(hipStream_t st, const GateDesc *d, int ng, int round, int max_pairs, int ksplit,
+                int npairs_stride);
+void launch_rot(hipStream_t st, const GateDesc *d, int ng, int round, int max_pairs,
+                int max_rows, int max_m);
 void launch_trunc(hipStream_t st, const GateDesc *d, int ng, int *dims_dev);
-void launch_writeback(hipStream_t st, const GateDesc *d, int ng, int precision, int max_m,
-                      int max_k, int max_n);
+void launch_wb_left(hipStream_t st, const GateDesc *d, int ng, int max_m, int max_k);
+void launch_wb_right(hipStream_t st, const GateDesc *d, int ng, int precision, int max_k,
+                     int max_n);
 
 // Readouts
 void launch_gemm_nn(hipStream_t st, int M, int N, int K, const double2 *A, int lda,

@@ -32,6 +32,10 @@ class Config(C.Structure):
                 ("max_layer_gates", C.c_int32)]
 
 
+KERNEL_CLASSES = ["theta", "gram", "eig", "rot", "colnorm", "trunc", "wb_left", "wb_right",
+                  "one_qubit", "other"]
+KSTAT_DTYPE = np.dtype([("ms", "<f8"), ("launches", "<i8"), ("flops", "<f8"), ("bytes", "<f8")])
+
 GATE_DTYPE = np.dtype([("q0", "<i4"), ("q1", "<i4"), ("m", "<c16", (16,))], align=True)
 assert GATE_DTYPE.itemsize == 264
 
@@ -56,10 +60,14 @@ _SIGS = {
     "tnsim_truncation_stats": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                          C.POINTER(C.c_int64)]),
     "tnsim_last_sweeps": (C.c_int, [_P, C.POINTER(C.c_int32)]),
+    "tnsim_sweep_stats": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                    C.POINTER(C.c_int32)]),
     "tnsim_export_site": (C.c_int, [_P, C.c_int32, _P, C.POINTER(C.c_int32),
                                     C.POINTER(C.c_int32)]),
     "tnsim_export_lambda": (C.c_int, [_P, C.c_int32, _P, C.POINTER(C.c_int32)]),
     "tnsim_import_state": (C.c_int, [_P, _P, _P, _P]),
+    "tnsim_profile": (C.c_int, [_P, C.c_int32]),
+    "tnsim_profile_read": (C.c_int, [_P, _P]),
     "tnsim_status_string": (C.c_char_p, [C.c_int]),
     "tnsim_last_error": (C.c_char_p, [_P]),
 }
@@ -242,6 +250,22 @@ class MPS:
         self._chk(lib().tnsim_last_sweeps(self._h, C.byref(sw)), "last_sweeps")
         return {"sum_eps": se.value, "prod_keep": pk.value, "n2q": n2.value,
                 "last_sweeps": sw.value}
+
+    def sweep_stats(self) -> dict:
+        g, sm = C.c_int64(), C.c_int64()
+        mx = C.c_int32()
+        self._chk(lib().tnsim_sweep_stats(self._h, C.byref(g), C.byref(sm), C.byref(mx)),
+                  "sweep_stats")
+        return {"gates": g.value, "mean": sm.value / max(g.value, 1), "max": mx.value}
+
+    def profile(self, enable: bool) -> None:
+        self._chk(lib().tnsim_profile(self._h, 1 if enable else 0), "profile")
+
+    def profile_read(self) -> dict:
+        out = np.zeros(len(KERNEL_CLASSES), dtype=KSTAT_DTYPE)
+        self._chk(lib().tnsim_profile_read(self._h, out.ctypes.data), "profile_read")
+        return {k: {f: out[i][f].item() for f in KSTAT_DTYPE.names}
+                for i, k in enumerate(KERNEL_CLASSES)}
 
     def site(self, q: int) -> np.ndarray:
         a, b = C.c_int32(), C.c_int32()

@@ -184,3 +184,36 @@ def test_errors_leave_state_unchanged(T):
     assert list(nc.bond_dims()) == [1] * (n - 1)
     # the handle stays usable after NOCONV
     assert abs(nc.amplitude([0] * n) - 1) < 1e-15
+
+
+# ---------------------------------------------------------------- mixed precision paths
+
+@pytest.mark.parametrize("precision,bound", [("f32acc", 1e-9), ("bf16x6", 1e-9), ("bf16x3", 1e-7)])
+def test_mixed_precision_vs_oracle(T, precision, bound):
+    """Complex64 storage with the matrix-core contraction / write-back against
+    the float64 oracle.  Tolerance: state fidelity error <= 1e-6 (the
+    requirement), with the bound expected from the arithmetic (float32-level
+    operands, ~1e-7 relative per gate for f32acc/bf16x6, ~2^-16 for bf16x3)."""
+    n, depth, chi = 16, 12, 24
+    layers = W.brickwork_haar(n, depth, 4242)
+    m = T.MPS(n, chi, 1e-10, precision=precision, storage="c64")
+    m.run_layers(layers)
+    o = O.OracleMPS(n, chi, 1e-10)
+    o.run_layers(layers)
+    err = 1 - _oracle_fid(m, o)
+    assert err <= 1e-6
+    assert err <= bound, err
+    for q in (0, 7, 15):
+        s = ["I"] * n
+        s[q] = "Z"
+        assert abs(m.expect("".join(s)) - o.expect("".join(s))) < 1e-5
+
+
+def test_mixed_untruncated_amplitudes(T):
+    cfg = W.config_small()
+    m = T.MPS(cfg.n, cfg.chi_max, cfg.cutoff, precision="bf16x6", storage="c64")
+    m.run_layers(cfg.layers)
+    ref = statevector(cfg.n, cfg.gates())
+    got = gpu_statevector(m)
+    assert np.max(np.abs(got - ref)) < 1e-6
+    assert 1 - fidelity_dense(got, ref) < 1e-10
