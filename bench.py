@@ -154,7 +154,10 @@ def main():
         total2q += len(layers[l][2])
         run_layer_batched(mix, layers[l])
         per_layer.append(time.perf_counter() - tl)
-        log(f"mixed layer {l}: {per_layer[-1]:.2f} s")
+        lb = mix.last_batch()
+        worst = lb[np.argsort(-lb[:, 5])[:4]]
+        log(f"mixed layer {l}: {per_layer[-1]:.2f} s; sweeps mean {lb[:, 5].mean():.1f}, "
+            f"slowest (i,chiL,chiM,chiR,k,sweeps): {worst.tolist()}")
     torch.cuda.synchronize()
     mix_s = time.perf_counter() - t0
     prof = mix.profile_read()

@@ -167,6 +167,10 @@ tnsim_status tnsim_last_sweeps(tnsim_mps mps, int32_t *sweeps);
    last tnsim_profile(mps, 1). */
 tnsim_status tnsim_sweep_stats(tnsim_mps mps, int64_t *gates, int64_t *sweeps_sum,
                                int32_t *sweeps_max);
+/* Per two-qubit gate of the last apply call, 6 entries: left site i, chiL,
+   chiM, chiR (before the gate), kept k, Jacobi sweeps.  Writes at most
+   max_gates records to out; *n receives the record count. */
+tnsim_status tnsim_last_batch(tnsim_mps mps, int32_t *out, int32_t max_gates, int32_t *n);
 /* Site q as complex128 (chiL*2*chiR entries); host may be NULL to query dims. */
 tnsim_status tnsim_export_site(tnsim_mps mps, int32_t q, tnsim_c128 *host, int32_t *chiL,
                                int32_t *chiR);
@@ -175,6 +179,33 @@ tnsim_status tnsim_export_lambda(tnsim_mps mps, int32_t bond, double *host, int3
    (chis[b+1] values); chis has n+1 entries, chis[0] = chis[n] = 1. */
 tnsim_status tnsim_import_state(tnsim_mps mps, const tnsim_c128 *const *sites,
                                 const double *const *lambdas, const int32_t *chis);
+
+/* ---- gradients of a Pauli-sum loss with respect to rotation angles ----
+   Loss L = sum_t coeffs[t] <psi|P_t|psi>/<psi|psi>, psi = circuit |0...0>.
+   Gate g of `circuit` with param_of_gate[g] = p >= 0 is the rotation
+   R_P(angles[p]) = exp(-i angles[p] P/2) about axis rot_axis[p] (0=X, 1=Y,
+   2=Z) on qubit q0 (its matrix field is ignored); other gates use their
+   matrix.  The adjoint is hand-written: the reverse sweep recomputes each
+   segment [segment_start[s], segment_start[s+1]) from a checkpoint of the
+   state at its start and back-propagates through every gate, including the
+   truncated SVD (Lorentzian-broadened 1/(sigma_j^2 - sigma_l^2) over the full
+   left basis; the loss is gauge invariant, so the phase term vanishes).
+   Requires precision TNSIM_FP64.  The caller provides a device workspace of
+   tnsim_grad_workspace_bytes(cfg, n_segments, max gates per segment,
+   n_params) bytes (256-byte aligned) that must stay valid until
+   tnsim_backward returns.  The forward resets the state to |0...0>; after
+   either call the handle holds the circuit's final state. */
+size_t tnsim_grad_workspace_bytes(const tnsim_config *cfg, int32_t n_segments,
+                                  int32_t max_segment_gates, int32_t n_params);
+tnsim_status tnsim_forward_checkpointed(tnsim_mps mps, void *dev_ws, size_t ws_bytes,
+                                        const tnsim_gate *circuit, int32_t n_gates,
+                                        const int32_t *param_of_gate, const int32_t *rot_axis,
+                                        const double *angles, int32_t n_params,
+                                        const int32_t *segment_start, int32_t n_segments,
+                                        const char *const *paulis, const double *coeffs,
+                                        int32_t n_terms, double *loss);
+/* grad_angles[p] = dloss * dL/d angles[p] (host array of n_params). */
+tnsim_status tnsim_backward(tnsim_mps mps, double dloss, double *grad_angles);
 
 /* ---- profiling (for measurement; off by default) ----
    When enabled, every kernel launch of the handle is bracketed by HIP events

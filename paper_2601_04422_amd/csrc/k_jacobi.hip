@@ -181,6 +181,10 @@ __global__ __launch_bounds__(256) void k_gram(const GateDesc *descs, int round, 
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
+// v_mfma_f64_16x16x4f64 operand layout (lane l = 0..63): A[l%16][l/16],
+// B[l/16][l%16]; result entry v of lane l is D[l/16 + 4v][l%16] (rows
+// strided by 4, unlike the float32 16x16 results).
+
 __device__ __forceinline__ d4_t mfma64(double a, double b, d4_t c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
@@ -252,7 +256,7 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const GateDesc *descs, int ro
     for (int tj = 0; tj < 2; tj++)
 #pragma unroll
       for (int e = 0; e < 4; e++) {
-        int p = wp + ti * 16 + 4 * lg + e, q = wq + tj * 16 + l16;
+        int p = wp + ti * 16 + lg + 4 * e, q = wq + tj * 16 + l16;
         G[p * PW + q] = make_double2(accR[ti][tj][e], accI[ti][tj][e]);
       }
 }
@@ -566,7 +570,7 @@ __global__ __launch_bounds__(256) void k_rot_mfma(const GateDesc *descs, int rou
     for (int tj = 0; tj < 2; tj++)
 #pragma unroll
       for (int e = 0; e < 4; e++) {
-        int r = wr + ti * 16 + 4 * lg + e, c = wc + tj * 16 + l16;
+        int r = wr + ti * 16 + lg + 4 * e, c = wc + tj * 16 + l16;
         Xs[r * LDG + c] = make_double2(accR[ti][tj][e], accI[ti][tj][e]);
       }
   __syncthreads();

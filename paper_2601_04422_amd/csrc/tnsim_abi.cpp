@@ -145,6 +145,43 @@ struct Pending {
   double2 g[16];
 };
 
+// One gate of the segment being differentiated, recorded during recompute.
+struct GradRec {
+  int kind = 0;  // 1 or 2 qubits
+  int q = 0;     // site (1q) or left site (2q)
+  int chiL = 0, chiM = 0, chiR = 0, k = 0;
+  double N = 1.0;
+  int param = -1, axis = -1;
+  bool has_lam = false;
+  Mat4 u{};
+  Mat16 g{};
+  size_t off = 0;  // record slot in the workspace
+};
+
+// Workspace layout and circuit of the last tnsim_forward_checkpointed call.
+struct GradState {
+  bool ready = false;
+  char *ws = nullptr;
+  size_t ws_bytes = 0;
+  int n = 0, n_params = 0, n_seg = 0, max_seg = 0;
+  std::vector<tnsim_gate> gates;
+  std::vector<int> param, axis, seg_start;
+  std::vector<double> angles;
+  std::vector<std::string> paulis;
+  std::vector<double> coeffs;
+  std::vector<std::vector<int>> ckpt_dims;
+  // workspace offsets
+  size_t state_bytes = 0, ckpt0 = 0;
+  std::vector<size_t> st_site, st_lam;  // offsets inside one checkpoint
+  std::vector<size_t> cot_site, cot_lam;
+  size_t envL = 0, envR = 0, env_stride = 0, envF = 0, envF2 = 0;
+  size_t tmp0 = 0, tmp_stride = 0, lam2 = 0, sbar = 0, dots = 0, ubar = 0, grad = 0;
+  size_t rec0 = 0, rec_stride = 0, rec_a = 0, rec_b = 0, rec_lam = 0, rec_T = 0, rec_J = 0,
+         rec_sig = 0, rec_perm = 0;
+  size_t total = 0;
+  double loss = 0.0;
+};
+
 }  // namespace
 
 struct tnsim_mps_s {
@@ -170,6 +207,8 @@ struct tnsim_mps_s {
   };
   bool prof = false;
   int inner_sweeps = 2;
+  std::vector<int32_t> last_batch;  // 6 ints per two-qubit gate of the last apply call
+  GradState grad;
   int64_t sw_gates = 0, sw_sum = 0;
   int sw_max = 0;
   std::vector<hipEvent_t> evpool;
@@ -285,7 +324,7 @@ tnsim_status init_state(tnsim_mps h) {
 }
 
 // Run one batch of two-qubit gates (at most nslots) through the whole path.
-tnsim_status run_2q_batch(tnsim_mps h, const Pending *gates, int ng) {
+tnsim_status run_2q_batch(tnsim_mps h, const Pending *gates, int ng, bool force_trans = false) {
   const Layout &L = h->L;
   const tnsim_config &c = h->cfg;
   std::vector<GateDesc> D(ng);
@@ -301,9 +340,11 @@ tnsim_status run_2q_batch(tnsim_mps h, const Pending *gates, int ng) {
     d.chiR = h->dims[i + 2];
     d.m = 2 * d.chiL;
     d.n = 2 * d.chiR;
-    d.trans = d.n > d.m;
-    d.rows = std::max(d.m, d.n);
-    d.cols = std::min(d.m, d.n);
+    // X = M^H (with the left vectors accumulated in J) when M is wide, or
+    // always when the caller needs the full left basis (the adjoint)
+    d.trans = force_trans || d.n > d.m;
+    d.rows = d.trans ? d.n : d.m;
+    d.cols = d.trans ? d.m : d.n;
     d.ldx = pad_to(d.rows, 4);
     d.ldj = pad_to(d.m, 4);
     d.colsPad = pad_to(d.cols, PW);
@@ -426,6 +467,8 @@ tnsim_status run_2q_batch(tnsim_mps h, const Pending *gates, int ng) {
   h->last_sweeps = std::max(h->last_sweeps, sweeps);
   for (int g = 0; g < ng; g++) {
     int sw = done_at[g] ? done_at[g] : sweeps;
+    h->last_batch.insert(h->last_batch.end(),
+                         {D[g].i, D[g].chiL, D[g].chiM, D[g].chiR, 0, sw});
     h->sw_gates += 1;
     h->sw_sum += sw;
     h->sw_max = std::max(h->sw_max, sw);
@@ -449,9 +492,11 @@ tnsim_status run_2q_batch(tnsim_mps h, const Pending *gates, int ng) {
   prof_drain(h);
   int maxK = 0;
   double wbl_byte = 0.0, wbr_flop = 0.0, wbr_byte = 0.0;
+  const size_t rec0 = h->last_batch.size() - 6 * (size_t)ng;
   for (int g = 0; g < ng; g++) {
     const SlotScalars &sv = sc_pin[g];
     const GateDesc &d = D[g];
+    h->last_batch[rec0 + 6 * g + 4] = sv.k;
     h->dims[d.i + 1] = sv.k;
     h->sum_eps += sv.eps;
     h->prod_keep *= (1.0 - sv.eps);
@@ -593,6 +638,408 @@ tnsim_status transfer(tnsim_mps h, tnsim_mps bra, tnsim_mps ket, const double2 *
 
 }  // namespace
 
+// ============================================================== gradients
+// Reverse-mode derivative of a Pauli-sum loss with respect to rotation angles.
+// The forward pass checkpoints the state at segment starts; the backward pass
+// walks the segments in reverse, recomputes each one from its checkpoint while
+// recording every gate's inputs and SVD, and then runs the adjoint of each gate
+// in reverse order.  All tensor arithmetic runs in the kernels of
+// k_adjoint.hip and the forward kernels.
+
+namespace {
+
+constexpr double ADJ_ETA = 1e-24;  // Lorentzian broadening of 1/(lambda_j - lambda_l)
+
+GradState grad_layout(const Layout &L, int n_seg, int max_seg, int n_params) {
+  GradState G;
+  const int n = L.n;
+  const size_t elem = L.elem;
+  int maxbond = 1;
+  for (int b = 0; b < n - 1; b++) maxbond = std::max(maxbond, L.bondcap[b]);
+  const size_t cmax = 2 * (size_t)maxbond;
+  size_t off = 0;
+  // one checkpoint
+  size_t st = 0;
+  G.st_site.resize(n);
+  G.st_lam.resize(std::max(n - 1, 0));
+  for (int q = 0; q < n; q++) {
+    G.st_site[q] = st;
+    st = align_up(st + L.site_cap[q] * elem);
+  }
+  for (int b = 0; b < n - 1; b++) {
+    G.st_lam[b] = st;
+    st = align_up(st + sizeof(double) * L.bondcap[b]);
+  }
+  G.state_bytes = st;
+  G.ckpt0 = off;
+  off = align_up(off + st * (n_seg + 1));
+  G.cot_site.resize(n);
+  for (int q = 0; q < n; q++) {
+    G.cot_site[q] = off;
+    off = align_up(off + L.site_cap[q] * sizeof(double2));
+  }
+  G.cot_lam.resize(std::max(n - 1, 0));
+  for (int b = 0; b < n - 1; b++) {
+    G.cot_lam[b] = off;
+    off = align_up(off + sizeof(double) * L.bondcap[b]);
+  }
+  G.env_stride = align_up(sizeof(double2) * (size_t)maxbond * maxbond);
+  G.envL = off;
+  off += G.env_stride * (n + 1);
+  G.envR = off;
+  off += G.env_stride * (n + 1);
+  G.envF = off;
+  off = align_up(off + sizeof(double2) * (size_t)maxbond * 2 * maxbond);
+  G.envF2 = off;
+  off = align_up(off + sizeof(double2) * (size_t)maxbond * 2 * maxbond);
+  G.tmp_stride = align_up(sizeof(double2) * cmax * cmax);
+  G.tmp0 = off;
+  off += G.tmp_stride * 12;
+  G.lam2 = off;
+  off = align_up(off + sizeof(double) * cmax);
+  G.sbar = off;
+  off = align_up(off + sizeof(double) * cmax);
+  G.dots = off;
+  off = align_up(off + 64);
+  G.ubar = off;
+  off = align_up(off + 64);
+  G.grad = off;
+  off = align_up(off + sizeof(double) * std::max(n_params, 1));
+  // per-gate records
+  const size_t site_max = (size_t)maxbond * 2 * maxbond;
+  size_t r = 0;
+  G.rec_a = r;
+  r = align_up(r + site_max * elem);
+  G.rec_b = r;
+  r = align_up(r + site_max * elem);
+  G.rec_lam = r;
+  r = align_up(r + sizeof(double) * maxbond);
+  G.rec_T = r;
+  r = align_up(r + sizeof(double2) * cmax * cmax);
+  G.rec_J = r;
+  r = align_up(r + sizeof(double2) * cmax * cmax);
+  G.rec_sig = r;
+  r = align_up(r + sizeof(double) * cmax);
+  G.rec_perm = r;
+  r = align_up(r + sizeof(int) * cmax);
+  G.rec_stride = r;
+  G.rec0 = off;
+  off = align_up(off + r * std::max(max_seg, 1));
+  G.total = off;
+  G.n = n;
+  G.n_seg = n_seg;
+  G.max_seg = max_seg;
+  G.n_params = n_params;
+  return G;
+}
+
+Mat4 rotation(int axis, double t) {
+  const double c = cos(0.5 * t), sn = sin(0.5 * t);
+  Mat4 u;
+  // R_P(t) = cos(t/2) I - i sin(t/2) P
+  if (axis == 0) {
+    u.v[0] = make_double2(c, 0); u.v[1] = make_double2(0, -sn);
+    u.v[2] = make_double2(0, -sn); u.v[3] = make_double2(c, 0);
+  } else if (axis == 1) {
+    u.v[0] = make_double2(c, 0); u.v[1] = make_double2(-sn, 0);
+    u.v[2] = make_double2(sn, 0); u.v[3] = make_double2(c, 0);
+  } else {
+    u.v[0] = make_double2(c, -sn); u.v[1] = make_double2(0, 0);
+    u.v[2] = make_double2(0, 0); u.v[3] = make_double2(c, sn);
+  }
+  return u;
+}
+
+GemmArgs gemm(int M, int N, int K, const void *A, long long sai, long long sak, int ac, int ast,
+              const void *B, long long sbk, long long sbj, int bc, int bst, double2 *C,
+              long long sci, long long scj, double2 alpha, int acc) {
+  GemmArgs g;
+  g.M = M; g.N = N; g.K = K;
+  g.A = A; g.sa_i = sai; g.sa_k = sak; g.a_conj = ac; g.a_storage = ast;
+  g.B = B; g.sb_k = sbk; g.sb_j = sbj; g.b_conj = bc; g.b_storage = bst;
+  g.C = C; g.sc_i = sci; g.sc_j = scj; g.alpha = alpha; g.accumulate = acc;
+  return g;
+}
+
+inline double2 cr(double x) { return make_double2(x, 0.0); }
+
+tnsim_status save_ckpt(tnsim_mps h, int idx) {
+  GradState &G = h->grad;
+  char *base = G.ws + G.ckpt0 + G.state_bytes * idx;
+  const int n = h->L.n;
+  for (int q = 0; q < n; q++)
+    HIPCHK(h, hipMemcpyAsync(base + G.st_site[q], h->site(q),
+                             (size_t)h->dims[q] * 2 * h->dims[q + 1] * h->L.elem,
+                             hipMemcpyDeviceToDevice, h->stream));
+  for (int b = 0; b < n - 1; b++)
+    HIPCHK(h, hipMemcpyAsync(base + G.st_lam[b], h->lam(b), sizeof(double) * h->dims[b + 1],
+                             hipMemcpyDeviceToDevice, h->stream));
+  G.ckpt_dims[idx] = h->dims;
+  return TNSIM_OK;
+}
+
+tnsim_status restore_ckpt(tnsim_mps h, int idx) {
+  GradState &G = h->grad;
+  const char *base = G.ws + G.ckpt0 + G.state_bytes * idx;
+  const int n = h->L.n;
+  h->dims = G.ckpt_dims[idx];
+  for (int q = 0; q < n; q++)
+    HIPCHK(h, hipMemcpyAsync(h->site(q), base + G.st_site[q],
+                             (size_t)h->dims[q] * 2 * h->dims[q + 1] * h->L.elem,
+                             hipMemcpyDeviceToDevice, h->stream));
+  for (int b = 0; b < n - 1; b++)
+    HIPCHK(h, hipMemcpyAsync(h->lam(b), base + G.st_lam[b], sizeof(double) * h->dims[b + 1],
+                             hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  memcpy(h->pin, h->dims.data(), sizeof(int32_t) * (n + 1));
+  HIPCHK(h, hipMemcpyAsync(h->dims_dev(), h->pin, sizeof(int32_t) * (n + 1),
+                           hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return TNSIM_OK;
+}
+
+// Apply gate g of the stored circuit (forward).  With rec != nullptr the
+// gate's inputs and SVD are recorded for the adjoint.
+tnsim_status grad_apply(tnsim_mps h, int gi, GradRec *rec) {
+  GradState &G = h->grad;
+  const tnsim_gate &gt = G.gates[gi];
+  hipStream_t st = h->stream;
+  if (gt.q1 < 0) {
+    const int q = gt.q0;
+    Mat4 u;
+    if (G.param[gi] >= 0)
+      u = rotation(G.axis[gi], G.angles[G.param[gi]]);
+    else
+      for (int e = 0; e < 4; e++) u.v[e] = to_d2(gt.m[e]);
+    if (rec) {
+      rec->kind = 1;
+      rec->q = q;
+      rec->chiL = h->dims[q];
+      rec->chiR = h->dims[q + 1];
+      rec->param = G.param[gi];
+      rec->axis = G.axis[gi];
+      rec->u = u;
+      HIPCHK(h, hipMemcpyAsync(G.ws + rec->off + G.rec_a, h->site(q),
+                               (size_t)rec->chiL * 2 * rec->chiR * h->L.elem,
+                               hipMemcpyDeviceToDevice, st));
+    }
+    tnsim_c128 um[4];
+    for (int e = 0; e < 4; e++) um[e] = tnsim_c128{u.v[e].x, u.v[e].y};
+    return run_1q(h, {{q, um}});
+  }
+  Pending p;
+  orient(gt.q0, gt.q1, gt.m, p);
+  const int i = p.i, n = h->L.n;
+  if (rec) {
+    rec->kind = 2;
+    rec->q = i;
+    rec->chiL = h->dims[i];
+    rec->chiM = h->dims[i + 1];
+    rec->chiR = h->dims[i + 2];
+    rec->has_lam = (i + 1 <= n - 2);
+    for (int e = 0; e < 16; e++) rec->g.v[e] = p.g[e];
+    char *r = G.ws + rec->off;
+    HIPCHK(h, hipMemcpyAsync(r + G.rec_a, h->site(i),
+                             (size_t)rec->chiL * 2 * rec->chiM * h->L.elem,
+                             hipMemcpyDeviceToDevice, st));
+    HIPCHK(h, hipMemcpyAsync(r + G.rec_b, h->site(i + 1),
+                             (size_t)rec->chiM * 2 * rec->chiR * h->L.elem,
+                             hipMemcpyDeviceToDevice, st));
+    if (rec->has_lam)
+      HIPCHK(h, hipMemcpyAsync(r + G.rec_lam, h->lam(i + 1), sizeof(double) * rec->chiR,
+                               hipMemcpyDeviceToDevice, st));
+  }
+  tnsim_status s = run_2q_batch(h, &p, 1, /*force_trans=*/true);
+  if (s != TNSIM_OK) return s;
+  if (rec) {
+    const Layout &L = h->L;
+    const SlotScalars *sc_pin =
+        reinterpret_cast<const SlotScalars *>(h->pin + align_up(sizeof(GateDesc) * L.nslots));
+    rec->k = sc_pin[0].k;
+    rec->N = sc_pin[0].N;
+    const int m = 2 * rec->chiL, nn = 2 * rec->chiR, ldj = pad_to(m, 4);
+    char *sl = h->slot(0), *r = G.ws + rec->off;
+    HIPCHK(h, hipMemcpyAsync(r + G.rec_T, sl + L.t_off, sizeof(double2) * (size_t)m * nn,
+                             hipMemcpyDeviceToDevice, st));
+    HIPCHK(h, hipMemcpy2DAsync(r + G.rec_J, sizeof(double2) * m, sl + L.j_off,
+                               sizeof(double2) * ldj, sizeof(double2) * m, m,
+                               hipMemcpyDeviceToDevice, st));
+    HIPCHK(h, hipMemcpyAsync(r + G.rec_sig, sl + L.sig_off, sizeof(double) * m,
+                             hipMemcpyDeviceToDevice, st));
+    launch_sort_all(st, (const double *)(sl + L.sig_off), m, (int *)(r + G.rec_perm));
+    LAUNCHCHK(h, "record");
+  }
+  return TNSIM_OK;
+}
+
+// One left transfer step: E' (rb x rk) = B^H [P] (E (lb x lk) K) for site q.
+void env_left(tnsim_mps h, int q, const double2 *E, double2 *Eo, const double2 *P) {
+  GradState &G = h->grad;
+  hipStream_t st = h->stream;
+  const int lb = h->dims[q], rb = h->dims[q + 1], sto = h->L.storage;
+  double2 *F = (double2 *)(G.ws + G.envF), *F2 = (double2 *)(G.ws + G.envF2);
+  launch_gemm_gen(st, gemm(lb, 2 * rb, lb, E, lb, 1, 0, 0, h->site(q), 2 * rb, 1, 0, sto, F,
+                           2 * rb, 1, cr(1.0), 0));
+  const double2 *Fp = F;
+  if (P) {
+    launch_pauli_phys(st, F, F2, lb, rb, P[0], P[1], P[2], P[3]);
+    Fp = F2;
+  }
+  launch_gemm_gen(st, gemm(rb, rb, 2 * lb, h->site(q), 1, rb, 1, sto, Fp, rb, 1, 0, 0, Eo, rb, 1,
+                           cr(1.0), 0));
+}
+
+// One right transfer step: R' (lb x lb)[a, a'] = sum conj(A[a,s,b]) P[s,s'] A[a',s',b'] R[b,b'].
+void env_right(tnsim_mps h, int q, const double2 *R, double2 *Ro, const double2 *P) {
+  GradState &G = h->grad;
+  hipStream_t st = h->stream;
+  const int lb = h->dims[q], rb = h->dims[q + 1], sto = h->L.storage;
+  double2 *F = (double2 *)(G.ws + G.envF), *F2 = (double2 *)(G.ws + G.envF2);
+  // G1[(a',s'), b] = sum_b' A[(a',s'), b'] R[b, b']
+  launch_gemm_gen(st, gemm(2 * lb, rb, rb, h->site(q), rb, 1, 0, sto, R, 1, rb, 0, 0, F, rb, 1,
+                           cr(1.0), 0));
+  const double2 *Fp = F;
+  if (P) {
+    launch_pauli_phys(st, F, F2, lb, rb, P[0], P[1], P[2], P[3]);
+    Fp = F2;
+  }
+  // R'[a, a'] = sum_{(s,b)} conj(A[a, (s,b)]) G2[a', (s,b)]
+  launch_gemm_gen(st, gemm(lb, lb, 2 * rb, h->site(q), 2 * rb, 1, 1, sto, Fp, 1, 2 * rb, 0, 0, Ro,
+                           lb, 1, cr(1.0), 0));
+}
+
+// Abar_q += w * (d <psi|P|psi> / d conj(A_q)) for every site, P given per site
+// (identity where isI).
+tnsim_status loss_cotangent_term(tnsim_mps h, const double2 *tab, const char *isI, double w) {
+  GradState &G = h->grad;
+  hipStream_t st = h->stream;
+  const int n = h->L.n, sto = h->L.storage;
+  auto envL = [&](int q) { return (double2 *)(G.ws + G.envL + G.env_stride * q); };
+  auto envR = [&](int q) { return (double2 *)(G.ws + G.envR + G.env_stride * q); };
+  launch_fill_c(st, envL(0), 1, cr(1.0));
+  for (int q = 0; q < n; q++) env_left(h, q, envL(q), envL(q + 1), isI[q] ? nullptr : tab + 4 * q);
+  launch_fill_c(st, envR(n), 1, cr(1.0));
+  for (int q = n - 1; q >= 0; q--)
+    env_right(h, q, envR(q + 1), envR(q), isI[q] ? nullptr : tab + 4 * q);
+  double2 *F = (double2 *)(G.ws + G.envF), *F2 = (double2 *)(G.ws + G.envF2);
+  for (int q = 0; q < n; q++) {
+    const int lb = h->dims[q], rb = h->dims[q + 1];
+    launch_gemm_gen(st, gemm(lb, 2 * rb, lb, envL(q), lb, 1, 0, 0, h->site(q), 2 * rb, 1, 0, sto,
+                             F, 2 * rb, 1, cr(1.0), 0));
+    const double2 *Fp = F;
+    if (!isI[q]) {
+      const double2 *P = tab + 4 * q;
+      launch_pauli_phys(st, F, F2, lb, rb, P[0], P[1], P[2], P[3]);
+      Fp = F2;
+    }
+    double2 *Ab = (double2 *)(G.ws + G.cot_site[q]);
+    // Abar[(a,s), b] += w sum_b' Fp[(a,s), b'] R[b, b']
+    launch_gemm_gen(st, gemm(2 * lb, rb, rb, Fp, rb, 1, 0, 0, envR(q + 1), 1, rb, 0, 0, Ab, rb, 1,
+                             cr(w), 1));
+  }
+  LAUNCHCHK(h, "loss cotangent");
+  return TNSIM_OK;
+}
+
+// Adjoint of one recorded two-qubit gate: consumes the cotangents of
+// (A_i', A_{i+1}', lambda_i') and produces those of (A_i, A_{i+1}) and the
+// contribution to lambda_{i+1}.
+tnsim_status adjoint_2q(tnsim_mps h, const GradRec &R) {
+  GradState &G = h->grad;
+  hipStream_t st = h->stream;
+  const int i = R.q, chiL = R.chiL, chiM = R.chiM, chiR = R.chiR, k = R.k;
+  const int m = 2 * chiL, n = 2 * chiR, sto = h->L.storage;
+  const double N = R.N;
+  const char *rb = G.ws + R.off;
+  const double2 *T = (const double2 *)(rb + G.rec_T);
+  const double2 *J = (const double2 *)(rb + G.rec_J);
+  const double *sig = (const double *)(rb + G.rec_sig);
+  const int *perm = (const int *)(rb + G.rec_perm);
+  const double *lamR = R.has_lam ? (const double *)(rb + G.rec_lam) : nullptr;
+  auto tmp = [&](int t) { return (double2 *)(G.ws + G.tmp0 + G.tmp_stride * t); };
+  double2 *U = tmp(0), *Ub = tmp(1), *Tb = tmp(2), *Ap = tmp(3), *Cm = tmp(4), *Ab = tmp(5),
+          *Y = tmp(6), *Hb = tmp(7), *Hs = tmp(8), *Mw = tmp(9), *Mb = tmp(10);
+  double *lam2 = (double *)(G.ws + G.lam2), *sbar = (double *)(G.ws + G.sbar),
+         *dots = (double *)(G.ws + G.dots);
+  double2 *cotA = (double2 *)(G.ws + G.cot_site[i]);      // m x k  (A_i')
+  double2 *cotB = (double2 *)(G.ws + G.cot_site[i + 1]);  // k x n  (A_{i+1}')
+  double *lamb_i = (double *)(G.ws + G.cot_lam[i]);       // k      (lambda_i')
+  double *lamb_r = R.has_lam ? (double *)(G.ws + G.cot_lam[i + 1]) : nullptr;
+
+  // full left basis in descending order
+  launch_gather_basis(st, J, m, perm, sig, U, lam2, m);
+  // Ubar = Abar_i' + theta' Abar_{i+1}'^H / N        (m x k, row-major)
+  HIPCHK(h, hipMemcpyAsync(Ub, cotA, sizeof(double2) * (size_t)m * k, hipMemcpyDeviceToDevice, st));
+  launch_gemm_gen(st, gemm(m, k, n, T, n, 1, 0, 0, cotB, 1, n, 1, 0, Ub, k, 1, cr(1.0 / N), 1));
+  // theta'_bar = U_k Abar_{i+1}' / N                   (m x n, row-major)
+  launch_gemm_gen(st, gemm(m, n, k, U, 1, m, 0, 0, cotB, n, 1, 0, 0, Tb, n, 1, cr(1.0 / N), 0));
+  // A_{i+1}' = U_k^H theta' / N (recomputed) and Re<Abar_{i+1}', A_{i+1}'>
+  launch_gemm_gen(st, gemm(k, n, m, U, m, 1, 1, 0, T, n, 1, 0, 0, Ap, n, 1, cr(1.0 / N), 0));
+  launch_fill_zero(st, dots, 64);
+  launch_dot_re(st, cotB, Ap, 0, (size_t)k * n, dots);
+  // sigma_bar from lambda' = sigma/N and N
+  launch_sigma_bar(st, dots, lamb_i, lam2, N, k, sbar);
+  // C = U^H Ubar (m x k col-major); Abar = F o C (+ diagonal sigma terms)
+  launch_gemm_gen(st, gemm(m, k, m, U, m, 1, 1, 0, Ub, k, 1, 0, 0, Cm, 1, m, cr(1.0), 0));
+  launch_svd_adj_mid(st, Cm, Ab, lam2, sbar, m, k, ADJ_ETA);
+  // Hbar = U Abar U_k^H (m x m col-major), Hs = Hbar + Hbar^H
+  launch_gemm_gen(st, gemm(m, k, m, U, 1, m, 0, 0, Ab, 1, m, 0, 0, Y, 1, m, cr(1.0), 0));
+  launch_gemm_gen(st, gemm(m, m, k, Y, 1, m, 0, 0, U, m, 1, 1, 0, Hb, 1, m, cr(1.0), 0));
+  launch_herm_sum(st, Hb, Hs, m);
+  // Mbar = Hs M with M = theta' diag(lambda_{i+1})      (m x n row-major)
+  launch_weight_apply(st, T, Mw, lamR, m, chiR);
+  launch_gemm_gen(st, gemm(m, n, m, Hs, 1, m, 0, 0, Mw, n, 1, 0, 0, Mb, n, 1, cr(1.0), 0));
+  // theta'_bar += Mbar diag(lambda); lambda_bar_{i+1} += 2 Re sum conj(Mbar) theta'
+  launch_weight_adj(st, Mb, T, Tb, lamR, lamb_r, m, chiR);
+  // theta_bar = G^H theta'_bar on (s, t)
+  launch_gate_adj(st, Tb, chiL, chiR, R.g);
+  // Abar_i = theta_bar A_{i+1}^H (m x chiM); Abar_{i+1} = A_i^H theta_bar (chiM x n)
+  const void *A0 = rb + G.rec_a, *A1 = rb + G.rec_b;
+  launch_gemm_gen(st, gemm(m, chiM, n, Tb, n, 1, 0, 0, A1, 1, n, 1, sto, cotA, chiM, 1, cr(1.0), 0));
+  launch_gemm_gen(st, gemm(chiM, n, m, A0, 1, chiM, 1, sto, Tb, n, 1, 0, 0, cotB, n, 1, cr(1.0), 0));
+  // the old lambda_i is overwritten by this gate: nothing later depends on it
+  launch_fill_zero(st, lamb_i, align_up(sizeof(double) * h->L.bondcap[i], 16));
+  LAUNCHCHK(h, "adjoint 2q");
+  return TNSIM_OK;
+}
+
+tnsim_status adjoint_1q(tnsim_mps h, const GradRec &R) {
+  GradState &G = h->grad;
+  hipStream_t st = h->stream;
+  double *ubar = (double *)(G.ws + G.ubar);
+  launch_fill_zero(st, ubar, 64);
+  launch_1q_adj(st, (double2 *)(G.ws + G.cot_site[R.q]), G.ws + R.off + G.rec_a, h->L.storage,
+                R.chiL, R.chiR, R.u, ubar);
+  if (R.param >= 0)
+    launch_angle_grad(st, ubar, R.u, R.axis, (double *)(G.ws + G.grad) + R.param);
+  LAUNCHCHK(h, "adjoint 1q");
+  return TNSIM_OK;
+}
+
+tnsim_status pauli_table(const char *p, int n, std::vector<double2> &tab, std::vector<char> &isI) {
+  static const double2 PM[4][4] = {{{1, 0}, {0, 0}, {0, 0}, {1, 0}},
+                                   {{0, 0}, {1, 0}, {1, 0}, {0, 0}},
+                                   {{0, 0}, {0, -1}, {0, 1}, {0, 0}},
+                                   {{1, 0}, {0, 0}, {0, 0}, {-1, 0}}};
+  tab.assign(4 * n, make_double2(0, 0));
+  isI.assign(n, 1);
+  for (int q = 0; q < n; q++) {
+    int k;
+    switch (p[q]) {
+      case 'I': k = 0; break;
+      case 'X': k = 1; break;
+      case 'Y': k = 2; break;
+      case 'Z': k = 3; break;
+      default: return TNSIM_E_ARG;
+    }
+    isI[q] = k == 0;
+    for (int e = 0; e < 4; e++) tab[4 * q + e] = PM[k][e];
+  }
+  return TNSIM_OK;
+}
+
+}  // namespace
+
 // ============================================================== C ABI
 
 extern "C" {
@@ -684,6 +1131,7 @@ tnsim_status tnsim_apply_2q(tnsim_mps h, int32_t q0, int32_t q1, const tnsim_c12
   Pending p;
   orient(q0, q1, g, p);
   h->last_sweeps = 0;
+  h->last_batch.clear();
   return run_2q_batch(h, &p, 1);
 }
 
@@ -695,6 +1143,7 @@ tnsim_status tnsim_apply_layer(tnsim_mps h, const tnsim_gate *gates, int32_t n_g
   s = validate_layer(h, gates, n_gates, g1, g2);
   if (s != TNSIM_OK) return s;
   h->last_sweeps = 0;
+  h->last_batch.clear();
   s = run_1q(h, g1);
   if (s != TNSIM_OK) return s;
   return run_2q(h, g2);
@@ -876,6 +1325,17 @@ tnsim_status tnsim_sweep_stats(tnsim_mps h, int64_t *gates, int64_t *sweeps_sum,
   return TNSIM_OK;
 }
 
+tnsim_status tnsim_last_batch(tnsim_mps h, int32_t *out, int32_t max_gates, int32_t *n) {
+  tnsim_status s = check_handle(h);
+  if (s != TNSIM_OK) return s;
+  if (!n || max_gates < 0 || (max_gates > 0 && !out)) return TNSIM_E_ARG;
+  int cnt = (int)(h->last_batch.size() / 6);
+  *n = cnt;
+  int w = std::min(cnt, (int)max_gates);
+  if (w > 0) memcpy(out, h->last_batch.data(), sizeof(int32_t) * 6 * w);
+  return TNSIM_OK;
+}
+
 tnsim_status tnsim_export_site(tnsim_mps h, int32_t q, tnsim_c128 *host, int32_t *chiL,
                                int32_t *chiR) {
   tnsim_status s = check_handle(h);
@@ -944,6 +1404,154 @@ tnsim_status tnsim_import_state(tnsim_mps h, const tnsim_c128 *const *sites,
                         hipMemcpyHostToDevice));
   HIPCHK(h, hipMemcpy(h->dims_dev(), chis, sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice));
   h->dims.assign(chis, chis + n + 1);
+  return TNSIM_OK;
+}
+
+size_t tnsim_grad_workspace_bytes(const tnsim_config *cfg, int32_t n_segments,
+                                  int32_t max_segment_gates, int32_t n_params) {
+  if (!valid_config(cfg) || n_segments < 1 || max_segment_gates < 1 || n_params < 0) return 0;
+  Layout L = make_layout(*cfg);
+  return grad_layout(L, n_segments, max_segment_gates, n_params).total;
+}
+
+tnsim_status tnsim_forward_checkpointed(tnsim_mps h, void *dev_ws, size_t ws_bytes,
+                                        const tnsim_gate *circuit, int32_t n_gates,
+                                        const int32_t *param_of_gate, const int32_t *rot_axis,
+                                        const double *angles, int32_t n_params,
+                                        const int32_t *segment_start, int32_t n_segments,
+                                        const char *const *paulis, const double *coeffs,
+                                        int32_t n_terms, double *loss) {
+  tnsim_status s = check_handle(h);
+  if (s != TNSIM_OK) return s;
+  const int n = h->L.n;
+  if (!dev_ws || !loss || n_gates < 0 || (n_gates > 0 && (!circuit || !param_of_gate)) ||
+      n_params < 0 || (n_params > 0 && (!angles || !rot_axis)) || n_segments < 1 ||
+      !segment_start || n_terms < 1 || !paulis || !coeffs)
+    return TNSIM_E_ARG;
+  if (h->cfg.precision != TNSIM_FP64) return TNSIM_E_ARG;  // the adjoint records float64
+  if (reinterpret_cast<uintptr_t>(dev_ws) % ALIGN) return TNSIM_E_ARG;
+  if (segment_start[0] != 0) return TNSIM_E_ARG;
+  int max_seg = 0;
+  for (int sg = 0; sg < n_segments; sg++) {
+    int a = segment_start[sg], b = sg + 1 < n_segments ? segment_start[sg + 1] : n_gates;
+    if (a > b || b > n_gates) return TNSIM_E_ARG;
+    max_seg = std::max(max_seg, b - a);
+  }
+  for (int g = 0; g < n_gates; g++) {
+    int a = circuit[g].q0, b = circuit[g].q1, p = param_of_gate[g];
+    if (a < 0 || a >= n || b < -1 || b >= n || a == b) return TNSIM_E_ARG;
+    if (b >= 0 && std::abs(a - b) != 1) return TNSIM_E_NONLOCAL;
+    if (p >= n_params || (p >= 0 && (b >= 0 || rot_axis[p] < 0 || rot_axis[p] > 2)))
+      return TNSIM_E_ARG;
+  }
+  std::vector<std::vector<double2>> tabs(n_terms);
+  std::vector<std::vector<char>> isIs(n_terms);
+  for (int t = 0; t < n_terms; t++) {
+    if (!paulis[t]) return TNSIM_E_ARG;
+    if (pauli_table(paulis[t], n, tabs[t], isIs[t]) != TNSIM_OK) return TNSIM_E_ARG;
+  }
+  GradState G = grad_layout(h->L, n_segments, std::max(max_seg, 1), n_params);
+  if (ws_bytes < G.total) return TNSIM_E_CAPACITY;
+  G.ws = (char *)dev_ws;
+  G.ws_bytes = ws_bytes;
+  G.gates.assign(circuit, circuit + n_gates);
+  G.param.assign(param_of_gate, param_of_gate + n_gates);
+  G.axis.assign(n_gates, -1);
+  for (int g = 0; g < n_gates; g++)
+    if (G.param[g] >= 0) G.axis[g] = rot_axis[G.param[g]];
+  G.angles.assign(angles, angles + n_params);
+  G.seg_start.assign(segment_start, segment_start + n_segments);
+  G.paulis.clear();
+  for (int t = 0; t < n_terms; t++) G.paulis.emplace_back(paulis[t], paulis[t] + n);
+  G.coeffs.assign(coeffs, coeffs + n_terms);
+  G.ckpt_dims.assign(n_segments + 1, {});
+  h->grad = std::move(G);
+  GradState &GS = h->grad;
+  s = init_state(h);
+  if (s != TNSIM_OK) return s;
+  for (int sg = 0; sg < n_segments; sg++) {
+    s = save_ckpt(h, sg);
+    if (s != TNSIM_OK) return s;
+    int a = GS.seg_start[sg], b = sg + 1 < n_segments ? GS.seg_start[sg + 1] : n_gates;
+    for (int g = a; g < b; g++) {
+      s = grad_apply(h, g, nullptr);
+      if (s != TNSIM_OK) return s;
+    }
+  }
+  s = save_ckpt(h, n_segments);
+  if (s != TNSIM_OK) return s;
+  double2 den, num;
+  s = transfer(h, h, h, nullptr, nullptr, &den);
+  if (s != TNSIM_OK) return s;
+  double L = 0.0;
+  for (int t = 0; t < n_terms; t++) {
+    s = transfer(h, h, h, tabs[t].data(), isIs[t].data(), &num);
+    if (s != TNSIM_OK) return s;
+    L += coeffs[t] * num.x / den.x;
+  }
+  GS.loss = L;
+  GS.ready = true;
+  *loss = L;
+  return TNSIM_OK;
+}
+
+tnsim_status tnsim_backward(tnsim_mps h, double dloss, double *grad_angles) {
+  tnsim_status s = check_handle(h);
+  if (s != TNSIM_OK) return s;
+  GradState &G = h->grad;
+  if (!G.ready || (G.n_params > 0 && !grad_angles)) return TNSIM_E_ARG;
+  const int n = h->L.n;
+  hipStream_t st = h->stream;
+  // zero the cotangents and gradients
+  for (int q = 0; q < n; q++)
+    launch_fill_zero(st, G.ws + G.cot_site[q], align_up(h->L.site_cap[q] * sizeof(double2), 16));
+  for (int b = 0; b < n - 1; b++)
+    launch_fill_zero(st, G.ws + G.cot_lam[b], align_up(sizeof(double) * h->L.bondcap[b], 16));
+  launch_fill_zero(st, G.ws + G.grad, align_up(sizeof(double) * std::max(G.n_params, 1), 16));
+  LAUNCHCHK(h, "backward init");
+  // the final state: loss = sum_t c_t N_t / D
+  s = restore_ckpt(h, G.n_seg);
+  if (s != TNSIM_OK) return s;
+  double2 den, num;
+  s = transfer(h, h, h, nullptr, nullptr, &den);
+  if (s != TNSIM_OK) return s;
+  const double D = den.x;
+  std::vector<double2> tab;
+  std::vector<char> isI;
+  for (size_t t = 0; t < G.paulis.size(); t++) {
+    pauli_table(G.paulis[t].c_str(), n, tab, isI);
+    s = loss_cotangent_term(h, tab.data(), isI.data(), dloss * G.coeffs[t] / D);
+    if (s != TNSIM_OK) return s;
+  }
+  {  // d(N/D): the norm term, weight -L/D
+    std::vector<char> allI(n, 1);
+    std::vector<double2> idt(4 * n, make_double2(0, 0));
+    s = loss_cotangent_term(h, idt.data(), allI.data(), -dloss * G.loss / D);
+    if (s != TNSIM_OK) return s;
+  }
+  const int n_gates = (int)G.gates.size();
+  std::vector<GradRec> recs;
+  for (int sg = G.n_seg - 1; sg >= 0; sg--) {
+    s = restore_ckpt(h, sg);
+    if (s != TNSIM_OK) return s;
+    int a = G.seg_start[sg], b = sg + 1 < G.n_seg ? G.seg_start[sg + 1] : n_gates;
+    recs.assign(b - a, GradRec{});
+    for (int g = a; g < b; g++) {
+      recs[g - a].off = G.rec0 + G.rec_stride * (size_t)(g - a);
+      s = grad_apply(h, g, &recs[g - a]);
+      if (s != TNSIM_OK) return s;
+    }
+    for (int g = b - 1; g >= a; g--) {
+      const GradRec &R = recs[g - a];
+      s = R.kind == 2 ? adjoint_2q(h, R) : adjoint_1q(h, R);
+      if (s != TNSIM_OK) return s;
+    }
+  }
+  s = restore_ckpt(h, G.n_seg);
+  if (s != TNSIM_OK) return s;
+  if (G.n_params > 0)
+    HIPCHK(h, hipMemcpy(grad_angles, G.ws + G.grad, sizeof(double) * G.n_params,
+                        hipMemcpyDeviceToHost));
   return TNSIM_OK;
 }
 

@@ -93,6 +93,48 @@ void launch_wb_left(hipStream_t st, const GateDesc *d, int ng, int max_m, int ma
 void launch_wb_right(hipStream_t st, const GateDesc *d, int ng, int precision, int max_k,
                      int max_n);
 
+// Adjoint sweep (k_adjoint.hip)
+struct Mat4 {
+  double2 v[4];
+};
+struct Mat16 {
+  double2 v[16];
+};
+struct GemmArgs {
+  int M, N, K;
+  const void *A;
+  long long sa_i, sa_k;
+  int a_conj, a_storage;
+  const void *B;
+  long long sb_k, sb_j;
+  int b_conj, b_storage;
+  double2 *C;
+  long long sc_i, sc_j;
+  double2 alpha;
+  int accumulate;
+};
+void launch_gemm_gen(hipStream_t st, const GemmArgs &g);
+void launch_fill_c(hipStream_t st, double2 *p, size_t n, double2 v);
+void launch_svd_adj_mid(hipStream_t st, const double2 *C, double2 *Abar, const double *lam2,
+                        const double *sbar, int m, int k, double eta);
+void launch_herm_sum(hipStream_t st, const double2 *H, double2 *S, int m);
+void launch_weight_adj(hipStream_t st, const double2 *Mbar, const double2 *Tp, double2 *Tbar,
+                       const double *lam, double *lambar, int m, int chiR);
+void launch_weight_apply(hipStream_t st, const double2 *Tp, double2 *M, const double *lam, int m,
+                         int chiR);
+void launch_gate_adj(hipStream_t st, double2 *T, int chiL, int chiR, const Mat16 &g);
+void launch_1q_adj(hipStream_t st, double2 *Abar, const void *Aold, int storage, int chiL,
+                   int chiR, const Mat4 &u, double *ubar);
+void launch_dot_re(hipStream_t st, const double2 *x, const void *y, int y_storage, size_t n,
+                   double *out);
+void launch_sigma_bar(hipStream_t st, const double *dots, const double *lambark,
+                      const double *lam2, double N, int k, double *sbar);
+void launch_gather_basis(hipStream_t st, const double2 *J, int ldj, const int *perm,
+                         const double *sig2, double2 *U, double *lam2, int m);
+void launch_sort_all(hipStream_t st, const double *sig2, int cols, int *perm);
+void launch_angle_grad(hipStream_t st, const double *ubar, const Mat4 &u, int axis,
+                       double *grad);
+
 // Readouts
 void launch_gemm_nn(hipStream_t st, int M, int N, int K, const double2 *A, int lda,
                     const void *B, int ldb, int b_storage, double2 *C, int ldc);

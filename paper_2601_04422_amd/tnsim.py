@@ -60,12 +60,19 @@ _SIGS = {
     "tnsim_truncation_stats": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                          C.POINTER(C.c_int64)]),
     "tnsim_last_sweeps": (C.c_int, [_P, C.POINTER(C.c_int32)]),
+    "tnsim_last_batch": (C.c_int, [_P, _P, C.c_int32, C.POINTER(C.c_int32)]),
     "tnsim_sweep_stats": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                     C.POINTER(C.c_int32)]),
     "tnsim_export_site": (C.c_int, [_P, C.c_int32, _P, C.POINTER(C.c_int32),
                                     C.POINTER(C.c_int32)]),
     "tnsim_export_lambda": (C.c_int, [_P, C.c_int32, _P, C.POINTER(C.c_int32)]),
     "tnsim_import_state": (C.c_int, [_P, _P, _P, _P]),
+    "tnsim_grad_workspace_bytes": (C.c_size_t, [C.POINTER(Config), C.c_int32, C.c_int32,
+                                                 C.c_int32]),
+    "tnsim_forward_checkpointed": (C.c_int, [_P, _P, C.c_size_t, _P, C.c_int32, _P, _P, _P,
+                                             C.c_int32, _P, C.c_int32, _P, _P, C.c_int32,
+                                             C.POINTER(C.c_double)]),
+    "tnsim_backward": (C.c_int, [_P, C.c_double, _P]),
     "tnsim_profile": (C.c_int, [_P, C.c_int32]),
     "tnsim_profile_read": (C.c_int, [_P, _P]),
     "tnsim_status_string": (C.c_char_p, [C.c_int]),
@@ -251,6 +258,54 @@ class MPS:
         return {"sum_eps": se.value, "prod_keep": pk.value, "n2q": n2.value,
                 "last_sweeps": sw.value}
 
+    def last_batch(self) -> np.ndarray:
+        """Rows (i, chiL, chiM, chiR, k, sweeps) for the last apply call."""
+        cnt = C.c_int32()
+        self._chk(lib().tnsim_last_batch(self._h, None, 0, C.byref(cnt)), "last_batch")
+        out = np.zeros((max(cnt.value, 1), 6), dtype=np.int32)
+        self._chk(lib().tnsim_last_batch(self._h, out.ctypes.data, cnt.value, C.byref(cnt)),
+                  "last_batch")
+        return out[: cnt.value]
+
+    # ---------------------------------------------------------------- gradients
+    def forward_checkpointed(self, gates: Sequence, param_of_gate: Sequence[int],
+                             rot_axis: Sequence[int], angles, segment_start: Sequence[int],
+                             paulis: Sequence[str], coeffs: Sequence[float]) -> float:
+        """Loss sum_t c_t <P_t> of the circuit from |0...0>, keeping checkpoints
+        for ``backward``.  Gates with param_of_gate >= 0 are rotations about
+        rot_axis[param] by angles[param] (their matrix is ignored)."""
+        import torch
+
+        arr = pack_gates(gates)
+        pg = np.ascontiguousarray(param_of_gate, dtype=np.int32)
+        ax = np.ascontiguousarray(rot_axis, dtype=np.int32)
+        ang = np.ascontiguousarray(angles, dtype=np.float64)
+        seg = np.ascontiguousarray(segment_start, dtype=np.int32)
+        bounds = list(seg) + [len(gates)]
+        max_seg = max(1, max(b - a for a, b in zip(bounds[:-1], bounds[1:])))
+        ws = lib().tnsim_grad_workspace_bytes(C.byref(self.cfg), len(seg), max_seg, ang.size)
+        if ws == 0:
+            raise TnsimError(E_ARG, "grad_workspace_bytes")
+        if getattr(self, "_grad_ws", None) is None or self._grad_ws.numel() < ws:
+            self._grad_ws = torch.empty(ws, dtype=torch.uint8, device=self.device)
+        enc = [p.encode() for p in paulis]
+        pp = (C.c_char_p * len(enc))(*enc)
+        cf = np.ascontiguousarray(coeffs, dtype=np.float64)
+        out = C.c_double()
+        self._grad_keep = (arr, pg, ax, ang, seg, enc, pp, cf)
+        self._chk(lib().tnsim_forward_checkpointed(
+            self._h, C.c_void_p(self._grad_ws.data_ptr()), self._grad_ws.numel(), arr.ctypes.data,
+            len(gates), pg.ctypes.data, ax.ctypes.data, ang.ctypes.data, ang.size,
+            seg.ctypes.data, seg.size, pp, cf.ctypes.data, cf.size, C.byref(out)),
+            "forward_checkpointed")
+        self._n_params = ang.size
+        return out.value
+
+    def backward(self, dloss: float = 1.0) -> np.ndarray:
+        g = np.zeros(max(self._n_params, 1), dtype=np.float64)
+        self._chk(lib().tnsim_backward(self._h, dloss, g.ctypes.data), "backward")
+        return g[: self._n_params]
+
     def sweep_stats(self) -> dict:
         g, sm = C.c_int64(), C.c_int64()
         mx = C.c_int32()
@@ -291,3 +346,35 @@ class MPS:
         sp = (C.c_void_p * n)(*[s.ctypes.data for s in sites])
         lp = (C.c_void_p * max(n - 1, 1))(*([l.ctypes.data for l in lams] or [None]))
         self._chk(lib().tnsim_import_state(self._h, sp, lp, chis.ctypes.data), "import_state")
+
+
+def _autograd_function():
+    import torch
+
+    class PauliSumLoss(torch.autograd.Function):
+        """loss(angles) = sum_t c_t <P_t> of a parametrised circuit on an MPS.
+
+        ``forward(angles, mps, spec)`` with spec = (gates, param_of_gate,
+        rot_axis, segment_start, paulis, coeffs); the gradient comes from the
+        library's hand-written adjoint (tnsim_backward)."""
+
+        @staticmethod
+        def forward(ctx, angles, mps, spec):
+            gates, pg, ax, seg, paulis, coeffs = spec
+            a = angles.detach().to("cpu", torch.float64).numpy()
+            loss = mps.forward_checkpointed(gates, pg, ax, a, seg, paulis, coeffs)
+            ctx.mps = mps
+            ctx.dev = angles.device
+            return torch.tensor(loss, dtype=torch.float64, device=angles.device)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            g = ctx.mps.backward(float(grad_out))
+            return torch.from_numpy(g).to(ctx.dev), None, None
+
+    return PauliSumLoss
+
+
+def pauli_sum_loss(angles, mps: "MPS", spec):
+    """Differentiable Pauli-sum loss (see PauliSumLoss)."""
+    return _autograd_function().apply(angles, mps, spec)
