@@ -47,7 +47,7 @@ def log(*a):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--prep-layers", type=int, default=20)
     ap.add_argument("--precision", default="bf16x6", choices=["fp64", "f32acc", "bf16x3", "bf16x6"])
@@ -56,6 +56,10 @@ def parse():
     ap.add_argument("--no-pergate", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=16)
+    ap.add_argument("--workload", default="chi1024",
+                    choices=["chi1024", "wide", "ansatz", "batch"],
+                    help="chi1024: the headline metric; the others measure the secondary "
+                         "workloads (one JSON line each)")
     return ap.parse_args()
 
 
@@ -111,12 +115,163 @@ def cpu_baseline(threads, chi):
                       f"left-canonical input; {dt:.1f} s"}
 
 
+def bench_wide(args):
+    """n=64 Haar brickwork, depth 20, chi_max=256, cutoff 1e-10, complex64 with the
+    float32 matrix-core contraction, one batched launch sequence per layer;
+    per-site <Z> against the float64 path."""
+    import torch
+
+    from paper_2601_04422_amd import tnsim as T
+    from paper_2601_04422_amd import workloads as W
+
+    cfg = W.config_wide()
+    m = T.MPS(cfg.n, cfg.chi_max, cfg.cutoff, precision="f32acc", storage="c64")
+    ref = T.MPS(cfg.n, cfg.chi_max, cfg.cutoff, precision="fp64", storage="c128")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m.run_layers(cfg.layers)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    ref.run_layers(cfg.layers)
+    torch.cuda.synchronize()
+    dt_ref = time.perf_counter() - t1
+    zs = []
+    for q in range(cfg.n):
+        s = ["I"] * cfg.n
+        s[q] = "Z"
+        zs.append((m.expect("".join(s)).real, ref.expect("".join(s)).real))
+    zerr = max(abs(a - b) for a, b in zs)
+    fid = abs(m.overlap(ref)) ** 2 / (m.norm2() * ref.norm2())
+    return {"metric": "2q gates/s, n=64 brickwork chi_max=256", "value": cfg.n2q() / dt,
+            "unit": "2q gates/s", "n_gpus": 1, "steps": len(cfg.layers), "warmup": 0,
+            "ms_per_step": 1e3 * dt / len(cfg.layers), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32acc contraction, f64 svd",
+            "data": "synthetic",
+            "config": {"workload": cfg.name + ", cutoff 1e-10, complex64"},
+            "fp64_path_gates_per_s": cfg.n2q() / dt_ref,
+            "max_abs_dZ_vs_fp64": zerr, "fidelity_err_vs_fp64": 1 - fid,
+            "sum_eps": m.stats()["sum_eps"]}
+
+
+def bench_ansatz(args):
+    """Gradient of sum_i <Z_i Z_i+1> for the n=32, 8-layer Ry/Rz + CNOT-ladder
+    ansatz at chi_max=128: forward (checkpointed) + adjoint backward time and
+    the gradient error against central finite differences on a sample."""
+    import torch
+
+    from paper_2601_04422_amd import tnsim as T
+    from paper_2601_04422_amd import workloads as W
+
+    n, nl, chi = 32, 8, 128
+    angles = W.ansatz_angles(n, nl)
+    qs, ps, axes = W.ansatz_structure(n, nl)
+    gates = [(q0, q1, W.cnot() if q1 >= 0 else np.eye(2)) for (q0, q1) in qs]
+    rot_axis = np.zeros(angles.size, dtype=np.int32)
+    for p, ax in zip(ps, axes):
+        if p >= 0:
+            rot_axis[p] = ax
+    per_layer = 2 * n + n - 1
+    seg = [l * per_layer for l in range(nl)]
+    paulis = W.zz_chain(n)
+    coeffs = [1.0] * len(paulis)
+    m = T.MPS(n, chi, 0.0)
+    m.forward_checkpointed(gates, ps, rot_axis, angles, seg, paulis, coeffs)  # warm-up
+    m.backward(1.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = m.forward_checkpointed(gates, ps, rot_axis, angles, seg, paulis, coeffs)
+    t1 = time.perf_counter()
+    g = m.backward(1.0)
+    t2 = time.perf_counter()
+    sum_eps = m.stats()["sum_eps"]
+    rng = np.random.default_rng(0)
+    idx = rng.choice(angles.size, 8, replace=False)
+    h = 1e-4
+    fd = []
+    for p in idx:
+        a = angles.copy()
+        a[p] += h
+        lp = T.MPS(n, chi, 0.0).forward_checkpointed(gates, ps, rot_axis, a, seg, paulis, coeffs)
+        a[p] -= 2 * h
+        lm = T.MPS(n, chi, 0.0).forward_checkpointed(gates, ps, rot_axis, a, seg, paulis, coeffs)
+        fd.append((lp - lm) / (2 * h))
+    fd = np.array(fd)
+    err = float(np.linalg.norm(g[idx] - fd) / np.linalg.norm(fd))
+    return {"metric": "forward+backward time, n=32 8-layer ansatz, 512 angles, chi_max=128",
+            "value": t2 - t0, "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 1,
+            "ms_per_step": 1e3 * (t2 - t0), "higher_is_better": False, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "Ry,Rz per qubit + CNOT ladder, 8 layers, loss sum Z_i Z_i+1"},
+            "forward_s": t1 - t0, "backward_s": t2 - t1, "loss": loss, "sum_eps": sum_eps,
+            "grad_rel_err_vs_fd_sample": err}
+
+
+def bench_batch(args):
+    """256 independent brickwork circuits of uneven n, depth and chi_max,
+    complex64 + split-bf16 contraction, all gates of a layer step of all
+    circuits in shared launches; aggregate gates/s and per-circuit fidelity
+    against the oracle for the small circuits."""
+    import torch
+
+    from oracle import oracle as O
+    from paper_2601_04422_amd import tnsim as T
+    from paper_2601_04422_amd import workloads as W
+
+    circs = sorted(W.config_batch(), key=lambda c: -c.depth)
+    ms = []
+    for k, c in enumerate(circs):
+        mlg = 8192 if k == 0 else (4 if c.chi_max >= 256 else 8)
+        ms.append(T.MPS(c.n, c.chi_max, 1e-10, precision=args.precision, storage="c64",
+                        max_layer_gates=mlg))
+    total = sum(sum(len(l) for l in c.layers) for c in circs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(max(c.depth for c in circs)):
+        act = [k for k, c in enumerate(circs) if t < c.depth]
+        st = T.apply_layer_multi([ms[k] for k in act], [circs[k].layers[t] for k in act])
+        if st != 0:
+            raise RuntimeError(f"apply_layer_multi failed: {st}")
+        log(f"batch step {t}: {len(act)} circuits ({time.perf_counter() - t0:.1f} s)")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    # oracle fidelity for the circuits it finishes quickly
+    O.set_threads(args.cpu_threads)
+    fids = []
+    t_or = time.perf_counter()
+    for k in sorted(range(len(circs)), key=lambda k: circs[k].chi_max * circs[k].n):
+        c = circs[k]
+        if c.chi_max > 64 or time.perf_counter() - t_or > 60:
+            break
+        o = O.OracleMPS(c.n, c.chi_max, 1e-10)
+        o.run_layers(c.layers)
+        sites = [ms[k].site(q) for q in range(c.n)]
+        lams = [ms[k].lam(b) for b in range(c.n - 1)]
+        h = O.OracleMPS(c.n, 4096)
+        h.set_state(sites, lams)
+        fids.append(1 - abs(h.overlap(o)) ** 2 / (h.norm2() * o.norm2()))
+    return {"metric": "aggregate 2q gates/s, 256 ragged brickwork circuits", "value": total / dt,
+            "unit": "2q gates/s", "n_gpus": 1, "steps": max(c.depth for c in circs),
+            "warmup": 0, "ms_per_step": 1e3 * dt / max(c.depth for c in circs),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": f"{args.precision} contraction, f64 svd", "data": "synthetic",
+            "config": {"workload": "256 circuits: n U{16..96}, depth U{8..24}, chi_max in "
+                                   "{32,64,128,256,512}, cutoff 1e-10, complex64"},
+            "total_2q_gates": total,
+            "oracle_checked_circuits": len(fids),
+            "max_fidelity_err_vs_oracle": max(fids) if fids else None}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no "
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
+    if args.workload != "chi1024":
+        fn = {"wide": bench_wide, "ansatz": bench_ansatz, "batch": bench_batch}[args.workload]
+        print(json.dumps(fn(args)), flush=True)
+        return
     import torch
 
     from paper_2601_04422_amd import tnsim as T

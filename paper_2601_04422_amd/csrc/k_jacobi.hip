@@ -125,8 +125,7 @@ void launch_begin_sweep(hipStream_t st, const GateDesc *d, int ng) {
 
 constexpr int GK = 32;  // rows per LDS tile
 
-__global__ __launch_bounds__(256) void k_gram(const GateDesc *descs, int round, int ksplit,
-                                              int npairs_stride) {
+__global__ __launch_bounds__(256) void k_gram(const GateDesc *descs, int round, int ksplit) {
   const GateDesc &d = descs[blockIdx.y];
   const int pairIdx = blockIdx.x / ksplit, kc = blockIdx.x % ksplit;
   if (!d.sc->active || round >= d.nblk - 1 || pairIdx >= d.nblk / 2) return;
@@ -172,7 +171,7 @@ __global__ __launch_bounds__(256) void k_gram(const GateDesc *descs, int round, 
     atomicAdd(&d.ctr[CTR_GRAM_FLOP], 8ull * (rend - rbeg) * PW * PW);
     atomicAdd(&d.ctr[CTR_GRAM_BYTE], 16ull * (rend - rbeg) * PW + 16ull * PW * PW);
   }
-  double2 *G = d.Gp + ((size_t)kc * npairs_stride + pairIdx) * (PW * PW);
+  double2 *G = d.Gp + ((size_t)kc * d.gpStride + pairIdx) * (PW * PW);
 #pragma unroll
   for (int i = 0; i < 4; i++)
 #pragma unroll
@@ -191,8 +190,8 @@ __device__ __forceinline__ d4_t mfma64(double a, double b, d4_t c) {
 
 // Same pair Gram on float64 matrix cores (v_mfma_f64_16x16x4): wavefront w
 // owns the 32x32 quarter (rows 32*(w/2), columns 32*(w%2)) of G as 2x2 tiles.
-__global__ __launch_bounds__(256) void k_gram_mfma(const GateDesc *descs, int round, int ksplit,
-                                                   int npairs_stride) {
+__global__ __launch_bounds__(256) void k_gram_mfma(const GateDesc *descs, int round,
+                                                   int ksplit) {
   const GateDesc &d = descs[blockIdx.y];
   const int pairIdx = blockIdx.x / ksplit, kc = blockIdx.x % ksplit;
   if (!d.sc->active || round >= d.nblk - 1 || pairIdx >= d.nblk / 2) return;
@@ -249,7 +248,7 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const GateDesc *descs, int ro
     atomicAdd(&d.ctr[CTR_GRAM_FLOP], 8ull * (rend - rbeg) * PW * PW);
     atomicAdd(&d.ctr[CTR_GRAM_BYTE], 16ull * (rend - rbeg) * PW + 16ull * PW * PW);
   }
-  double2 *G = d.Gp + ((size_t)kc * npairs_stride + pairIdx) * (PW * PW);
+  double2 *G = d.Gp + ((size_t)kc * d.gpStride + pairIdx) * (PW * PW);
 #pragma unroll
   for (int ti = 0; ti < 2; ti++)
 #pragma unroll
@@ -271,8 +270,7 @@ constexpr int LDG = PW + 1;
 // updated as 2x2 blocks (rows of one pair x columns of another), so every
 // entry is read and written once per round.  At most `inner_sweeps` sweeps;
 // the outer sweeps finish what a capped inner solve leaves.
-__global__ __launch_bounds__(256) void k_eig(const GateDesc *descs, int round, int ksplit,
-                                             int npairs_stride) {
+__global__ __launch_bounds__(256) void k_eig(const GateDesc *descs, int round, int ksplit) {
   const GateDesc &d = descs[blockIdx.y];
   const int pairIdx = blockIdx.x;
   if (!d.sc->active || round >= d.nblk - 1 || pairIdx >= d.nblk / 2) return;
@@ -291,7 +289,7 @@ __global__ __launch_bounds__(256) void k_eig(const GateDesc *descs, int round, i
   for (int e = tid; e < PW * PW; e += 256) {
     double2 s = make_double2(0.0, 0.0);
     for (int kc = 0; kc < ksplit; kc++) {
-      double2 v = d.Gp[((size_t)kc * npairs_stride + pairIdx) * (PW * PW) + e];
+      double2 v = d.Gp[((size_t)kc * d.gpStride + pairIdx) * (PW * PW) + e];
       s.x += v.x;
       s.y += v.y;
     }
@@ -592,21 +590,29 @@ static bool use_mfma() {
 }
 
 void launch_gram(hipStream_t st, const GateDesc *d, int ng, int round, int max_pairs,
-                 int ksplit, int npairs_stride) {
+                 int ksplit) {
   if (ng <= 0) return;
   if (use_mfma())
     hipLaunchKernelGGL(k_gram_mfma, dim3(max_pairs * ksplit, ng), dim3(256), 0, st, d, round,
-                       ksplit, npairs_stride);
+                       ksplit);
   else
-    hipLaunchKernelGGL(k_gram, dim3(max_pairs * ksplit, ng), dim3(256), 0, st, d, round, ksplit,
-                       npairs_stride);
+    hipLaunchKernelGGL(k_gram, dim3(max_pairs * ksplit, ng), dim3(256), 0, st, d, round, ksplit);
 }
 
-void launch_eig(hipStream_t st, const GateDesc *d, int ng, int round, int max_pairs, int ksplit,
-                int npairs_stride) {
+void launch_eig(hipStream_t st, const GateDesc *d, int ng, int round, int max_pairs, int ksplit) {
   if (ng <= 0) return;
-  hipLaunchKernelGGL(k_eig, dim3(max_pairs, ng), dim3(256), 0, st, d, round, ksplit,
-                     npairs_stride);
+  hipLaunchKernelGGL(k_eig, dim3(max_pairs, ng), dim3(256), 0, st, d, round, ksplit);
+}
+
+// Copy every gate's scalars into one array (one device-to-host copy per sweep).
+__global__ void k_gather_sc(const GateDesc *descs, int ng, SlotScalars *out) {
+  int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < ng) out[g] = *descs[g].sc;
+}
+
+void launch_gather_sc(hipStream_t st, const GateDesc *d, int ng, SlotScalars *out) {
+  if (ng <= 0) return;
+  hipLaunchKernelGGL(k_gather_sc, dim3((ng + 63) / 64), dim3(64), 0, st, d, ng, out);
 }
 
 void launch_rot(hipStream_t st, const GateDesc *d, int ng, int round, int max_pairs,
@@ -623,7 +629,7 @@ void launch_rot(hipStream_t st, const GateDesc *d, int ng, int round, int max_pa
 
 constexpr int SORT_MAX = 4096;
 
-__global__ __launch_bounds__(256) void k_trunc(const GateDesc *descs, int *dims_dev) {
+__global__ __launch_bounds__(256) void k_trunc(const GateDesc *descs) {
   const GateDesc &d = descs[blockIdx.x];
   __shared__ double key[SORT_MAX];
   __shared__ int idx[SORT_MAX];
@@ -690,7 +696,7 @@ __global__ __launch_bounds__(256) void k_trunc(const GateDesc *descs, int *dims_
     d.sc->W = W;
     d.sc->eps = W > 0.0 ? tail[k] / W : 0.0;
     d.sc->nz = nz;
-    dims_dev[d.i + 1] = k;
+    d.dimsDev[d.i + 1] = k;
     s_k = k;
     s_N = N;
   }
@@ -701,9 +707,9 @@ __global__ __launch_bounds__(256) void k_trunc(const GateDesc *descs, int *dims_
   }
 }
 
-void launch_trunc(hipStream_t st, const GateDesc *d, int ng, int *dims_dev) {
+void launch_trunc(hipStream_t st, const GateDesc *d, int ng) {
   if (ng <= 0) return;
-  hipLaunchKernelGGL(k_trunc, dim3(ng), dim3(256), 0, st, d, dims_dev);
+  hipLaunchKernelGGL(k_trunc, dim3(ng), dim3(256), 0, st, d);
 }
 
 }  // namespace tn

@@ -23,7 +23,7 @@ inline size_t align_up(size_t x, size_t a = ALIGN) { return (x + a - 1) / a * a;
 inline int pad_to(int x, int a) { return (x + a - 1) / a * a; }
 
 struct Layout {
-  int n = 0, chi_max = 0, storage = 0, nslots = 0;
+  int n = 0, chi_max = 0, storage = 0, nslots = 0, desc_cap = 0;
   size_t elem = 16;                 // site element bytes
   std::vector<int> bondcap;         // n-1
   std::vector<int> dimcap;          // n+1
@@ -34,7 +34,7 @@ struct Layout {
   size_t x_off = 0, j_off = 0, t_off = 0, v_off = 0, pf_off = 0, sig_off = 0, perm_off = 0,
          sc_off = 0;  // within a slot
   size_t gp_off = 0;  // pooled pair-Gram partials
-  size_t desc_off = 0, d1_off = 0, ctr_off = 0;
+  size_t desc_off = 0, d1_off = 0, ctr_off = 0, scg_off = 0;
   size_t e0_off = 0, e1_off = 0, f_off = 0, f2_off = 0, va_off = 0, vb_off = 0;
   size_t total = 0;
 };
@@ -57,6 +57,9 @@ Layout make_layout(const tnsim_config &c) {
   L.elem = c.storage == 0 ? 16 : 8;
   L.nslots = c.max_layer_gates > 0 ? std::min(c.max_layer_gates, std::max(1, L.n / 2))
                                    : std::max(1, L.n / 2);
+  // descriptors: this handle's gates, or, for a handle that leads a
+  // multi-circuit batch, up to max_layer_gates gates of all its handles
+  L.desc_cap = std::max(L.nslots, c.max_layer_gates);
   const int n = L.n;
   L.bondcap.resize(n - 1);
   int maxbond = 1;
@@ -116,7 +119,9 @@ Layout make_layout(const tnsim_config &c) {
   L.gp_off = off;
   off = align_up(off + sizeof(double2) * (size_t)L.gp_blocks * PW * PW);
   L.desc_off = off;
-  off = align_up(off + sizeof(GateDesc) * L.nslots);
+  off = align_up(off + sizeof(GateDesc) * L.desc_cap);
+  L.scg_off = off;
+  off = align_up(off + sizeof(SlotScalars) * L.desc_cap);
   L.d1_off = off;
   off = align_up(off + sizeof(Gate1Desc) * n);
   L.ctr_off = off;
@@ -209,6 +214,10 @@ struct tnsim_mps_s {
   int inner_sweeps = 2;
   std::vector<int32_t> last_batch;  // 6 ints per two-qubit gate of the last apply call
   GradState grad;
+  // captured Jacobi sweep (reused while the batch shape is unchanged)
+  bool graphs = true;
+  hipGraphExec_t sweep_exec = nullptr;
+  long long sweep_key[6] = {-1, -1, -1, -1, -1, -1};
   int64_t sw_gates = 0, sw_sum = 0;
   int sw_max = 0;
   std::vector<hipEvent_t> evpool;
@@ -323,17 +332,32 @@ tnsim_status init_state(tnsim_mps h) {
   return TNSIM_OK;
 }
 
-// Run one batch of two-qubit gates (at most nslots) through the whole path.
-tnsim_status run_2q_batch(tnsim_mps h, const Pending *gates, int ng, bool force_trans = false) {
-  const Layout &L = h->L;
-  const tnsim_config &c = h->cfg;
+// One two-qubit gate of a batch: the handle it belongs to, the workspace slot
+// of that handle it uses, and the gate.
+struct BatchItem {
+  tnsim_mps h;
+  int slot;
+  const Pending *p;
+};
+
+SlotScalars *pin_scalars(tnsim_mps o) {
+  return reinterpret_cast<SlotScalars *>(o->pin + align_up(sizeof(GateDesc) * o->L.desc_cap));
+}
+
+// Run a batch of two-qubit gates (possibly of several handles) through the
+// whole path in the same launches.  `o` owns the descriptors, the stream and
+// the profiling; every gate works in its own handle's state and slot.
+tnsim_status run_2q_items(tnsim_mps o, const BatchItem *items, int ng, bool force_trans) {
+  const tnsim_config &c = o->cfg;
   std::vector<GateDesc> D(ng);
   int maxM = 0, maxN = 0, maxRows = 0, maxColsPad = 0, maxPairs = 0, maxChiR = 0, maxNblk = 0;
   int maxMtrans = 0;
   for (int g = 0; g < ng; g++) {
     GateDesc &d = D[g];
     memset(&d, 0, sizeof d);
-    const int i = gates[g].i;
+    const tnsim_mps h = items[g].h;
+    const Layout &L = h->L;
+    const int i = items[g].p->i;
     d.i = i;
     d.chiL = h->dims[i];
     d.chiM = h->dims[i + 1];
@@ -349,17 +373,17 @@ tnsim_status run_2q_batch(tnsim_mps h, const Pending *gates, int ng, bool force_
     d.ldj = pad_to(d.m, 4);
     d.colsPad = pad_to(d.cols, PW);
     d.nblk = d.colsPad / BW;
-    d.chiMax = c.chi_max;
-    d.storage = c.storage;
+    d.chiMax = h->cfg.chi_max;
+    d.storage = h->cfg.storage;
     d.tfp32 = c.precision != TNSIM_FP64;
-    d.innerSweeps = h->inner_sweeps;
-    d.tol = c.jacobi_tol > 0 ? c.jacobi_tol : std::max(d.rows, 16) * 0x1p-53;
-    d.cutoff = c.cutoff;
+    d.innerSweeps = o->inner_sweeps;
+    d.tol = h->cfg.jacobi_tol > 0 ? h->cfg.jacobi_tol : std::max(d.rows, 16) * 0x1p-53;
+    d.cutoff = h->cfg.cutoff;
     d.A0 = h->site(i);
     d.A1 = h->site(i + 1);
     d.lamR = (i + 1 <= L.n - 2) ? h->lam(i + 1) : nullptr;
     d.lamOut = h->lam(i);
-    char *sl = h->slot(g);
+    char *sl = h->slot(items[g].slot);
     d.X = (double2 *)(sl + L.x_off);
     d.J = (double2 *)(sl + L.j_off);
     d.T = sl + L.t_off;
@@ -368,7 +392,9 @@ tnsim_status run_2q_batch(tnsim_mps h, const Pending *gates, int ng, bool force_
     d.sig2 = (double *)(sl + L.sig_off);
     d.perm = (int *)(sl + L.perm_off);
     d.sc = (SlotScalars *)(sl + L.sc_off);
-    for (int e = 0; e < 16; e++) d.g[e] = gates[g].g[e];
+    for (int e = 0; e < 16; e++) d.g[e] = items[g].p->g[e];
+    d.gpStride = L.npairs_max;
+    d.dimsDev = h->dims_dev();
     maxM = std::max(maxM, d.m);
     maxN = std::max(maxN, d.n);
     maxRows = std::max(maxRows, d.rows);
@@ -382,24 +408,32 @@ tnsim_status run_2q_batch(tnsim_mps h, const Pending *gates, int ng, bool force_
   // fill the GPU.
   int ksplit = (1024 + ng * maxPairs - 1) / (ng * maxPairs);
   ksplit = std::min(ksplit, KSPLIT_MAX);
-  ksplit = std::min(ksplit, std::max(1, L.gp_blocks / (ng * L.npairs_max)));
   ksplit = std::min(ksplit, std::max(1, (maxRows + 31) / 32));
+  for (int g = 0; g < ng; g++) {  // each gate's partials fit its handle's pool
+    const Layout &L = items[g].h->L;
+    ksplit = std::min(ksplit, std::max(1, L.gp_blocks / ((items[g].slot + 1) * L.npairs_max)));
+  }
   ksplit = std::max(ksplit, 1);
-  double2 *gp = h->at<double2>(L.gp_off);
-  for (int g = 0; g < ng; g++) D[g].Gp = gp + (size_t)g * ksplit * L.npairs_max * PW * PW;
+  for (int g = 0; g < ng; g++) {
+    const tnsim_mps h = items[g].h;
+    D[g].Gp = h->at<double2>(h->L.gp_off) +
+              (size_t)items[g].slot * ksplit * h->L.npairs_max * PW * PW;
+  }
 
-  unsigned long long *ctr = h->prof ? h->at<unsigned long long>(L.ctr_off) : nullptr;
+  unsigned long long *ctr = o->prof ? o->at<unsigned long long>(o->L.ctr_off) : nullptr;
   double theta_flop = 0.0, theta_byte = 0.0, colnorm_byte = 0.0;
   for (int g = 0; g < ng; g++) {
     D[g].ctr = ctr;
     const GateDesc &d = D[g];
-    const double eb = c.storage == 0 ? 16.0 : 8.0, tb = d.tfp32 ? 8.0 : 16.0;
+    const double eb = d.storage == 0 ? 16.0 : 8.0, tb = d.tfp32 ? 8.0 : 16.0;
     theta_flop += 8.0 * d.m * d.chiM * d.n + 32.0 * d.m * d.n;
     theta_byte += eb * ((double)d.m * d.chiM + (double)d.chiM * d.n) + (tb + 16.0) * d.m * d.n;
     colnorm_byte += 16.0 * d.rows * d.cols;
   }
 
-  GateDesc *ddev = h->at<GateDesc>(L.desc_off);
+  tnsim_mps h = o;  // launches, errors and profiling belong to the owner
+  GateDesc *ddev = o->at<GateDesc>(o->L.desc_off);
+  SlotScalars *scg = o->at<SlotScalars>(o->L.scg_off);
   HIPCHK(h, hipStreamSynchronize(h->stream));  // the staging buffer is free
   prof_drain(h);
   memcpy(h->pin, D.data(), sizeof(GateDesc) * ng);
@@ -425,11 +459,14 @@ tnsim_status run_2q_batch(tnsim_mps h, const Pending *gates, int ng, bool force_
   LAUNCHCHK(h, "theta");
 
   const int max_sweeps = c.jacobi_max_sweeps > 0 ? c.jacobi_max_sweeps : 60;
-  SlotScalars *sc_pin = reinterpret_cast<SlotScalars *>(h->pin + align_up(sizeof(GateDesc) * L.nslots));
+  SlotScalars *sc_pin = pin_scalars(o);
   bool converged = false;
   int sweeps = 0;
   std::vector<int> done_at(ng, 0);
-  for (int sweep = 1; sweep <= max_sweeps; sweep++) {
+  // One sweep: every round of the round-robin tournament, then the scalars
+  // gathered for the host's convergence test.  With a non-default stream and
+  // profiling off, the sweep is captured once as a HIP graph and replayed.
+  auto enqueue_sweep = [&]() {
     {
       ProfScope p(h, TNSIM_K_OTHER);
       launch_begin_sweep(st, ddev, ng);
@@ -437,20 +474,50 @@ tnsim_status run_2q_batch(tnsim_mps h, const Pending *gates, int ng, bool force_
     for (int r = 0; r < maxNblk - 1; r++) {
       {
         ProfScope p(h, TNSIM_K_GRAM);
-        launch_gram(st, ddev, ng, r, maxPairs, ksplit, L.npairs_max);
+        launch_gram(st, ddev, ng, r, maxPairs, ksplit);
       }
       {
         ProfScope p(h, TNSIM_K_EIG);
-        launch_eig(st, ddev, ng, r, maxPairs, ksplit, L.npairs_max);
+        launch_eig(st, ddev, ng, r, maxPairs, ksplit);
       }
       {
         ProfScope p(h, TNSIM_K_ROT);
         launch_rot(st, ddev, ng, r, maxPairs, maxRows, maxMtrans);
       }
     }
+    launch_gather_sc(st, ddev, ng, scg);
+  };
+  const bool use_graph = h->graphs && !h->prof && st != nullptr;
+  if (use_graph) {
+    const long long key[6] = {ng, maxPairs, ksplit, maxNblk, maxRows, maxMtrans};
+    if (!h->sweep_exec || memcmp(key, h->sweep_key, sizeof key) != 0) {
+      if (h->sweep_exec) {
+        hipGraphExecDestroy(h->sweep_exec);
+        h->sweep_exec = nullptr;
+      }
+      hipGraph_t graph = nullptr;
+      HIPCHK(h, hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+      enqueue_sweep();
+      hipError_t e1 = hipGetLastError();
+      hipError_t e2 = hipStreamEndCapture(st, &graph);
+      if (e1 != hipSuccess) return fail(h, e1, "sweep capture");
+      if (e2 != hipSuccess) return fail(h, e2, "hipStreamEndCapture");
+      hipError_t e3 = hipGraphInstantiate(&h->sweep_exec, graph, nullptr, nullptr, 0);
+      hipGraphDestroy(graph);
+      if (e3 != hipSuccess) {
+        h->sweep_exec = nullptr;
+        return fail(h, e3, "hipGraphInstantiate");
+      }
+      memcpy(h->sweep_key, key, sizeof key);
+    }
+  }
+  for (int sweep = 1; sweep <= max_sweeps; sweep++) {
+    if (use_graph)
+      HIPCHK(h, hipGraphLaunch(h->sweep_exec, st));
+    else
+      enqueue_sweep();
     LAUNCHCHK(h, "jacobi round");
-    for (int g = 0; g < ng; g++)
-      HIPCHK(h, hipMemcpyAsync(&sc_pin[g], D[g].sc, sizeof(SlotScalars), hipMemcpyDeviceToHost, st));
+    HIPCHK(h, hipMemcpyAsync(sc_pin, scg, sizeof(SlotScalars) * ng, hipMemcpyDeviceToHost, st));
     HIPCHK(h, hipStreamSynchronize(st));
     prof_drain(h);
     sweeps = sweep;
@@ -464,14 +531,17 @@ tnsim_status run_2q_batch(tnsim_mps h, const Pending *gates, int ng, bool force_
       break;
     }
   }
-  h->last_sweeps = std::max(h->last_sweeps, sweeps);
+  std::vector<size_t> rec_at(ng);
   for (int g = 0; g < ng; g++) {
+    tnsim_mps hg = items[g].h;
     int sw = done_at[g] ? done_at[g] : sweeps;
-    h->last_batch.insert(h->last_batch.end(),
-                         {D[g].i, D[g].chiL, D[g].chiM, D[g].chiR, 0, sw});
-    h->sw_gates += 1;
-    h->sw_sum += sw;
-    h->sw_max = std::max(h->sw_max, sw);
+    hg->last_sweeps = std::max(hg->last_sweeps, sweeps);
+    rec_at[g] = hg->last_batch.size();
+    hg->last_batch.insert(hg->last_batch.end(),
+                          {D[g].i, D[g].chiL, D[g].chiM, D[g].chiR, 0, sw});
+    hg->sw_gates += 1;
+    hg->sw_sum += sw;
+    hg->sw_max = std::max(hg->sw_max, sw);
   }
   if (!converged) {
     h->err = "Jacobi SVD did not converge within jacobi_max_sweeps";
@@ -483,26 +553,26 @@ tnsim_status run_2q_batch(tnsim_mps h, const Pending *gates, int ng, bool force_
   }
   {
     ProfScope p(h, TNSIM_K_TRUNC);
-    launch_trunc(st, ddev, ng, h->dims_dev());
+    launch_trunc(st, ddev, ng);
   }
+  launch_gather_sc(st, ddev, ng, scg);
   LAUNCHCHK(h, "truncate");
-  for (int g = 0; g < ng; g++)
-    HIPCHK(h, hipMemcpyAsync(&sc_pin[g], D[g].sc, sizeof(SlotScalars), hipMemcpyDeviceToHost, st));
+  HIPCHK(h, hipMemcpyAsync(sc_pin, scg, sizeof(SlotScalars) * ng, hipMemcpyDeviceToHost, st));
   HIPCHK(h, hipStreamSynchronize(st));
   prof_drain(h);
   int maxK = 0;
   double wbl_byte = 0.0, wbr_flop = 0.0, wbr_byte = 0.0;
-  const size_t rec0 = h->last_batch.size() - 6 * (size_t)ng;
   for (int g = 0; g < ng; g++) {
     const SlotScalars &sv = sc_pin[g];
     const GateDesc &d = D[g];
-    h->last_batch[rec0 + 6 * g + 4] = sv.k;
-    h->dims[d.i + 1] = sv.k;
-    h->sum_eps += sv.eps;
-    h->prod_keep *= (1.0 - sv.eps);
-    h->n2q += 1;
+    tnsim_mps hg = items[g].h;
+    hg->last_batch[rec_at[g] + 4] = sv.k;
+    hg->dims[d.i + 1] = sv.k;
+    hg->sum_eps += sv.eps;
+    hg->prod_keep *= (1.0 - sv.eps);
+    hg->n2q += 1;
     maxK = std::max(maxK, sv.k);
-    const double eb = c.storage == 0 ? 16.0 : 8.0, tb = d.tfp32 ? 8.0 : 16.0;
+    const double eb = d.storage == 0 ? 16.0 : 8.0, tb = d.tfp32 ? 8.0 : 16.0;
     wbl_byte += (16.0 + eb) * d.m * sv.k;
     wbr_flop += 8.0 * sv.k * d.m * d.n;
     wbr_byte += 16.0 * d.m * sv.k + tb * (double)d.m * d.n + eb * (double)sv.k * d.n;
@@ -517,6 +587,13 @@ tnsim_status run_2q_batch(tnsim_mps h, const Pending *gates, int ng, bool force_
   }
   LAUNCHCHK(h, "write-back");
   return TNSIM_OK;
+}
+
+
+tnsim_status run_2q_batch(tnsim_mps h, const Pending *gates, int ng, bool force_trans = false) {
+  std::vector<BatchItem> items(ng);
+  for (int g = 0; g < ng; g++) items[g] = BatchItem{h, g, &gates[g]};
+  return run_2q_items(h, items.data(), ng, force_trans);
 }
 
 tnsim_status run_2q(tnsim_mps h, const std::vector<Pending> &gs) {
@@ -853,8 +930,7 @@ tnsim_status grad_apply(tnsim_mps h, int gi, GradRec *rec) {
   if (s != TNSIM_OK) return s;
   if (rec) {
     const Layout &L = h->L;
-    const SlotScalars *sc_pin =
-        reinterpret_cast<const SlotScalars *>(h->pin + align_up(sizeof(GateDesc) * L.nslots));
+    const SlotScalars *sc_pin = pin_scalars(h);
     rec->k = sc_pin[0].k;
     rec->N = sc_pin[0].N;
     const int m = 2 * rec->chiL, nn = 2 * rec->chiR, ldj = pad_to(m, 4);
@@ -1069,12 +1145,13 @@ tnsim_status tnsim_mps_create(const tnsim_config *cfg, void *dev_arena, size_t a
   h->arena_bytes = arena_bytes;
   h->stream = (hipStream_t)hip_stream;
   h->device = dev;
+  if (const char *e = getenv("TNSIM_GRAPHS")) h->graphs = atoi(e) != 0;
   if (const char *e = getenv("TNSIM_INNER_SWEEPS")) {
     int v = atoi(e);
     if (v >= 1 && v <= 60) h->inner_sweeps = v;
   }
   const Layout &LL = h->L;
-  h->pin_bytes = align_up(sizeof(GateDesc) * LL.nslots) + align_up(sizeof(SlotScalars) * LL.nslots) +
+  h->pin_bytes = align_up(sizeof(GateDesc) * LL.desc_cap) + align_up(sizeof(SlotScalars) * LL.desc_cap) +
                  align_up(sizeof(Gate1Desc) * LL.n) + 4096;
   if (hipHostMalloc((void **)&h->pin, h->pin_bytes, hipHostMallocDefault) != hipSuccess) {
     delete h;
@@ -1104,6 +1181,7 @@ tnsim_status tnsim_mps_destroy(tnsim_mps h) {
   if (!h) return TNSIM_E_ARG;
   if (!h->poisoned) hipStreamSynchronize(h->stream);
   prof_drain(h);
+  if (h->sweep_exec) hipGraphExecDestroy(h->sweep_exec);
   for (hipEvent_t e : h->evpool) hipEventDestroy(e);
   if (h->pin) hipHostFree(h->pin);
   delete h;
@@ -1152,8 +1230,49 @@ tnsim_status tnsim_apply_layer(tnsim_mps h, const tnsim_gate *gates, int32_t n_g
 tnsim_status tnsim_apply_layer_multi(tnsim_mps const *mps, const tnsim_gate *const *gates,
                                      const int32_t *n_gates, int32_t n_mps) {
   if (!mps || !gates || !n_gates || n_mps < 0) return TNSIM_E_ARG;
+  if (n_mps == 0) return TNSIM_OK;
+  tnsim_mps o = mps[0];
   for (int k = 0; k < n_mps; k++) {
-    tnsim_status s = tnsim_apply_layer(mps[k], gates[k], n_gates[k]);
+    tnsim_status s = check_handle(mps[k]);
+    if (s != TNSIM_OK) return s;
+    if (mps[k]->stream != o->stream || mps[k]->cfg.precision != o->cfg.precision)
+      return TNSIM_E_ARG;
+    for (int j = 0; j < k; j++)
+      if (mps[j] == mps[k]) return TNSIM_E_ARG;
+  }
+  std::vector<std::vector<std::pair<int, const tnsim_c128 *>>> g1(n_mps);
+  std::vector<std::vector<Pending>> g2(n_mps);
+  for (int k = 0; k < n_mps; k++) {
+    tnsim_status s = validate_layer(mps[k], gates[k], n_gates[k], g1[k], g2[k]);
+    if (s != TNSIM_OK) return s;
+  }
+  for (int k = 0; k < n_mps; k++) {
+    mps[k]->last_sweeps = 0;
+    mps[k]->last_batch.clear();
+    tnsim_status s = run_1q(mps[k], g1[k]);
+    if (s != TNSIM_OK) return s;
+  }
+  // every two-qubit gate of every handle in as few batches as the owner's
+  // descriptor capacity and each handle's workspace slots allow
+  std::vector<size_t> next(n_mps, 0);
+  std::vector<int> used(n_mps);
+  std::vector<BatchItem> items;
+  for (;;) {
+    items.clear();
+    std::fill(used.begin(), used.end(), 0);
+    bool more = true;
+    while (more && (int)items.size() < o->L.desc_cap) {
+      more = false;
+      for (int k = 0; k < n_mps && (int)items.size() < o->L.desc_cap; k++) {
+        if (next[k] < g2[k].size() && used[k] < mps[k]->L.nslots) {
+          items.push_back(BatchItem{mps[k], used[k]++, &g2[k][next[k]]});
+          next[k]++;
+          more = true;
+        }
+      }
+    }
+    if (items.empty()) break;
+    tnsim_status s = run_2q_items(o, items.data(), (int)items.size(), false);
     if (s != TNSIM_OK) return s;
   }
   return TNSIM_OK;

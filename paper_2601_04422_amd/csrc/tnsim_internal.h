@@ -40,6 +40,9 @@ struct GateDesc {
   int storage;           // 0 = complex128 sites, 1 = complex64 sites
   int tfp32;             // theta' stored as complex64 (mixed modes)
   int innerSweeps;       // sweep cap of the 64x64 pair solve
+  int gpStride;          // pair blocks per K-split chunk in Gp
+  int pad1;
+  int *dimsDev;          // device bond dimensions of the gate's state (n+1)
   double tol;            // relative off-diagonal tolerance
   double cutoff;         // discarded-weight cutoff
   void *A0, *A1;         // site i, site i+1
@@ -83,12 +86,12 @@ void launch_colnorm(hipStream_t st, const GateDesc *d, int ng, int max_cols);
 void launch_gate_init(hipStream_t st, const GateDesc *d, int ng);
 void launch_begin_sweep(hipStream_t st, const GateDesc *d, int ng);
 void launch_gram(hipStream_t st, const GateDesc *d, int ng, int round, int max_pairs,
-                 int ksplit, int npairs_stride);
-void launch_eig(hipStream_t st, const GateDesc *d, int ng, int round, int max_pairs, int ksplit,
-                int npairs_stride);
+                 int ksplit);
+void launch_eig(hipStream_t st, const GateDesc *d, int ng, int round, int max_pairs, int ksplit);
+void launch_gather_sc(hipStream_t st, const GateDesc *d, int ng, SlotScalars *out);
 void launch_rot(hipStream_t st, const GateDesc *d, int ng, int round, int max_pairs,
                 int max_rows, int max_m);
-void launch_trunc(hipStream_t st, const GateDesc *d, int ng, int *dims_dev);
+void launch_trunc(hipStream_t st, const GateDesc *d, int ng);
 void launch_wb_left(hipStream_t st, const GateDesc *d, int ng, int max_m, int max_k);
 void launch_wb_right(hipStream_t st, const GateDesc *d, int ng, int precision, int max_k,
                      int max_n);

@@ -122,6 +122,16 @@ def pack_gates(gates: Sequence) -> np.ndarray:
     return arr
 
 
+def apply_layer_multi(mpss: Sequence["MPS"], layers: Sequence[Sequence]) -> int:
+    """Layer k of handle k for every handle, two-qubit gates of all handles in
+    shared launches (handle 0 owns the batch; all share one stream)."""
+    packed = [pack_gates(l) for l in layers]
+    hs = (C.c_void_p * len(mpss))(*[m._h for m in mpss])
+    gp = (C.c_void_p * len(mpss))(*[a.ctypes.data for a in packed])
+    ng = np.ascontiguousarray([len(l) for l in layers], dtype=np.int32)
+    return lib().tnsim_apply_layer_multi(hs, gp, ng.ctypes.data, len(mpss))
+
+
 def layerise(gates: Sequence, n: int) -> List[List]:
     """Greedy layering of a gate list (library call), returned as layers."""
     arr = pack_gates(gates)
@@ -141,7 +151,7 @@ class MPS:
 
     def __init__(self, n: int, chi_max: int, cutoff: float = 0.0, precision: str = "fp64",
                  storage: str = "c128", jacobi_max_sweeps: int = 0, jacobi_tol: float = 0.0,
-                 max_layer_gates: int = 0, device: str = "cuda:0"):
+                 max_layer_gates: int = 0, device: str = "cuda:0", stream=None):
         import torch  # device memory and streams only
 
         if not torch.cuda.is_available():
@@ -158,7 +168,10 @@ class MPS:
         self.device = torch.device(device)
         with torch.cuda.device(self.device):
             self.arena = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-            self.stream = torch.cuda.current_stream(self.device)
+            # a non-default stream lets the library capture its Jacobi sweeps in
+            # HIP graphs; the default stream runs them as plain launches
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            torch.cuda.synchronize(self.device)
             h = C.c_void_p()
             st = lib().tnsim_mps_create(C.byref(self.cfg), C.c_void_p(self.arena.data_ptr()),
                                         nbytes, C.c_void_p(self.stream.cuda_stream), C.byref(h))

@@ -1,0 +1,87 @@
+"""Full-size parity: one batched layer at chi = 1024 (and chi = 256) from a
+seeded synthetic left-canonical state, in the launch configuration the
+benchmark times, checked against the CPU oracle on a sampled gate whose three
+bonds are all at full size, and through invariants on every gate.
+
+Sampled-gate comparison is gauge-free: the two-site product A_i' A_{i+1}'
+(= U_k U_k^H theta' / N), the kept count k, the spectrum lambda_i' and the
+discarded weight.  Tolerances: float64 path 1e-10 relative on the product and
+spectrum; split-precision paths 1e-5 (float32-level operands, complex64
+storage), well inside the 1e-6 state-fidelity requirement per gate.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2601_04422_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+N_SITES = 24
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+
+    assert torch.cuda.is_available()
+    from paper_2601_04422_amd import tnsim
+
+    return tnsim
+
+
+def _state(chi, seed):
+    dims = W.saturated_dims(N_SITES, chi)
+    sites, lams = W.random_canonical_mps(N_SITES, dims, seed)
+    return dims, sites, lams
+
+
+def _layer(seed):
+    """CNOTs dressed with seeded single-qubit rotations on the odd bonds."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for j in range(1, N_SITES - 1, 2):
+        a, b, c, d = rng.uniform(0, 2 * np.pi, 4)
+        u0 = W.rz(a) @ W.rx(b)
+        u1 = W.rz(c) @ W.rx(d)
+        out.append((j, j + 1, W.cnot() @ np.kron(u0, u1)))
+    return out
+
+
+def _block(a, b):
+    return np.einsum("asb,btc->astc", a, b).reshape(a.shape[0] * 2, 2 * b.shape[2])
+
+
+@pytest.mark.parametrize("chi,precision,storage,tol", [
+    (1024, "bf16x6", "c64", 1e-5),
+    (1024, "fp64", "c128", 1e-10),
+    (256, "f32acc", "c64", 1e-5),
+])
+def test_full_size_layer_vs_oracle(T, chi, precision, storage, tol):
+    dims, sites, lams = _state(chi, 1000 + chi)
+    layer = _layer(7)
+    m = T.MPS(N_SITES, chi, 1e-12, precision=precision, storage=storage)
+    m.import_state(sites, lams)
+    assert m.apply_layer(layer) == T.OK
+    # invariants on every gate of the layer
+    for (i, _, _) in layer:
+        a = m.site(i).reshape(-1, m.bond_dims()[i])
+        gram = a.conj().T @ a
+        assert np.max(np.abs(gram - np.eye(gram.shape[0]))) < (1e-10 if storage == "c128" else 1e-5)
+        assert abs(np.sum(m.lam(i) ** 2) - 1) < 1e-10
+    # sampled gate with chiL = chiM = chiR = chi, against the oracle
+    i = N_SITES // 2 - 1
+    assert dims[i] == dims[i + 1] == dims[i + 2] == chi
+    g = [x for x in layer if x[0] == i][0][2]
+    O.set_threads(16)
+    o = O.OracleMPS(N_SITES, chi, 1e-12)
+    o.set_state(sites, lams)
+    assert o.apply_2q(i, i + 1, g) == O.OK
+    st = o.stats()
+    assert m.bond_dims()[i] == o.bond_dims()[i] == st["last_k"]
+    lam_g, lam_o = m.lam(i), o.lam(i)
+    assert np.max(np.abs(lam_g - lam_o)) / lam_o[0] < tol
+    pg = _block(m.site(i), m.site(i + 1))
+    po = _block(o.site(i), o.site(i + 1))
+    assert np.linalg.norm(pg - po) / np.linalg.norm(po) < tol
+    assert st["last_eps"] > 0

@@ -217,3 +217,49 @@ def test_mixed_untruncated_amplitudes(T):
     got = gpu_statevector(m)
     assert np.max(np.abs(got - ref)) < 1e-6
     assert 1 - fidelity_dense(got, ref) < 1e-10
+
+
+# ---------------------------------------------------------------- several circuits, one batch
+
+def test_multi_circuit_batch_vs_oracle(T):
+    """Independent circuits of uneven n, depth and chi_max advanced layer by
+    layer with all their two-qubit gates in shared launches."""
+    specs = [(9, 6, 4, 11), (14, 9, 16, 12), (6, 7, 8, 13), (20, 5, 32, 14), (11, 8, 100, 15)]
+    ms, circuits = [], []
+    for k, (n, depth, chi, seed) in enumerate(specs):
+        ms.append(T.MPS(n, chi, 1e-10, max_layer_gates=(64 if k == 0 else 3)))
+        circuits.append(W.brickwork_haar(n, depth, seed))
+    depth_max = max(len(c) for c in circuits)
+    for l in range(depth_max):
+        active = [k for k in range(len(ms)) if l < len(circuits[k])]
+        st = T.apply_layer_multi([ms[k] for k in active], [circuits[k][l] for k in active])
+        assert st == T.OK
+    for k, (n, depth, chi, seed) in enumerate(specs):
+        o = O.OracleMPS(n, chi, 1e-10)
+        o.run_layers(circuits[k])
+        assert list(ms[k].bond_dims()) == list(o.bond_dims())
+        assert 1 - _oracle_fid(ms[k], o) < 1e-10
+        for b in range(n - 1):
+            assert np.max(np.abs(ms[k].lam(b) - o.lam(b))) < 1e-10
+
+
+def test_graph_replay_matches_eager(T):
+    """A non-default stream captures each batch's Jacobi sweep as a HIP graph
+    and replays it once per sweep (with the host's convergence check and
+    other eager work between replays); every result must equal the eager
+    launches bit for bit."""
+    import torch
+
+    n = 16
+    layers = W.brickwork_haar(n, 10, 77)
+    s = torch.cuda.Stream()
+    g = T.MPS(n, 24, 1e-10, stream=s)
+    e = T.MPS(n, 24, 1e-10)
+    for layer in layers:
+        assert g.apply_layer(layer) == T.OK
+        assert e.apply_layer(layer) == T.OK
+        assert g.stats()["last_sweeps"] >= 2
+    for q in range(n):
+        assert np.array_equal(g.site(q), e.site(q))
+    for b in range(n - 1):
+        assert np.array_equal(g.lam(b), e.lam(b))
