@@ -47,7 +47,7 @@ def log(*a):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--prep-layers", type=int, default=20)
     ap.add_argument("--precision", default="bf16x6", choices=["fp64", "f32acc", "bf16x3", "bf16x6"])

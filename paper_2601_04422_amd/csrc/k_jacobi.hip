@@ -188,8 +188,14 @@ __device__ __forceinline__ d4_t mfma64(double a, double b, d4_t c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// Same pair Gram on float64 matrix cores (v_mfma_f64_16x16x4): wavefront w
-// owns the 32x32 quarter (rows 32*(w/2), columns 32*(w%2)) of G as 2x2 tiles.
+// Same pair Gram on float64 matrix cores (v_mfma_f64_16x16x4).  G is
+// Hermitian, so only the 10 upper 16x16 tiles (TI <= TJ) are computed; the
+// pair solve mirrors the lower triangle.  Wavefronts take 3, 3, 2 and 2 tiles.
+__constant__ int kGramTiles[4][3][2] = {{{0, 0}, {0, 1}, {0, 2}},
+                                        {{0, 3}, {1, 1}, {1, 2}},
+                                        {{1, 3}, {2, 2}, {-1, -1}},
+                                        {{2, 3}, {3, 3}, {-1, -1}}};
+
 __global__ __launch_bounds__(256) void k_gram_mfma(const GateDesc *descs, int round,
                                                    int ksplit) {
   const GateDesc &d = descs[blockIdx.y];
@@ -204,15 +210,20 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const GateDesc *descs, int ro
 
   __shared__ double2 Xs[GK][PW + 1];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wp = (wave >> 1) * 32, wq = (wave & 1) * 32, l16 = lane & 15, lg = lane >> 4;
-  d4_t accR[2][2], accI[2][2];
+  const int l16 = lane & 15, lg = lane >> 4;
+  const int nt = wave < 2 ? 3 : 2;
+  int tI[3], tJ[3];
 #pragma unroll
-  for (int i = 0; i < 2; i++)
+  for (int t = 0; t < 3; t++) {
+    tI[t] = kGramTiles[wave][t][0];
+    tJ[t] = kGramTiles[wave][t][1];
+  }
+  d4_t accR[3], accI[3];
 #pragma unroll
-    for (int j = 0; j < 2; j++) {
-      accR[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
-      accI[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
-    }
+  for (int t = 0; t < 3; t++) {
+    accR[t] = d4_t{0.0, 0.0, 0.0, 0.0};
+    accI[t] = d4_t{0.0, 0.0, 0.0, 0.0};
+  }
   const int lcol = tid >> 2, lr = (tid & 3) * 8;
   const double2 *xcol = d.X + (size_t)pair_col(I, J, lcol) * d.ldx;
   for (int r0 = rbeg; r0 < rend; r0 += GK) {
@@ -225,22 +236,18 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const GateDesc *descs, int ro
 #pragma unroll
     for (int kk = 0; kk < GK; kk += 4) {
       const int row = kk + lg;
-      double2 xa[2], xb[2];
-#pragma unroll
-      for (int t = 0; t < 2; t++) {
-        xa[t] = Xs[row][wp + t * 16 + l16];
-        xb[t] = Xs[row][wq + t * 16 + l16];
-      }
       // G_pq = sum_r conj(x_rp) x_rq
 #pragma unroll
-      for (int ti = 0; ti < 2; ti++)
-#pragma unroll
-        for (int tj = 0; tj < 2; tj++) {
-          accR[ti][tj] = mfma64(xa[ti].x, xb[tj].x, accR[ti][tj]);
-          accR[ti][tj] = mfma64(xa[ti].y, xb[tj].y, accR[ti][tj]);
-          accI[ti][tj] = mfma64(xa[ti].x, xb[tj].y, accI[ti][tj]);
-          accI[ti][tj] = mfma64(-xa[ti].y, xb[tj].x, accI[ti][tj]);
+      for (int t = 0; t < 3; t++) {
+        if (t < nt) {
+          const double2 xa = Xs[row][tI[t] * 16 + l16];
+          const double2 xb = Xs[row][tJ[t] * 16 + l16];
+          accR[t] = mfma64(xa.x, xb.x, accR[t]);
+          accR[t] = mfma64(xa.y, xb.y, accR[t]);
+          accI[t] = mfma64(xa.x, xb.y, accI[t]);
+          accI[t] = mfma64(-xa.y, xb.x, accI[t]);
         }
+      }
     }
     __syncthreads();
   }
@@ -250,13 +257,12 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const GateDesc *descs, int ro
   }
   double2 *G = d.Gp + ((size_t)kc * d.gpStride + pairIdx) * (PW * PW);
 #pragma unroll
-  for (int ti = 0; ti < 2; ti++)
-#pragma unroll
-    for (int tj = 0; tj < 2; tj++)
+  for (int t = 0; t < 3; t++)
+    if (t < nt)
 #pragma unroll
       for (int e = 0; e < 4; e++) {
-        int p = wp + ti * 16 + lg + 4 * e, q = wq + tj * 16 + l16;
-        G[p * PW + q] = make_double2(accR[ti][tj][e], accI[ti][tj][e]);
+        int p = tI[t] * 16 + lg + 4 * e, q = tJ[t] * 16 + l16;
+        G[p * PW + q] = make_double2(accR[t][e], accI[t][e]);
       }
 }
 
@@ -287,14 +293,17 @@ __global__ __launch_bounds__(256) void k_eig(const GateDesc *descs, int round, i
   unsigned nrot_local = 0;  // rotations applied by this thread (profiling)
 
   for (int e = tid; e < PW * PW; e += 256) {
+    int r = e / PW, c = e % PW;
+    // the Gram kernels store the upper 16x16 tiles; lower ones are mirrored
+    const bool lower = (r >> 4) > (c >> 4);
+    const int src = lower ? c * PW + r : e;
     double2 s = make_double2(0.0, 0.0);
     for (int kc = 0; kc < ksplit; kc++) {
-      double2 v = d.Gp[((size_t)kc * d.gpStride + pairIdx) * (PW * PW) + e];
+      double2 v = d.Gp[((size_t)kc * d.gpStride + pairIdx) * (PW * PW) + src];
       s.x += v.x;
       s.y += v.y;
     }
-    int r = e / PW, c = e % PW;
-    Gs[r * LDG + c] = s;
+    Gs[r * LDG + c] = lower ? cconj(s) : s;
     Vs[r * LDG + c] = make_double2(r == c ? 1.0 : 0.0, 0.0);
   }
   if (tid == 0) first_rot = 0;
@@ -337,9 +346,16 @@ __global__ __launch_bounds__(256) void k_eig(const GateDesc *descs, int round, i
       __syncthreads();
       if (any_rot) {
         // R = [[c, s e^{i phi}], [-s e^{-i phi}, c]] on columns (p, q);
-        // block (row pair i, column pair j): B <- R_i^H B R_j
-        for (int task = tid; task < (PW / 2) * (PW / 2); task += 256) {
-          const int i = task >> 5, j = task & 31;
+        // block (row pair i, column pair j): B <- R_i^H B R_j.  G stays
+        // Hermitian, so only blocks i <= j are computed and block (j, i) is
+        // written as the conjugate transpose.
+        for (int task = tid; task < (PW / 2) * (PW / 2 + 1) / 2; task += 256) {
+          int i = 0, rem = task;
+          while (rem >= PW / 2 - i) {
+            rem -= PW / 2 - i;
+            i++;
+          }
+          const int j = i + rem;
           if (!ract[i] && !ract[j]) continue;
           const int pi = rp[i], qi = rq[i], pj = rp[j], qj = rq[j];
           double2 b00 = Gs[pi * LDG + pj], b01 = Gs[pi * LDG + qj];
@@ -372,6 +388,12 @@ __global__ __launch_bounds__(256) void k_eig(const GateDesc *descs, int round, i
           Gs[pi * LDG + qj] = b01;
           Gs[qi * LDG + pj] = b10;
           Gs[qi * LDG + qj] = b11;
+          if (i != j) {
+            Gs[pj * LDG + pi] = cconj(b00);
+            Gs[qj * LDG + pi] = cconj(b01);
+            Gs[pj * LDG + qi] = cconj(b10);
+            Gs[qj * LDG + qi] = cconj(b11);
+          }
         }
         // V <- V R (columns)
         for (int task = tid; task < PW * (PW / 2); task += 256) {
@@ -579,6 +601,106 @@ __global__ __launch_bounds__(256) void k_rot_mfma(const GateDesc *descs, int rou
   }
 }
 
+// Pair rotation, variant 2: X operands go straight from global memory into the
+// matrix cores (lanes of a 16-group read 16 consecutive rows of one column, a
+// coalesced segment); only V is staged in LDS, so two workgroups fit per CU.
+// Each workgroup handles RR2 rows; results stay in registers until every
+// wavefront has read its inputs, then overwrite X in place.
+constexpr int RR2 = 256;  // rows per workgroup (V is staged once for all of them)
+
+__global__ __launch_bounds__(256) void k_rot_mfma2(const GateDesc *descs, int round) {
+  const GateDesc &d = descs[blockIdx.y];
+  if (!d.sc->active || round >= d.nblk - 1) return;
+  const int npairs = d.nblk / 2;
+  const int xchunks = (d.rows + RR2 - 1) / RR2;
+  const int jchunks = d.trans ? (d.m + RR2 - 1) / RR2 : 0;
+  const int per = xchunks + jchunks;
+  const int pairIdx = blockIdx.x / per, chunk = blockIdx.x % per;
+  if (pairIdx >= npairs) return;
+  if (!d.pairFlag[pairIdx]) return;
+  int I, J;
+  rr_pair(round, pairIdx, d.nblk, I, J);
+  double2 *base;
+  int ld, nrows, r0;
+  if (chunk < xchunks) {
+    base = d.X;
+    ld = d.ldx;
+    nrows = d.rows;
+    r0 = chunk * RR2;
+  } else {
+    base = d.J;
+    ld = d.ldj;
+    nrows = d.m;
+    r0 = (chunk - xchunks) * RR2;
+  }
+  __shared__ double2 Vs[PW * LDG];  // [k][col]
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32, l16 = lane & 15, lg = lane >> 4;
+  const double2 *V = d.V + (size_t)pairIdx * (PW * PW);
+  for (int e = tid; e < PW * PW; e += 256) Vs[(e / PW) * LDG + e % PW] = V[e];
+  if (tid == 0 && d.ctr) {
+    unsigned long long nr = (unsigned long long)min(RR2, nrows - r0);  // all row blocks
+    atomicAdd(&d.ctr[CTR_ROT_FLOP], 8ull * nr * PW * PW);
+    atomicAdd(&d.ctr[CTR_ROT_BYTE], 32ull * nr * PW + 16ull * PW * PW);
+  }
+  __syncthreads();
+  for (int rb = r0; rb < min(nrows, r0 + RR2); rb += 64) {
+    d4_t accR[2][2], accI[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+      for (int j = 0; j < 2; j++) {
+        accR[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+        accI[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+      }
+    int grow[2];
+#pragma unroll
+    for (int t = 0; t < 2; t++) grow[t] = rb + wr + t * 16 + l16;
+#pragma unroll 4
+    for (int k0 = 0; k0 < PW; k0 += 4) {
+      const int k = k0 + lg;
+      const double2 *xc = base + (size_t)pair_col(I, J, k) * ld;
+      double2 xa[2], vb[2];
+#pragma unroll
+      for (int t = 0; t < 2; t++) {
+        xa[t] = grow[t] < nrows ? xc[grow[t]] : make_double2(0.0, 0.0);
+        vb[t] = Vs[k * LDG + wc + t * 16 + l16];
+      }
+#pragma unroll
+      for (int ti = 0; ti < 2; ti++)
+#pragma unroll
+        for (int tj = 0; tj < 2; tj++) {
+          accR[ti][tj] = mfma64(xa[ti].x, vb[tj].x, accR[ti][tj]);
+          accR[ti][tj] = mfma64(-xa[ti].y, vb[tj].y, accR[ti][tj]);
+          accI[ti][tj] = mfma64(xa[ti].x, vb[tj].y, accI[ti][tj]);
+          accI[ti][tj] = mfma64(xa[ti].y, vb[tj].x, accI[ti][tj]);
+        }
+    }
+    __syncthreads();  // every wavefront has read this block's rows of X
+#pragma unroll
+    for (int ti = 0; ti < 2; ti++)
+#pragma unroll
+      for (int tj = 0; tj < 2; tj++)
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+          int r = rb + wr + ti * 16 + lg + 4 * e, c = wc + tj * 16 + l16;
+          if (r < nrows)
+            base[(size_t)pair_col(I, J, c) * ld + r] =
+                make_double2(accR[ti][tj][e], accI[ti][tj][e]);
+        }
+  }
+}
+
+int g_rot_variant = -1;  // -1: read TNSIM_ROT_KERNEL once ("1" selects the LDS-staged kernel)
+
+static int rot_variant() {
+  if (g_rot_variant < 0) {
+    const char *e = getenv("TNSIM_ROT_KERNEL");
+    g_rot_variant = (e && e[0] == '1') ? 1 : 2;
+  }
+  return g_rot_variant;
+}
+
 int g_jacobi_mfma = -1;  // -1: read TNSIM_JACOBI_KERNELS once
 
 static bool use_mfma() {
@@ -619,7 +741,10 @@ void launch_rot(hipStream_t st, const GateDesc *d, int ng, int round, int max_pa
                 int max_rows, int max_m) {
   if (ng <= 0) return;
   int per = (max_rows + RR - 1) / RR + (max_m + RR - 1) / RR;
-  if (use_mfma())
+  if (use_mfma() && rot_variant() == 2) {
+    int per2 = (max_rows + RR2 - 1) / RR2 + (max_m + RR2 - 1) / RR2;
+    hipLaunchKernelGGL(k_rot_mfma2, dim3(max_pairs * per2, ng), dim3(256), 0, st, d, round);
+  } else if (use_mfma())
     hipLaunchKernelGGL(k_rot_mfma, dim3(max_pairs * per, ng), dim3(256), 0, st, d, round);
   else
     hipLaunchKernelGGL(k_rot, dim3(max_pairs * per, ng), dim3(256), 0, st, d, round);

@@ -211,7 +211,7 @@ struct tnsim_mps_s {
     double flops, bytes;
   };
   bool prof = false;
-  int inner_sweeps = 2;
+  int inner_sweeps = 1;  // one inner sweep per pair solve (outer sweeps finish the job)
   std::vector<int32_t> last_batch;  // 6 ints per two-qubit gate of the last apply call
   GradState grad;
   // captured Jacobi sweep (reused while the batch shape is unchanged)
