@@ -226,13 +226,23 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const GateDesc *descs, int ro
   }
   const int lcol = tid >> 2, lr = (tid & 3) * 8;
   const double2 *xcol = d.X + (size_t)pair_col(I, J, lcol) * d.ldx;
+  double2 pre[8];  // next row tile, loaded while the current one is multiplied
+#pragma unroll
+  for (int j = 0; j < 8; j++) {
+    int r = rbeg + lr + j;
+    pre[j] = r < rend ? xcol[r] : make_double2(0.0, 0.0);
+  }
   for (int r0 = rbeg; r0 < rend; r0 += GK) {
 #pragma unroll
-    for (int j = 0; j < 8; j++) {
-      int r = r0 + lr + j;
-      Xs[lr + j][lcol] = r < rend ? xcol[r] : make_double2(0.0, 0.0);
-    }
+    for (int j = 0; j < 8; j++) Xs[lr + j][lcol] = pre[j];
     __syncthreads();
+    if (r0 + GK < rend) {
+#pragma unroll
+      for (int j = 0; j < 8; j++) {
+        int r = r0 + GK + lr + j;
+        pre[j] = r < rend ? xcol[r] : make_double2(0.0, 0.0);
+      }
+    }
 #pragma unroll
     for (int kk = 0; kk < GK; kk += 4) {
       const int row = kk + lg;
@@ -269,6 +279,7 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const GateDesc *descs, int ro
 // ---------------------------------------------------------------- 64x64 Hermitian Jacobi
 
 constexpr int LDG = PW + 1;
+constexpr int EIG_THREADS = 512;  // 8 wavefronts hide the LDS latency of the pair solve
 
 // Cyclic two-sided Jacobi on the pair Gram G (64x64, in LDS) with the
 // rotations accumulated in V.  A round applies the 32 disjoint rotations of
@@ -276,7 +287,7 @@ constexpr int LDG = PW + 1;
 // updated as 2x2 blocks (rows of one pair x columns of another), so every
 // entry is read and written once per round.  At most `inner_sweeps` sweeps;
 // the outer sweeps finish what a capped inner solve leaves.
-__global__ __launch_bounds__(256) void k_eig(const GateDesc *descs, int round, int ksplit) {
+__global__ __launch_bounds__(EIG_THREADS) void k_eig(const GateDesc *descs, int round, int ksplit) {
   const GateDesc &d = descs[blockIdx.y];
   const int pairIdx = blockIdx.x;
   if (!d.sc->active || round >= d.nblk - 1 || pairIdx >= d.nblk / 2) return;
@@ -292,7 +303,7 @@ __global__ __launch_bounds__(256) void k_eig(const GateDesc *descs, int round, i
   const double small = small_norm2(d);
   unsigned nrot_local = 0;  // rotations applied by this thread (profiling)
 
-  for (int e = tid; e < PW * PW; e += 256) {
+  for (int e = tid; e < PW * PW; e += EIG_THREADS) {
     int r = e / PW, c = e % PW;
     // the Gram kernels store the upper 16x16 tiles; lower ones are mirrored
     const bool lower = (r >> 4) > (c >> 4);
@@ -346,16 +357,9 @@ __global__ __launch_bounds__(256) void k_eig(const GateDesc *descs, int round, i
       __syncthreads();
       if (any_rot) {
         // R = [[c, s e^{i phi}], [-s e^{-i phi}, c]] on columns (p, q);
-        // block (row pair i, column pair j): B <- R_i^H B R_j.  G stays
-        // Hermitian, so only blocks i <= j are computed and block (j, i) is
-        // written as the conjugate transpose.
-        for (int task = tid; task < (PW / 2) * (PW / 2 + 1) / 2; task += 256) {
-          int i = 0, rem = task;
-          while (rem >= PW / 2 - i) {
-            rem -= PW / 2 - i;
-            i++;
-          }
-          const int j = i + rem;
+        // block (row pair i, column pair j): B <- R_i^H B R_j
+        for (int task = tid; task < (PW / 2) * (PW / 2); task += EIG_THREADS) {
+          const int i = task >> 5, j = task & 31;
           if (!ract[i] && !ract[j]) continue;
           const int pi = rp[i], qi = rq[i], pj = rp[j], qj = rq[j];
           double2 b00 = Gs[pi * LDG + pj], b01 = Gs[pi * LDG + qj];
@@ -388,15 +392,9 @@ __global__ __launch_bounds__(256) void k_eig(const GateDesc *descs, int round, i
           Gs[pi * LDG + qj] = b01;
           Gs[qi * LDG + pj] = b10;
           Gs[qi * LDG + qj] = b11;
-          if (i != j) {
-            Gs[pj * LDG + pi] = cconj(b00);
-            Gs[qj * LDG + pi] = cconj(b01);
-            Gs[pj * LDG + qi] = cconj(b10);
-            Gs[qj * LDG + qi] = cconj(b11);
-          }
         }
         // V <- V R (columns)
-        for (int task = tid; task < PW * (PW / 2); task += 256) {
+        for (int task = tid; task < PW * (PW / 2); task += EIG_THREADS) {
           const int j = task & 31, row = task >> 5;
           if (!ract[j]) continue;
           const int pj = rp[j], qj = rq[j];
@@ -429,7 +427,7 @@ __global__ __launch_bounds__(256) void k_eig(const GateDesc *descs, int round, i
   }
   if (first_rot) {
     double2 *V = d.V + (size_t)pairIdx * (PW * PW);
-    for (int e = tid; e < PW * PW; e += 256) V[e] = Vs[(e / PW) * LDG + e % PW];
+    for (int e = tid; e < PW * PW; e += EIG_THREADS) V[e] = Vs[(e / PW) * LDG + e % PW];
   }
 }
 
@@ -723,7 +721,7 @@ void launch_gram(hipStream_t st, const GateDesc *d, int ng, int round, int max_p
 
 void launch_eig(hipStream_t st, const GateDesc *d, int ng, int round, int max_pairs, int ksplit) {
   if (ng <= 0) return;
-  hipLaunchKernelGGL(k_eig, dim3(max_pairs, ng), dim3(256), 0, st, d, round, ksplit);
+  hipLaunchKernelGGL(k_eig, dim3(max_pairs, ng), dim3(EIG_THREADS), 0, st, d, round, ksplit);
 }
 
 // Copy every gate's scalars into one array (one device-to-host copy per sweep).
