@@ -50,6 +50,15 @@ __device__ __forceinline__ int pair_col(int I, int J, int p) {
   return p < BW ? I * BW + p : J * BW + (p - BW);
 }
 
+// A block pair that tested orthogonal and whose two blocks have not been
+// rotated since has the same Gram matrix as then, so it would test orthogonal
+// again: its Gram and pair solve are skipped (the result is unchanged).
+__device__ __forceinline__ bool pair_known_orthogonal(const GateDesc &d, int I, int J) {
+  if (!d.blkVer) return false;
+  const int2 s = d.pairSeen[I * d.nblk + J];
+  return s.x == d.blkVer[I] && s.y == d.blkVer[J];
+}
+
 // ---------------------------------------------------------------- setup
 
 // Zero X's padding columns; J = identity (trans gates).
@@ -89,9 +98,15 @@ void launch_colnorm(hipStream_t st, const GateDesc *d, int ng, int max_cols) {
   hipLaunchKernelGGL(k_colnorm, dim3((max_cols + 3) / 4, ng), dim3(256), 0, st, d);
 }
 
-// ||X||_F^2 in a fixed order; all gates start active.
+// ||X||_F^2 in a fixed order; all gates start active; no block pair is known
+// orthogonal yet.
 __global__ void k_gate_init(const GateDesc *descs) {
   const GateDesc &d = descs[blockIdx.x];
+  if (d.blkVer) {
+    for (int b = threadIdx.x; b < d.nblk; b += blockDim.x) d.blkVer[b] = 0;
+    for (int e = threadIdx.x; e < d.nblk * d.nblk; e += blockDim.x)
+      d.pairSeen[e] = make_int2(-1, -1);
+  }
   if (threadIdx.x == 0) {
     double s = 0.0;
     for (int j = 0; j < d.cols; j++) s += d.sig2[j];
@@ -131,6 +146,7 @@ __global__ __launch_bounds__(256) void k_gram(const GateDesc *descs, int round, 
   if (!d.sc->active || round >= d.nblk - 1 || pairIdx >= d.nblk / 2) return;
   int I, J;
   rr_pair(round, pairIdx, d.nblk, I, J);
+  if (pair_known_orthogonal(d, I, J)) return;
   int chunk = (d.rows + ksplit - 1) / ksplit;
   chunk = (chunk + GK - 1) / GK * GK;
   const int rbeg = kc * chunk;
@@ -203,6 +219,7 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const GateDesc *descs, int ro
   if (!d.sc->active || round >= d.nblk - 1 || pairIdx >= d.nblk / 2) return;
   int I, J;
   rr_pair(round, pairIdx, d.nblk, I, J);
+  if (pair_known_orthogonal(d, I, J)) return;
   int chunk = (d.rows + ksplit - 1) / ksplit;
   chunk = (chunk + GK - 1) / GK * GK;
   const int rbeg = kc * chunk;
@@ -291,6 +308,12 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(const GateDesc *descs, int 
   const GateDesc &d = descs[blockIdx.y];
   const int pairIdx = blockIdx.x;
   if (!d.sc->active || round >= d.nblk - 1 || pairIdx >= d.nblk / 2) return;
+  int I, J;
+  rr_pair(round, pairIdx, d.nblk, I, J);
+  if (pair_known_orthogonal(d, I, J)) {
+    if (threadIdx.x == 0) d.pairFlag[pairIdx] = 0;
+    return;
+  }
   __shared__ double2 Gs[PW * LDG];
   __shared__ double2 Vs[PW * LDG];
   __shared__ double rc[PW / 2];    // cos
@@ -424,6 +447,14 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(const GateDesc *descs, int 
   if (tid == 0) {
     d.pairFlag[pairIdx] = first_rot;
     if (first_rot) atomicOr(&d.sc->rot, 1);
+    if (d.blkVer) {  // only this workgroup touches blocks I and J during the round
+      if (first_rot) {
+        d.blkVer[I] += 1;
+        d.blkVer[J] += 1;
+      } else {
+        d.pairSeen[I * d.nblk + J] = make_int2(d.blkVer[I], d.blkVer[J]);
+      }
+    }
   }
   if (first_rot) {
     double2 *V = d.V + (size_t)pairIdx * (PW * PW);
@@ -602,14 +633,16 @@ __global__ __launch_bounds__(256) void k_rot_mfma(const GateDesc *descs, int rou
 // Pair rotation, variant 2: X operands go straight from global memory into the
 // matrix cores (lanes of a 16-group read 16 consecutive rows of one column, a
 // coalesced segment); only V is staged in LDS, so two workgroups fit per CU.
-// Each workgroup handles RR2 rows; results stay in registers until every
-// wavefront has read its inputs, then overwrite X in place.
-constexpr int RR2 = 256;  // rows per workgroup (V is staged once for all of them)
+// Each workgroup handles d.rotRows rows (V is staged once for all of them:
+// 256 when the batch fills the GPU, fewer when only a few pairs are left);
+// results stay in registers until every wavefront has read its inputs, then
+// overwrite X in place.
 
 __global__ __launch_bounds__(256) void k_rot_mfma2(const GateDesc *descs, int round) {
   const GateDesc &d = descs[blockIdx.y];
   if (!d.sc->active || round >= d.nblk - 1) return;
   const int npairs = d.nblk / 2;
+  const int RR2 = d.rotRows;
   const int xchunks = (d.rows + RR2 - 1) / RR2;
   const int jchunks = d.trans ? (d.m + RR2 - 1) / RR2 : 0;
   const int per = xchunks + jchunks;
@@ -736,11 +769,11 @@ void launch_gather_sc(hipStream_t st, const GateDesc *d, int ng, SlotScalars *ou
 }
 
 void launch_rot(hipStream_t st, const GateDesc *d, int ng, int round, int max_pairs,
-                int max_rows, int max_m) {
+                int max_rows, int max_m, int rot_rows) {
   if (ng <= 0) return;
   int per = (max_rows + RR - 1) / RR + (max_m + RR - 1) / RR;
   if (use_mfma() && rot_variant() == 2) {
-    int per2 = (max_rows + RR2 - 1) / RR2 + (max_m + RR2 - 1) / RR2;
+    int per2 = (max_rows + rot_rows - 1) / rot_rows + (max_m + rot_rows - 1) / rot_rows;
     hipLaunchKernelGGL(k_rot_mfma2, dim3(max_pairs * per2, ng), dim3(256), 0, st, d, round);
   } else if (use_mfma())
     hipLaunchKernelGGL(k_rot_mfma, dim3(max_pairs * per, ng), dim3(256), 0, st, d, round);

@@ -31,8 +31,8 @@ struct Layout {
   size_t dims_off = 0, site_tab_off = 0, lam_tab_off = 0;
   int cmax = 0, ldx_max = 0, cols_pad_max = 0, npairs_max = 0, gp_blocks = 0;
   size_t slot_bytes = 0, slot0_off = 0;
-  size_t x_off = 0, j_off = 0, t_off = 0, v_off = 0, pf_off = 0, sig_off = 0, perm_off = 0,
-         sc_off = 0;  // within a slot
+  size_t x_off = 0, j_off = 0, t_off = 0, v_off = 0, pf_off = 0, ver_off = 0, seen_off = 0,
+         sig_off = 0, perm_off = 0, sc_off = 0;  // within a slot
   size_t gp_off = 0;  // pooled pair-Gram partials
   size_t desc_off = 0, d1_off = 0, ctr_off = 0, scg_off = 0;
   size_t e0_off = 0, e1_off = 0, f_off = 0, f2_off = 0, va_off = 0, vb_off = 0;
@@ -106,6 +106,10 @@ Layout make_layout(const tnsim_config &c) {
   s = align_up(s + sizeof(double2) * (size_t)L.npairs_max * PW * PW);
   L.pf_off = s;
   s = align_up(s + sizeof(int) * L.npairs_max);
+  L.ver_off = s;
+  s = align_up(s + sizeof(int) * 2 * L.npairs_max);
+  L.seen_off = s;
+  s = align_up(s + sizeof(int2) * 4 * (size_t)L.npairs_max * L.npairs_max);
   L.sig_off = s;
   s = align_up(s + sizeof(double) * L.cols_pad_max);
   L.perm_off = s;
@@ -216,8 +220,9 @@ struct tnsim_mps_s {
   GradState grad;
   // captured Jacobi sweep (reused while the batch shape is unchanged)
   bool graphs = true;
+  bool pair_skip = true;  // skip Grams of block pairs known orthogonal (TNSIM_PAIR_SKIP=0: off)
   hipGraphExec_t sweep_exec = nullptr;
-  long long sweep_key[6] = {-1, -1, -1, -1, -1, -1};
+  long long sweep_key[7] = {-1, -1, -1, -1, -1, -1, -1};
   int64_t sw_gates = 0, sw_sum = 0;
   int sw_max = 0;
   std::vector<hipEvent_t> evpool;
@@ -350,8 +355,7 @@ SlotScalars *pin_scalars(tnsim_mps o) {
 tnsim_status run_2q_items(tnsim_mps o, const BatchItem *items, int ng, bool force_trans) {
   const tnsim_config &c = o->cfg;
   std::vector<GateDesc> D(ng);
-  int maxM = 0, maxN = 0, maxRows = 0, maxColsPad = 0, maxPairs = 0, maxChiR = 0, maxNblk = 0;
-  int maxMtrans = 0;
+  int maxM = 0, maxN = 0, maxColsPad = 0, maxChiR = 0;
   for (int g = 0; g < ng; g++) {
     GateDesc &d = D[g];
     memset(&d, 0, sizeof d);
@@ -389,6 +393,8 @@ tnsim_status run_2q_items(tnsim_mps o, const BatchItem *items, int ng, bool forc
     d.T = sl + L.t_off;
     d.V = (double2 *)(sl + L.v_off);
     d.pairFlag = (int *)(sl + L.pf_off);
+    d.blkVer = o->pair_skip ? (int *)(sl + L.ver_off) : nullptr;
+    d.pairSeen = o->pair_skip ? (int2 *)(sl + L.seen_off) : nullptr;
     d.sig2 = (double *)(sl + L.sig_off);
     d.perm = (int *)(sl + L.perm_off);
     d.sc = (SlotScalars *)(sl + L.sc_off);
@@ -397,29 +403,9 @@ tnsim_status run_2q_items(tnsim_mps o, const BatchItem *items, int ng, bool forc
     d.dimsDev = h->dims_dev();
     maxM = std::max(maxM, d.m);
     maxN = std::max(maxN, d.n);
-    maxRows = std::max(maxRows, d.rows);
     maxColsPad = std::max(maxColsPad, d.colsPad);
-    maxPairs = std::max(maxPairs, d.nblk / 2);
-    maxNblk = std::max(maxNblk, d.nblk);
     maxChiR = std::max(maxChiR, d.chiR);
-    if (d.trans) maxMtrans = std::max(maxMtrans, d.m);
   }
-  // Split the row dimension of the pair Grams when the batch alone cannot
-  // fill the GPU.
-  int ksplit = (1024 + ng * maxPairs - 1) / (ng * maxPairs);
-  ksplit = std::min(ksplit, KSPLIT_MAX);
-  ksplit = std::min(ksplit, std::max(1, (maxRows + 31) / 32));
-  for (int g = 0; g < ng; g++) {  // each gate's partials fit its handle's pool
-    const Layout &L = items[g].h->L;
-    ksplit = std::min(ksplit, std::max(1, L.gp_blocks / ((items[g].slot + 1) * L.npairs_max)));
-  }
-  ksplit = std::max(ksplit, 1);
-  for (int g = 0; g < ng; g++) {
-    const tnsim_mps h = items[g].h;
-    D[g].Gp = h->at<double2>(h->L.gp_off) +
-              (size_t)items[g].slot * ksplit * h->L.npairs_max * PW * PW;
-  }
-
   unsigned long long *ctr = o->prof ? o->at<unsigned long long>(o->L.ctr_off) : nullptr;
   double theta_flop = 0.0, theta_byte = 0.0, colnorm_byte = 0.0;
   for (int g = 0; g < ng; g++) {
@@ -463,74 +449,146 @@ tnsim_status run_2q_items(tnsim_mps o, const BatchItem *items, int ng, bool forc
   bool converged = false;
   int sweeps = 0;
   std::vector<int> done_at(ng, 0);
+
+  // Launch plan of the sweeps: only the gates still sweeping are launched
+  // (their descriptors packed at the front of the descriptor array), and the
+  // row dimension of the pair Grams (K-split) and of the rotations is cut
+  // finer when those gates alone cannot fill the GPU.
+  struct Plan {
+    int na = 0, maxPairs = 0, maxNblk = 0, maxRows = 0, maxMtrans = 0, ksplit = 1, rotRows = 256;
+  } P;
+  std::vector<int> act(ng);
+  for (int g = 0; g < ng; g++) act[g] = g;
+  auto make_plan = [&]() -> tnsim_status {
+    P = Plan{};
+    P.na = (int)act.size();
+    for (int g : act) {
+      const GateDesc &d = D[g];
+      P.maxPairs = std::max(P.maxPairs, d.nblk / 2);
+      P.maxNblk = std::max(P.maxNblk, d.nblk);
+      P.maxRows = std::max(P.maxRows, d.rows);
+      if (d.trans) P.maxMtrans = std::max(P.maxMtrans, d.m);
+    }
+    const int pairs = P.na * P.maxPairs;
+    int ks = (1024 + pairs - 1) / pairs;
+    ks = std::min(ks, KSPLIT_MAX);
+    ks = std::min(ks, std::max(1, (P.maxRows + 31) / 32));
+    // each gate's partials go to its handle's pool, at its position among the
+    // active gates of that handle
+    std::vector<int> pos(act.size());
+    for (size_t a = 0; a < act.size(); a++) {
+      int p = 0;
+      for (size_t b = 0; b < a; b++) p += items[act[b]].h == items[act[a]].h;
+      pos[a] = p;
+      const Layout &L = items[act[a]].h->L;
+      ks = std::min(ks, std::max(1, L.gp_blocks / ((p + 1) * L.npairs_max)));
+    }
+    P.ksplit = std::max(ks, 1);
+    const int rchunks = std::max(1, P.maxRows + P.maxMtrans);
+    while (P.rotRows > 64 && (long long)pairs * ((rchunks + P.rotRows - 1) / P.rotRows) < 1024)
+      P.rotRows /= 2;
+    GateDesc *stage = reinterpret_cast<GateDesc *>(o->pin);
+    for (size_t a = 0; a < act.size(); a++) {
+      const tnsim_mps hg = items[act[a]].h;
+      stage[a] = D[act[a]];
+      stage[a].Gp = hg->at<double2>(hg->L.gp_off) +
+                    (size_t)pos[a] * P.ksplit * hg->L.npairs_max * PW * PW;
+      stage[a].rotRows = P.rotRows;
+    }
+    HIPCHK(o, hipMemcpyAsync(ddev, o->pin, sizeof(GateDesc) * P.na, hipMemcpyHostToDevice, st));
+    return TNSIM_OK;
+  };
+
   // One sweep: every round of the round-robin tournament, then the scalars
   // gathered for the host's convergence test.  With a non-default stream and
-  // profiling off, the sweep is captured once as a HIP graph and replayed.
+  // profiling off, the sweep is captured once per plan as a HIP graph and
+  // replayed.
   auto enqueue_sweep = [&]() {
     {
       ProfScope p(h, TNSIM_K_OTHER);
-      launch_begin_sweep(st, ddev, ng);
+      launch_begin_sweep(st, ddev, P.na);
     }
-    for (int r = 0; r < maxNblk - 1; r++) {
+    for (int r = 0; r < P.maxNblk - 1; r++) {
       {
         ProfScope p(h, TNSIM_K_GRAM);
-        launch_gram(st, ddev, ng, r, maxPairs, ksplit);
+        launch_gram(st, ddev, P.na, r, P.maxPairs, P.ksplit);
       }
       {
         ProfScope p(h, TNSIM_K_EIG);
-        launch_eig(st, ddev, ng, r, maxPairs, ksplit);
+        launch_eig(st, ddev, P.na, r, P.maxPairs, P.ksplit);
       }
       {
         ProfScope p(h, TNSIM_K_ROT);
-        launch_rot(st, ddev, ng, r, maxPairs, maxRows, maxMtrans);
+        launch_rot(st, ddev, P.na, r, P.maxPairs, P.maxRows, P.maxMtrans, P.rotRows);
       }
     }
-    launch_gather_sc(st, ddev, ng, scg);
+    launch_gather_sc(st, ddev, P.na, scg);
   };
   const bool use_graph = h->graphs && !h->prof && st != nullptr;
-  if (use_graph) {
-    const long long key[6] = {ng, maxPairs, ksplit, maxNblk, maxRows, maxMtrans};
-    if (!h->sweep_exec || memcmp(key, h->sweep_key, sizeof key) != 0) {
-      if (h->sweep_exec) {
-        hipGraphExecDestroy(h->sweep_exec);
-        h->sweep_exec = nullptr;
-      }
-      hipGraph_t graph = nullptr;
-      HIPCHK(h, hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
-      enqueue_sweep();
-      hipError_t e1 = hipGetLastError();
-      hipError_t e2 = hipStreamEndCapture(st, &graph);
-      if (e1 != hipSuccess) return fail(h, e1, "sweep capture");
-      if (e2 != hipSuccess) return fail(h, e2, "hipStreamEndCapture");
-      hipError_t e3 = hipGraphInstantiate(&h->sweep_exec, graph, nullptr, nullptr, 0);
-      hipGraphDestroy(graph);
-      if (e3 != hipSuccess) {
-        h->sweep_exec = nullptr;
-        return fail(h, e3, "hipGraphInstantiate");
-      }
-      memcpy(h->sweep_key, key, sizeof key);
+  auto prepare_graph = [&]() -> tnsim_status {
+    const long long key[7] = {P.na, P.maxPairs, P.ksplit, P.maxNblk, P.maxRows, P.maxMtrans,
+                              P.rotRows};
+    if (h->sweep_exec && memcmp(key, h->sweep_key, sizeof key) == 0) return TNSIM_OK;
+    if (h->sweep_exec) {
+      hipGraphExecDestroy(h->sweep_exec);
+      h->sweep_exec = nullptr;
     }
-  }
+    hipGraph_t graph = nullptr;
+    HIPCHK(h, hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+    enqueue_sweep();
+    hipError_t e1 = hipGetLastError();
+    hipError_t e2 = hipStreamEndCapture(st, &graph);
+    if (e1 != hipSuccess) return fail(h, e1, "sweep capture");
+    if (e2 != hipSuccess) return fail(h, e2, "hipStreamEndCapture");
+    hipError_t e3 = hipGraphInstantiate(&h->sweep_exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e3 != hipSuccess) {
+      h->sweep_exec = nullptr;
+      return fail(h, e3, "hipGraphInstantiate");
+    }
+    memcpy(h->sweep_key, key, sizeof key);
+    return TNSIM_OK;
+  };
+
+  tnsim_status ps = make_plan();
+  if (ps != TNSIM_OK) return ps;
   for (int sweep = 1; sweep <= max_sweeps; sweep++) {
-    if (use_graph)
+    if (use_graph) {
+      tnsim_status gs = prepare_graph();
+      if (gs != TNSIM_OK) return gs;
       HIPCHK(h, hipGraphLaunch(h->sweep_exec, st));
-    else
+    } else {
       enqueue_sweep();
+    }
     LAUNCHCHK(h, "jacobi round");
-    HIPCHK(h, hipMemcpyAsync(sc_pin, scg, sizeof(SlotScalars) * ng, hipMemcpyDeviceToHost, st));
+    HIPCHK(h, hipMemcpyAsync(sc_pin, scg, sizeof(SlotScalars) * P.na, hipMemcpyDeviceToHost, st));
     HIPCHK(h, hipStreamSynchronize(st));
     prof_drain(h);
     sweeps = sweep;
-    bool any = false;
-    for (int g = 0; g < ng; g++) {
-      any |= sc_pin[g].rot != 0;
-      if (!sc_pin[g].rot && !done_at[g]) done_at[g] = sweep;
+    std::vector<int> still;
+    for (int a = 0; a < P.na; a++) {
+      if (sc_pin[a].rot)
+        still.push_back(act[a]);
+      else if (!done_at[act[a]])
+        done_at[act[a]] = sweep;
     }
-    if (!any) {
+    if (still.empty()) {
       converged = true;
       break;
     }
+    // re-plan once the active set has shrunk by a quarter (a converged gate
+    // left in the plan only costs early-exiting workgroups)
+    if (4 * (int)still.size() <= 3 * P.na) {
+      act.swap(still);
+      ps = make_plan();
+      if (ps != TNSIM_OK) return ps;
+    }
   }
+  // the descriptors of the whole batch again, for the truncation and write-back
+  // (the staging buffer is free once the stream is idle)
+  HIPCHK(h, hipStreamSynchronize(st));
+  memcpy(h->pin, D.data(), sizeof(GateDesc) * ng);
+  HIPCHK(h, hipMemcpyAsync(ddev, h->pin, sizeof(GateDesc) * ng, hipMemcpyHostToDevice, st));
   std::vector<size_t> rec_at(ng);
   for (int g = 0; g < ng; g++) {
     tnsim_mps hg = items[g].h;
@@ -1146,6 +1204,7 @@ tnsim_status tnsim_mps_create(const tnsim_config *cfg, void *dev_arena, size_t a
   h->stream = (hipStream_t)hip_stream;
   h->device = dev;
   if (const char *e = getenv("TNSIM_GRAPHS")) h->graphs = atoi(e) != 0;
+  if (const char *e = getenv("TNSIM_PAIR_SKIP")) h->pair_skip = atoi(e) != 0;
   if (const char *e = getenv("TNSIM_INNER_SWEEPS")) {
     int v = atoi(e);
     if (v >= 1 && v <= 60) h->inner_sweeps = v;

@@ -41,7 +41,7 @@ struct GateDesc {
   int tfp32;             // theta' stored as complex64 (mixed modes)
   int innerSweeps;       // sweep cap of the 64x64 pair solve
   int gpStride;          // pair blocks per K-split chunk in Gp
-  int pad1;
+  int rotRows;           // rows of X (and J) per rotation workgroup, a multiple of 64
   int *dimsDev;          // device bond dimensions of the gate's state (n+1)
   double tol;            // relative off-diagonal tolerance
   double cutoff;         // discarded-weight cutoff
@@ -52,6 +52,9 @@ struct GateDesc {
   void *T;               // theta' (m x n, row-major)
   double2 *Gp, *V;       // pair Gram partials, pair rotations
   int *pairFlag;         // pair rotated in this round
+  int *blkVer;           // per column block: number of rotations applied to it so far
+  int2 *pairSeen;        // per block pair (I * nblk + J): block versions when the pair
+                         // last tested orthogonal, or (-1, -1)
   double *sig2;          // column norms squared
   int *perm;             // columns sorted by descending norm
   SlotScalars *sc;
@@ -90,7 +93,7 @@ void launch_gram(hipStream_t st, const GateDesc *d, int ng, int round, int max_p
 void launch_eig(hipStream_t st, const GateDesc *d, int ng, int round, int max_pairs, int ksplit);
 void launch_gather_sc(hipStream_t st, const GateDesc *d, int ng, SlotScalars *out);
 void launch_rot(hipStream_t st, const GateDesc *d, int ng, int round, int max_pairs,
-                int max_rows, int max_m);
+                int max_rows, int max_m, int rot_rows);
 void launch_trunc(hipStream_t st, const GateDesc *d, int ng);
 void launch_wb_left(hipStream_t st, const GateDesc *d, int ng, int max_m, int max_k);
 void launch_wb_right(hipStream_t st, const GateDesc *d, int ng, int precision, int max_k,
