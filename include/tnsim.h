@@ -94,6 +94,13 @@ typedef struct {
   int32_t jacobi_max_sweeps; /* <= 0 selects 60 */
   double jacobi_tol;         /* <= 0 selects max(rows, 16) * 2^-53 */
   int32_t max_layer_gates;   /* two-qubit gates processed together; <= 0 selects n/2 */
+  /* 0: one-sided Jacobi on M.  1: QR preconditioning before the Jacobi
+     (Drmac and Veselic, SIAM J. Matrix Anal. Appl. 29(4), 2008): M = Q1 R1,
+     R1^H = Q2 R2 by blocked Householder QR in float64, one-sided Jacobi on
+     R2^H = W S V^H, left vectors U = Q1 W; it takes about half the Jacobi
+     sweeps.  Used for gates with 2 chiR <= 2 chiL <= 2048 and no recorded
+     adjoint; other gates take the plain path. */
+  int32_t svd_precondition;
 } tnsim_config;
 
 typedef struct {
@@ -222,6 +229,7 @@ typedef enum {
   TNSIM_K_WB_RIGHT,  /* right-site write-back */
   TNSIM_K_1Q,        /* one-qubit gates */
   TNSIM_K_OTHER,     /* setup, sweep control */
+  TNSIM_K_QR,        /* QR preconditioning: Householder panels, updates, Q1 W */
   TNSIM_K_COUNT
 } tnsim_kernel_class;
 

@@ -55,13 +55,19 @@ __device__ void theta_epilogue(const GateDesc &d, int r0, int c0, double2 *Cs) {
     }
   }
   if (!d.trans) {
-    // X = M, column-major: coalesced along rows
+    // M goes to Qm when the SVD is QR-preconditioned, else it is X itself.
+    double2 *Xt = d.qr ? d.Qm : d.X;
+    const int ldt = d.qr ? d.ldq : d.ldx;
+    // X = M with its columns in the order (c, t) instead of M's (t, c):
+    // lambda_{i+1} is sorted, so neighbouring columns then carry weights of
+    // the same size, which saves the block Jacobi one or two sweeps (the SVD
+    // does not depend on the column order).  Column-major, coalesced along rows.
     for (int task = tid; task < TM * 2 * TC; task += 256) {
       int r = task % TM, jj = task / TM;
       int t = jj / TC, c = c0 + jj % TC, gr = r0 + r;
       if (gr < m && c < chiR) {
         double w = d.lamR ? d.lamR[c] : 1.0;
-        d.X[(size_t)(t * chiR + c) * d.ldx + gr] = cscale(Cs[r * LD + jj], w);
+        Xt[(size_t)(2 * c + t) * ldt + gr] = cscale(Cs[r * LD + jj], w);
       }
     }
   } else {

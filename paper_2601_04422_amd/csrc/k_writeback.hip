@@ -5,9 +5,9 @@
 //   A_i'[a,s,j]     = u_j[2a+s]                        j < k
 //   A_{i+1}'[j,t,c] = (1/N) sum_{a,s} conj(u_j[2a+s]) theta'[a,s,t,c]
 //
-// u_j is column perm[j] of X divided by its norm (X = M), or column perm[j]
-// of J (X = M^H).  Using theta' rather than M keeps lambda_{i+1} from being
-// divided out.
+// u_j is column perm[j] of X divided by its norm (X = M), column perm[j] of
+// J (X = M^H), or column j of U (QR-preconditioned SVD, U = Q1 [W_k; 0]).
+// Using theta' rather than M keeps lambda_{i+1} from being divided out.
 #include "tnsim_internal.h"
 #include "tn_complex.h"
 #include "tn_mfma.h"
@@ -15,7 +15,14 @@
 namespace tn {
 
 __device__ __forceinline__ double2 left_vec(const GateDesc &d, int r, int col, double inv) {
+  if (d.qr) return d.U[(size_t)col * d.ldu + r];
   return d.trans ? d.J[(size_t)col * d.ldj + r] : cscale(d.X[(size_t)col * d.ldx + r], inv);
+}
+
+// Which stored column holds u_j, and the factor that normalises it.
+__device__ __forceinline__ int left_col(const GateDesc &d, int j) { return d.qr ? j : d.perm[j]; }
+__device__ __forceinline__ double left_inv(const GateDesc &d, int col) {
+  return (d.trans || d.qr) ? 1.0 : 1.0 / sqrt(d.sig2[col]);
 }
 
 // grid: (m tiles of 64, k tiles of 64, gate)
@@ -28,8 +35,8 @@ __device__ void wb_left_tile(const GateDesc &d, int k, int r0, int j0, double2 *
     int gr = r0 + r, gj = j0 + j;
     double2 v = make_double2(0.0, 0.0);
     if (gr < d.m && gj < k) {
-      int col = d.perm[gj];
-      double inv = d.trans ? 1.0 : 1.0 / sqrt(d.sig2[col]);
+      int col = left_col(d, gj);
+      double inv = left_inv(d, col);
       v = left_vec(d, gr, col, inv);
     }
     tile[r * LD + j] = v;
@@ -74,8 +81,8 @@ __device__ void wb_right_tile(const GateDesc &d, int k, int j0, int c0, double2 
   int colA = 0;
   double invA = 1.0;
   if (gj < k) {
-    colA = d.perm[gj];
-    invA = d.trans ? 1.0 : 1.0 / sqrt(d.sig2[colA]);
+    colA = left_col(d, gj);
+    invA = left_inv(d, colA);
   }
   const int br = tid >> 4, bc = (tid & 15) * 4;  // B: row r, 4 consecutive c
   for (int r0 = 0; r0 < m; r0 += 16) {
@@ -163,8 +170,8 @@ __device__ void wb_right_tile_mfma(const GateDesc &d, int k, int j0, int c0, flo
   int colA = 0;
   double invA = 1.0;
   if (gj < k) {
-    colA = d.perm[gj];
-    invA = d.trans ? 1.0 : 1.0 / sqrt(d.sig2[colA]);
+    colA = left_col(d, gj);
+    invA = left_inv(d, colA);
   }
   const int bk = tid >> 4, bc = (tid & 15) * 4;
   for (int r0 = 0; r0 < m; r0 += TILE_K) {

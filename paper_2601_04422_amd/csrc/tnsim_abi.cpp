@@ -32,7 +32,7 @@ struct Layout {
   int cmax = 0, ldx_max = 0, cols_pad_max = 0, npairs_max = 0, gp_blocks = 0;
   size_t slot_bytes = 0, slot0_off = 0;
   size_t x_off = 0, j_off = 0, t_off = 0, v_off = 0, pf_off = 0, ver_off = 0, seen_off = 0,
-         sig_off = 0, perm_off = 0, sc_off = 0;  // within a slot
+         sig_off = 0, perm_off = 0, sc_off = 0, u_off = 0, tq_off = 0;  // within a slot
   size_t gp_off = 0;  // pooled pair-Gram partials
   size_t desc_off = 0, d1_off = 0, ctr_off = 0, scg_off = 0;
   size_t e0_off = 0, e1_off = 0, f_off = 0, f2_off = 0, va_off = 0, vb_off = 0;
@@ -116,6 +116,12 @@ Layout make_layout(const tnsim_config &c) {
   s = align_up(s + sizeof(int) * L.cols_pad_max);
   L.sc_off = s;
   s = align_up(s + sizeof(SlotScalars));
+  if (c.svd_precondition) {  // U_k and the panels' T factors of both QR stages
+    L.u_off = s;
+    s = align_up(s + sizeof(double2) * (size_t)L.ldx_max * L.cols_pad_max);
+    L.tq_off = s;
+    s = align_up(s + sizeof(double2) * 2 * (size_t)(L.cols_pad_max / QNB) * QNB * QNB);
+  }
   L.slot_bytes = s;
   L.slot0_off = off;
   off = align_up(off + L.slot_bytes * L.nslots);
@@ -371,7 +377,9 @@ tnsim_status run_2q_items(tnsim_mps o, const BatchItem *items, int ng, bool forc
     // X = M^H (with the left vectors accumulated in J) when M is wide, or
     // always when the caller needs the full left basis (the adjoint)
     d.trans = force_trans || d.n > d.m;
-    d.rows = d.trans ? d.n : d.m;
+    // QR-preconditioned SVD for square or tall M that fits one panel workgroup
+    d.qr = h->cfg.svd_precondition && !d.trans && d.m <= QR_MAX_ROWS;
+    d.rows = d.qr ? d.n : (d.trans ? d.n : d.m);
     d.cols = d.trans ? d.m : d.n;
     d.ldx = pad_to(d.rows, 4);
     d.ldj = pad_to(d.m, 4);
@@ -390,6 +398,15 @@ tnsim_status run_2q_items(tnsim_mps o, const BatchItem *items, int ng, bool forc
     char *sl = h->slot(items[g].slot);
     d.X = (double2 *)(sl + L.x_off);
     d.J = (double2 *)(sl + L.j_off);
+    if (d.qr) {  // M and Q1's reflectors in the X buffer; the Jacobi on R2^H in J's
+      d.Qm = d.X;
+      d.ldq = pad_to(d.m, 4);
+      d.X = d.J;
+      d.J = nullptr;
+      d.U = (double2 *)(sl + L.u_off);
+      d.ldu = pad_to(d.m, 4);
+      d.Tq = (double2 *)(sl + L.tq_off);
+    }
     d.T = sl + L.t_off;
     d.V = (double2 *)(sl + L.v_off);
     d.pairFlag = (int *)(sl + L.pf_off);
@@ -433,6 +450,28 @@ tnsim_status run_2q_items(tnsim_mps o, const BatchItem *items, int ng, bool forc
   {
     ProfScope p(h, TNSIM_K_THETA, theta_flop, theta_byte);
     launch_theta(st, ddev, ng, c.precision, maxM, maxChiR);
+  }
+  // QR preconditioning of the gates that take it: M = Q1 R1 (stage 0),
+  // R1^H = Q2 R2 (stage 1), then the Jacobi matrix X = R2^H.
+  int qrN = 0;
+  double qr_flop = 0.0;
+  for (int g = 0; g < ng; g++)
+    if (D[g].qr) {
+      const double mm = D[g].m, nn = D[g].n;
+      qrN = std::max(qrN, D[g].n);
+      qr_flop += 8.0 * (mm * nn * nn - nn * nn * nn / 3.0) + 16.0 * nn * nn * nn / 3.0;
+    }
+  const int qrPanels = (qrN + QNB - 1) / QNB;
+  if (qrN > 0) {
+    ProfScope p(h, TNSIM_K_QR, qr_flop, 0.0);
+    for (int stage = 0; stage < 2; stage++) {
+      for (int pnl = 0; pnl < qrPanels; pnl++) {
+        launch_qr_panel(st, ddev, ng, stage, pnl);
+        launch_qr_update(st, ddev, ng, stage, pnl, 0, qrN - (pnl + 1) * QNB);
+      }
+      if (stage == 0) launch_qr_r1h(st, ddev, ng, qrN);
+    }
+    launch_qr_r2h(st, ddev, ng, qrN);
   }
   {
     ProfScope p(h, TNSIM_K_COLNORM, 0.0, colnorm_byte);
@@ -634,6 +673,22 @@ tnsim_status run_2q_items(tnsim_mps o, const BatchItem *items, int ng, bool forc
     wbl_byte += (16.0 + eb) * d.m * sv.k;
     wbr_flop += 8.0 * sv.k * d.m * d.n;
     wbr_byte += 16.0 * d.m * sv.k + tb * (double)d.m * d.n + eb * (double)sv.k * d.n;
+  }
+  // U_k = Q1 [W_k; 0] for the QR-preconditioned gates: the panels' reflectors
+  // in reverse order
+  int qrK = 0, qrM = 0;
+  double qa_flop = 0.0;
+  for (int g = 0; g < ng; g++)
+    if (D[g].qr) {
+      qrK = std::max(qrK, sc_pin[g].k);
+      qrM = std::max(qrM, D[g].m);
+      qa_flop += 8.0 * (2.0 * D[g].m * D[g].n - (double)D[g].n * D[g].n) * sc_pin[g].k;
+    }
+  if (qrK > 0) {
+    ProfScope p(h, TNSIM_K_QR, qa_flop, 0.0);
+    launch_qr_gather(st, ddev, ng, qrM, qrK);
+    for (int pnl = qrPanels - 1; pnl >= 0; pnl--) launch_qr_update(st, ddev, ng, 0, pnl, 1, qrK);
+    LAUNCHCHK(h, "qr apply");
   }
   {
     ProfScope p(h, TNSIM_K_WB_LEFT, 0.0, wbl_byte);

@@ -12,6 +12,11 @@ namespace tn {
 constexpr int BW = 32;
 constexpr int PW = 64;
 constexpr int KSPLIT_MAX = 16;
+// QR preconditioning: Householder panels of QNB columns; a panel of up to
+// QR_MAX_ROWS rows is held in the registers of one 512-thread workgroup
+// (4 rows x 8 complex128 columns per thread).
+constexpr int QNB = 8;
+constexpr int QR_MAX_ROWS = 2048;
 
 // Scalars per gate slot (device memory).
 struct SlotScalars {
@@ -58,6 +63,11 @@ struct GateDesc {
   double *sig2;          // column norms squared
   int *perm;             // columns sorted by descending norm
   SlotScalars *sc;
+  // QR preconditioning (qr = 1): theta writes M (m x n) to Qm, which then
+  // holds Q1's reflectors below R1; X is R2^H (n x n); U gets U_k = Q1 [W_k; 0]
+  // (m x k) for the write-back; Tq holds the compact-WY factor of every panel.
+  int qr, ldq, ldu, pad2;
+  double2 *Qm, *U, *Tq;
   unsigned long long *ctr;  // work counters (see CTR_*), may be nullptr
   double2 g[16];            // the 4x4 gate
 };
@@ -95,6 +105,14 @@ void launch_gather_sc(hipStream_t st, const GateDesc *d, int ng, SlotScalars *ou
 void launch_rot(hipStream_t st, const GateDesc *d, int ng, int round, int max_pairs,
                 int max_rows, int max_m, int rot_rows);
 void launch_trunc(hipStream_t st, const GateDesc *d, int ng);
+// QR preconditioning (k_qr.hip).  stage 0 factors M (in Qm), stage 1 factors
+// R1^H (in X); apply = 1 multiplies U by Q1 instead of a factor's trailing part.
+void launch_qr_panel(hipStream_t st, const GateDesc *d, int ng, int stage, int panel);
+void launch_qr_update(hipStream_t st, const GateDesc *d, int ng, int stage, int panel, int apply,
+                      int max_cols);
+void launch_qr_r1h(hipStream_t st, const GateDesc *d, int ng, int max_n);
+void launch_qr_r2h(hipStream_t st, const GateDesc *d, int ng, int max_n);
+void launch_qr_gather(hipStream_t st, const GateDesc *d, int ng, int max_m, int max_k);
 void launch_wb_left(hipStream_t st, const GateDesc *d, int ng, int max_m, int max_k);
 void launch_wb_right(hipStream_t st, const GateDesc *d, int ng, int precision, int max_k,
                      int max_n);

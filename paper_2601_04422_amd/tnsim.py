@@ -29,11 +29,11 @@ class Config(C.Structure):
     _fields_ = [("n_qubits", C.c_int32), ("chi_max", C.c_int32), ("cutoff", C.c_double),
                 ("precision", C.c_int32), ("storage", C.c_int32),
                 ("jacobi_max_sweeps", C.c_int32), ("jacobi_tol", C.c_double),
-                ("max_layer_gates", C.c_int32)]
+                ("max_layer_gates", C.c_int32), ("svd_precondition", C.c_int32)]
 
 
 KERNEL_CLASSES = ["theta", "gram", "eig", "rot", "colnorm", "trunc", "wb_left", "wb_right",
-                  "one_qubit", "other"]
+                  "one_qubit", "other", "qr"]
 KSTAT_DTYPE = np.dtype([("ms", "<f8"), ("launches", "<i8"), ("flops", "<f8"), ("bytes", "<f8")])
 
 GATE_DTYPE = np.dtype([("q0", "<i4"), ("q1", "<i4"), ("m", "<c16", (16,))], align=True)
@@ -151,7 +151,10 @@ class MPS:
 
     def __init__(self, n: int, chi_max: int, cutoff: float = 0.0, precision: str = "fp64",
                  storage: str = "c128", jacobi_max_sweeps: int = 0, jacobi_tol: float = 0.0,
-                 max_layer_gates: int = 0, device: str = "cuda:0", stream=None):
+                 max_layer_gates: int = 0, device: str = "cuda:0", stream=None,
+                 svd_precondition: bool | None = None):
+        """svd_precondition: QR-preconditioned Jacobi SVD; None selects it for
+        the mixed precisions and leaves the float64 path on plain Jacobi."""
         import torch  # device memory and streams only
 
         if not torch.cuda.is_available():
@@ -160,8 +163,10 @@ class MPS:
         self.chi_max = chi_max
         self.precision = precision
         self.storage = storage
+        if svd_precondition is None:
+            svd_precondition = precision != "fp64"
         self.cfg = Config(n, chi_max, cutoff, PRECISION[precision], STORAGE[storage],
-                          jacobi_max_sweeps, jacobi_tol, max_layer_gates)
+                          jacobi_max_sweeps, jacobi_tol, max_layer_gates, int(svd_precondition))
         nbytes = lib().tnsim_mps_arena_bytes(C.byref(self.cfg))
         if nbytes == 0:
             raise TnsimError(E_ARG, "arena_bytes")

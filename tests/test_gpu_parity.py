@@ -263,3 +263,44 @@ def test_graph_replay_matches_eager(T):
         assert np.array_equal(g.site(q), e.site(q))
     for b in range(n - 1):
         assert np.array_equal(g.lam(b), e.lam(b))
+
+
+# ---------------------------------------------------------------- QR-preconditioned SVD
+
+@pytest.mark.parametrize("n,depth,chi,cutoff", [(16, 12, 12, 1e-10), (18, 14, 100, 1e-10),
+                                                (12, 10, 5, 0.0), (14, 12, 64, 0.0)])
+def test_qr_preconditioned_vs_oracle(T, n, depth, chi, cutoff):
+    """float64 arithmetic with the QR-preconditioned Jacobi (square and tall M
+    take it, wide M the plain path): same bond dimensions, spectra and
+    discarded weight as the oracle's plain Jacobi, at the float64 tolerances."""
+    layers = W.brickwork_haar(n, depth, 700 + n + chi)
+    m = T.MPS(n, chi, cutoff, svd_precondition=True)
+    m.run_layers(layers)
+    o = O.OracleMPS(n, chi, cutoff)
+    o.run_layers(layers)
+    assert list(m.bond_dims()) == list(o.bond_dims())
+    for b in range(n - 1):
+        assert np.max(np.abs(m.lam(b) - o.lam(b))) < 1e-10
+    st_g, st_o = m.stats(), o.stats()
+    assert abs(st_g["sum_eps"] - st_o["sum_eps"]) <= 1e-10 * max(1.0, st_o["sum_eps"])
+    assert 1 - _oracle_fid(m, o) < 1e-10
+    for (q0, q1, _) in layers[-1]:  # the left site of each last gate is U_k, an isometry
+        a = m.site(min(q0, q1))
+        a = a.reshape(-1, a.shape[2])
+        assert np.max(np.abs(a.conj().T @ a - np.eye(a.shape[1]))) < 1e-11
+
+
+def test_qr_preconditioned_amplitudes(T):
+    cfg = W.config_small()
+    m = T.MPS(cfg.n, cfg.chi_max, cfg.cutoff, svd_precondition=True)
+    m.run_layers(cfg.layers)
+    ref = statevector(cfg.n, cfg.gates())
+    assert np.max(np.abs(gpu_statevector(m) - ref)) < 1e-12
+    g = T.MPS(9, 16, svd_precondition=True)
+    rng = np.random.default_rng(21)
+    gates = []
+    for _ in range(30):
+        j = int(rng.integers(0, 8))
+        gates.append((j, j + 1, W.haar_u4(rng)) if rng.random() < 0.5 else (j + 1, j, W.haar_u4(rng)))
+    g.run_gates(gates)
+    assert np.max(np.abs(gpu_statevector(g) - statevector(9, gates))) < 1e-12
