@@ -31,9 +31,15 @@ __device__ __forceinline__ QrView qr_view(const GateDesc &d, int stage) {
   return QrView{d.X, d.ldx, d.n, d.n};
 }
 
+// T factors: those of the QNB-column panels of both stages, then those of
+// the QG-column groups (QG / QNB panels each) of both stages.
 __device__ __forceinline__ double2 *qr_tfac(const GateDesc &d, int stage, int panel) {
   const int np = d.colsPad / QNB;  // panels per stage
   return d.Tq + ((size_t)stage * np + panel) * (QNB * QNB);
+}
+__device__ __forceinline__ double2 *qr_tgrp(const GateDesc &d, int stage, int group) {
+  const int np = d.colsPad / QNB, ngp = d.colsPad / QG;
+  return d.Tq + (size_t)2 * np * (QNB * QNB) + ((size_t)stage * ngp + group) * (QG * QG);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -194,21 +200,21 @@ void launch_qr_panel(hipStream_t st, const GateDesc *d, int ng, int stage, int p
 
 // ---------------------------------------------------------------- block update
 
-constexpr int QU_COLS = 32;  // target columns per workgroup
 constexpr int QU_ROWS = 64;  // rows per LDS chunk
 
-// apply = 0: B = A(j0:, j0+w:) <- (I - V T V^H)^H B   (trailing part of a factor)
-// apply = 1: B = U(j0:, 0:k)   <- (I - V T V^H) B     (U = Q1 [W; 0], panels in reverse)
-// One workgroup per 32 target columns: S = V^H B over all rows, Y = op(T) S,
-// then B -= V Y.
-__global__ __launch_bounds__(256) void k_qr_update(const GateDesc *descs, int stage, int panel,
-                                                   int apply) {
-  const GateDesc &d = descs[blockIdx.y];
-  if (!d.qr) return;
-  const QrView q = qr_view(d, apply ? 0 : stage);
-  const int j0 = panel * QNB;
+// Apply a block reflector of NB Householder vectors (a panel, NB = QNB, or a
+// group of panels, NB = QG) to COLS target columns per workgroup:
+//   apply = 0: B = A(j0:, first:last) <- (I - V T V^H)^H B  (factoring: the
+//              columns after the block, up to col_end)
+//   apply = 1: B = U(j0:, 0:k) <- (I - V T V^H) B          (U = Q1 [W; 0])
+// S = V^H B over all rows, Y = op(T) S, B -= V Y; V is staged in LDS.
+template <int NB, int COLS>
+__device__ void qr_block_update(const GateDesc &d, const QrView q, int j0, const double2 *T,
+                                int apply, int col_end) {
+  static_assert((NB * COLS) % 256 == 0, "whole entries per thread");
+  constexpr int EPT = NB * COLS / 256;
   if (j0 >= q.cols) return;
-  const int w = min(QNB, q.cols - j0);
+  const int w = min(NB, q.cols - j0);
   double2 *B;
   int ldb, rows, ncols;
   if (apply) {
@@ -220,86 +226,380 @@ __global__ __launch_bounds__(256) void k_qr_update(const GateDesc *descs, int st
     B = q.A + (size_t)(j0 + w) * q.ld;
     ldb = q.ld;
     rows = q.rows;
-    ncols = q.cols - j0 - w;
+    ncols = min(col_end, q.cols) - j0 - w;
   }
-  const int c0 = blockIdx.x * QU_COLS;
+  const int c0 = blockIdx.x * COLS;
   if (c0 >= ncols) return;
-  const int nc = min(QU_COLS, ncols - c0);
+  const int nc = min(COLS, ncols - c0);
   B += (size_t)c0 * ldb;
-  const double2 *V = q.A + (size_t)j0 * q.ld;  // reflector p is column p of V, from row j0 + p
+  const double2 *V = q.A + (size_t)j0 * q.ld;  // reflector p: column p, from row j0 + p
 
-  __shared__ double2 Vs[QU_ROWS][QNB + 1];
-  __shared__ double2 Bs[QU_ROWS][QU_COLS + 1];
-  __shared__ double2 S[QNB][QU_COLS];
-  __shared__ double2 Y[QNB][QU_COLS];
-  __shared__ double2 Tl[QNB][QNB];
+  __shared__ double2 Vs[QU_ROWS][NB + 1];
+  __shared__ double2 Bs[QU_ROWS][COLS + 1];
+  __shared__ double2 S[NB][COLS];
+  __shared__ double2 Y[NB][COLS];
+  __shared__ double2 Tl[NB][NB + 1];
   const int tid = threadIdx.x;
-  const double2 *T = qr_tfac(d, apply ? 0 : stage, panel);
-  if (tid < QNB * QNB) Tl[tid / QNB][tid % QNB] = T[tid];
+  for (int e = tid; e < NB * NB; e += 256) Tl[e / NB][e % NB] = T[e];
 
-  // reflector entry p at row r (absolute): 1 on the diagonal, stored below it
-  auto vget = [&](int r, int p) -> double2 {
-    if (p >= w) return make_double2(0.0, 0.0);
-    const int dr = r - (j0 + p);
-    if (dr < 0) return make_double2(0.0, 0.0);
-    if (dr == 0) return make_double2(1.0, 0.0);
-    return V[(size_t)p * q.ld + r];
+  auto load_v = [&](int r0) {  // rows r0 .. r0+63 of V: 1 on the diagonal, stored below
+    for (int e = tid; e < QU_ROWS * NB; e += 256) {
+      const int r = e % QU_ROWS, p = e / QU_ROWS, gr = r0 + r, dr = gr - (j0 + p);
+      double2 v = make_double2(0.0, 0.0);
+      if (p < w && gr < rows && dr >= 0)
+        v = dr == 0 ? make_double2(1.0, 0.0) : V[(size_t)p * q.ld + gr];
+      Vs[r][p] = v;
+    }
   };
 
-  // phase 1: S = V^H B; thread (p, cc) owns one entry
-  const int sp = tid / QU_COLS, scc = tid % QU_COLS;  // 8 x 32 = 256 threads
-  double2 sacc = make_double2(0.0, 0.0);
+  // phase 1: S = V^H B
+  double2 sacc[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; e++) sacc[e] = make_double2(0.0, 0.0);
   for (int r0 = j0; r0 < rows; r0 += QU_ROWS) {
-    for (int e = tid; e < QU_ROWS * QNB; e += 256) {
-      const int r = e % QU_ROWS, p = e / QU_ROWS;
-      Vs[r][p] = (r0 + r < rows) ? vget(r0 + r, p) : make_double2(0.0, 0.0);
-    }
-    for (int e = tid; e < QU_ROWS * QU_COLS; e += 256) {
+    load_v(r0);
+    for (int e = tid; e < QU_ROWS * COLS; e += 256) {
       const int r = e % QU_ROWS, cc = e / QU_ROWS;
       Bs[r][cc] = (r0 + r < rows && cc < nc) ? B[(size_t)cc * ldb + r0 + r]
                                               : make_double2(0.0, 0.0);
     }
     __syncthreads();
+#pragma unroll
+    for (int e = 0; e < EPT; e++) {
+      const int id = tid + 256 * e, p = id / COLS, cc = id % COLS;
 #pragma unroll 8
-    for (int r = 0; r < QU_ROWS; r++) cfmac(sacc, Vs[r][sp], Bs[r][scc]);
+      for (int r = 0; r < QU_ROWS; r++) cfmac(sacc[e], Vs[r][p], Bs[r][cc]);
+    }
     __syncthreads();
   }
-  S[sp][scc] = sacc;
-  __syncthreads();
-  // phase 2: Y = T^H S (factor) or T S (apply)
-  {
-    double2 y = make_double2(0.0, 0.0);
-    for (int l = 0; l < QNB; l++) {
-      const double2 t = apply ? Tl[sp][l] : cconj(Tl[l][sp]);
-      y = cadd(y, cmul(t, S[l][scc]));
-    }
-    Y[sp][scc] = y;
+#pragma unroll
+  for (int e = 0; e < EPT; e++) {
+    const int id = tid + 256 * e;
+    S[id / COLS][id % COLS] = sacc[e];
   }
   __syncthreads();
-  // phase 3: B -= V Y; lanes along rows, each thread 8 columns
+  // phase 2: Y = T^H S (factor) or T S (apply)
+#pragma unroll
+  for (int e = 0; e < EPT; e++) {
+    const int id = tid + 256 * e, p = id / COLS, cc = id % COLS;
+    double2 y = make_double2(0.0, 0.0);
+    for (int l = 0; l < NB; l++) {
+      const double2 t = apply ? Tl[p][l] : cconj(Tl[l][p]);
+      y = cadd(y, cmul(t, S[l][cc]));
+    }
+    Y[p][cc] = y;
+  }
+  __syncthreads();
+  // phase 3: B -= V Y; lanes along rows
   const int rl = tid % QU_ROWS, cg = tid / QU_ROWS;  // 64 rows x 4 column groups
   for (int r0 = j0; r0 < rows; r0 += QU_ROWS) {
+    load_v(r0);
+    __syncthreads();
     const int r = r0 + rl;
     if (r < rows) {
-      double2 v[QNB];
-#pragma unroll
-      for (int p = 0; p < QNB; p++) v[p] = vget(r, p);
       for (int cc = cg; cc < nc; cc += 4) {
-        double2 s = make_double2(0.0, 0.0);
-#pragma unroll
-        for (int p = 0; p < QNB; p++) s = cadd(s, cmul(v[p], Y[p][cc]));
+        double2 acc = make_double2(0.0, 0.0);
+#pragma unroll 8
+        for (int p = 0; p < NB; p++) cfma(acc, Vs[rl][p], Y[p][cc]);
         double2 *bp = B + (size_t)cc * ldb + r;
-        *bp = csub(*bp, s);
+        *bp = csub(*bp, acc);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+constexpr int QU_COLS = 32;   // target columns per workgroup, panel updates
+
+// One panel's reflectors on the columns after it up to col_end (inside its
+// group while the group is being factored).
+__global__ __launch_bounds__(256) void k_qr_update(const GateDesc *descs, int stage, int panel,
+                                                   int col_end) {
+  const GateDesc &d = descs[blockIdx.y];
+  if (!d.qr) return;
+  qr_block_update<QNB, QU_COLS>(d, qr_view(d, stage), panel * QNB, qr_tfac(d, stage, panel), 0,
+                                col_end);
+}
+
+void launch_qr_update(hipStream_t st, const GateDesc *d, int ng, int stage, int panel,
+                      int col_end, int max_cols) {
+  if (ng <= 0 || max_cols <= 0) return;
+  hipLaunchKernelGGL(k_qr_update, dim3((max_cols + QU_COLS - 1) / QU_COLS, ng), dim3(256), 0, st,
+                     d, stage, panel, col_end);
+}
+
+// ------------------------------------------------ group update on matrix cores
+//
+// A group's QG reflectors on everything after the group (apply = 0), or on U
+// (apply = 1, stage-0 groups in reverse order), in three launches so that the
+// rows are spread over workgroups as well as the columns:
+//   k_qrg_s : partial S = V^H B over a chunk of QR_RC rows      (per chunk)
+//   k_qrg_y : Y = op(T) sum_chunks S                           (per column tile)
+//   k_qrg_b : B -= V Y over a chunk of rows                     (per chunk)
+// Partial sums and Y go to a scratch buffer that is idle at that time (U while
+// factoring, the Jacobi matrix once its columns have been gathered into U).
+// Fixed summation order: results do not depend on scheduling.
+
+typedef double qd4_t __attribute__((ext_vector_type(4)));
+
+// v_mfma_f64_16x16x4f64: lane l supplies A[l%16][l/16] and B[l/16][l%16];
+// result entry v of lane l is D[l/16 + 4v][l%16].
+__device__ __forceinline__ qd4_t qmfma(double a, double b, qd4_t c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+constexpr int QGT = 32;     // target columns per workgroup
+
+struct QrTarget {
+  double2 *B;     // first target column
+  int ldb, rows;  // rows of B (all of them; the reflectors start at row j0)
+  int ncols;      // target columns
+  double2 *scr;   // scratch: partial S then Y, QG rows of ldS each
+  int ldS;
+};
+
+__device__ __forceinline__ QrTarget qr_target(const GateDesc &d, const QrView &q, int j0, int w,
+                                              int apply) {
+  QrTarget t;
+  t.ldS = d.colsPad;
+  if (apply) {
+    t.B = d.U;
+    t.ldb = d.ldu;
+    t.rows = d.m;
+    t.ncols = d.sc->k;
+    t.scr = d.X;
+  } else {
+    t.B = q.A + (size_t)(j0 + w) * q.ld;
+    t.ldb = q.ld;
+    t.rows = q.rows;
+    t.ncols = q.cols - j0 - w;
+    t.scr = d.U;
+  }
+  return t;
+}
+
+// reflector p of the group at absolute row r: 1 on its diagonal, stored below
+__device__ __forceinline__ double2 qr_vget(const QrView &q, int j0, int w, int r, int p) {
+  if (p >= w || r >= q.rows) return make_double2(0.0, 0.0);
+  const int dr = r - (j0 + p);
+  if (dr < 0) return make_double2(0.0, 0.0);
+  if (dr == 0) return make_double2(1.0, 0.0);
+  return q.A[(size_t)(j0 + p) * q.ld + r];
+}
+
+__global__ __launch_bounds__(256) void k_qrg_s(const GateDesc *descs, int stage, int group,
+                                               int apply) {
+  const GateDesc &d = descs[blockIdx.z];
+  if (!d.qr) return;
+  const int stg = apply ? 0 : stage;
+  const QrView q = qr_view(d, stg);
+  const int j0 = group * QG;
+  if (j0 >= q.cols) return;
+  const int w = min(QG, q.cols - j0);
+  const QrTarget t = qr_target(d, q, j0, w, apply);
+  const int c0 = blockIdx.x * QGT;
+  const int rbeg = j0 + blockIdx.y * QR_RC;
+  if (c0 >= t.ncols || rbeg >= t.rows) return;
+  const int rend = min(t.rows, rbeg + QR_RC);
+  __shared__ double2 Vs[32][QG + 1];
+  __shared__ double2 Bs[32][QGT + 1];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int l16 = lane & 15, lg = lane >> 4;
+  const int tp = (wave >> 1) * 16, tc = (wave & 1) * 16;  // this wave's 16x16 tile of S
+  qd4_t accR = {0.0, 0.0, 0.0, 0.0}, accI = {0.0, 0.0, 0.0, 0.0};
+  for (int r0 = rbeg; r0 < rend; r0 += 32) {
+    for (int e = tid; e < 32 * QG; e += 256) {
+      const int r = e % 32, p = e / 32;
+      Vs[r][p] = (r0 + r < rend) ? qr_vget(q, j0, w, r0 + r, p) : make_double2(0.0, 0.0);
+    }
+    for (int e = tid; e < 32 * QGT; e += 256) {
+      const int r = e % 32, cc = e / 32;
+      Bs[r][cc] = (r0 + r < rend && c0 + cc < t.ncols)
+                      ? t.B[(size_t)(c0 + cc) * t.ldb + r0 + r]
+                      : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 32; kk += 4) {
+      const double2 a = Vs[kk + lg][tp + l16];  // S = conj(V)^T B
+      const double2 b = Bs[kk + lg][tc + l16];
+      accR = qmfma(a.x, b.x, accR);
+      accR = qmfma(a.y, b.y, accR);
+      accI = qmfma(a.x, b.y, accI);
+      accI = qmfma(-a.y, b.x, accI);
+    }
+    __syncthreads();
+  }
+  double2 *Sp = t.scr + (size_t)blockIdx.y * QG * t.ldS;
+#pragma unroll
+  for (int v = 0; v < 4; v++) {
+    const int p = tp + lg + 4 * v, c = c0 + tc + l16;
+    if (c < t.ncols) Sp[(size_t)p * t.ldS + c] = make_double2(accR[v], accI[v]);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_qrg_y(const GateDesc *descs, int stage, int group,
+                                               int apply) {
+  const GateDesc &d = descs[blockIdx.y];
+  if (!d.qr) return;
+  const int stg = apply ? 0 : stage;
+  const QrView q = qr_view(d, stg);
+  const int j0 = group * QG;
+  if (j0 >= q.cols) return;
+  const int w = min(QG, q.cols - j0);
+  const QrTarget t = qr_target(d, q, j0, w, apply);
+  const int c0 = blockIdx.x * QGT;
+  if (c0 >= t.ncols) return;
+  const int nch = (t.rows - j0 + QR_RC - 1) / QR_RC;
+  __shared__ double2 S[QG][QGT + 1];
+  __shared__ double2 Tl[QG][QG + 1];
+  const double2 *T = qr_tgrp(d, stg, group);
+  const int tid = threadIdx.x;
+  for (int e = tid; e < QG * QG; e += 256) Tl[e / QG][e % QG] = T[e];
+  for (int e = tid; e < QG * QGT; e += 256) {
+    const int p = e / QGT, cc = e % QGT, c = c0 + cc;
+    double2 sum = make_double2(0.0, 0.0);
+    if (c < t.ncols)
+      for (int ch = 0; ch < nch; ch++)
+        sum = cadd(sum, t.scr[((size_t)ch * QG + p) * t.ldS + c]);
+    S[p][cc] = sum;
+  }
+  __syncthreads();
+  double2 *Yg = t.scr + (size_t)nch * QG * t.ldS;  // after the partials
+  for (int e = tid; e < QG * QGT; e += 256) {
+    const int p = e / QGT, cc = e % QGT, c = c0 + cc;
+    double2 y = make_double2(0.0, 0.0);
+    for (int l = 0; l < QG; l++) {
+      const double2 tv = apply ? Tl[p][l] : cconj(Tl[l][p]);  // T or T^H
+      y = cadd(y, cmul(tv, S[l][cc]));
+    }
+    if (c < t.ncols) Yg[(size_t)p * t.ldS + c] = y;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_qrg_b(const GateDesc *descs, int stage, int group,
+                                               int apply) {
+  const GateDesc &d = descs[blockIdx.z];
+  if (!d.qr) return;
+  const int stg = apply ? 0 : stage;
+  const QrView q = qr_view(d, stg);
+  const int j0 = group * QG;
+  if (j0 >= q.cols) return;
+  const int w = min(QG, q.cols - j0);
+  const QrTarget t = qr_target(d, q, j0, w, apply);
+  const int c0 = blockIdx.x * QGT;
+  const int rbeg = j0 + blockIdx.y * QR_RC;
+  if (c0 >= t.ncols || rbeg >= t.rows) return;
+  const int rend = min(t.rows, rbeg + QR_RC);
+  const int nch = (t.rows - j0 + QR_RC - 1) / QR_RC;
+  __shared__ double2 Ys[QG][QGT + 1];
+  const double2 *Yg = t.scr + (size_t)nch * QG * t.ldS;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int l16 = lane & 15, lg = lane >> 4;
+  for (int e = tid; e < QG * QGT; e += 256) {
+    const int p = e / QGT, cc = e % QGT;
+    Ys[p][cc] = (c0 + cc < t.ncols) ? Yg[(size_t)p * t.ldS + c0 + cc] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  // (V Y)^T = Y^T V^T: tiles of 16 target columns x 16 rows; the wave's tiles
+  // are column tile (wave & 1) and every other row tile of the chunk
+  const int tc = (wave & 1) * 16;
+  for (int rt = rbeg + (wave >> 1) * 16; rt < rend; rt += 32) {
+    qd4_t accR = {0.0, 0.0, 0.0, 0.0}, accI = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k0 = 0; k0 < QG; k0 += 4) {
+      const double2 a = Ys[k0 + lg][tc + l16];               // Y^T[col][k]
+      const double2 b = qr_vget(q, j0, w, rt + l16, k0 + lg);  // V^T[k][row]
+      accR = qmfma(a.x, b.x, accR);
+      accR = qmfma(-a.y, b.y, accR);
+      accI = qmfma(a.x, b.y, accI);
+      accI = qmfma(a.y, b.x, accI);
+    }
+    const int r = rt + l16;
+    if (r < rend) {
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const int c = c0 + tc + lg + 4 * v;
+        if (c < t.ncols) {
+          double2 *bp = t.B + (size_t)c * t.ldb + r;
+          *bp = make_double2(bp->x - accR[v], bp->y - accI[v]);
+        }
       }
     }
   }
 }
 
-void launch_qr_update(hipStream_t st, const GateDesc *d, int ng, int stage, int panel, int apply,
-                      int max_cols) {
-  if (ng <= 0 || max_cols <= 0) return;
-  hipLaunchKernelGGL(k_qr_update, dim3((max_cols + QU_COLS - 1) / QU_COLS, ng), dim3(256), 0, st,
-                     d, stage, panel, apply);
+void launch_qr_update_group(hipStream_t st, const GateDesc *d, int ng, int stage, int group,
+                            int apply, int max_cols, int max_rows) {
+  if (ng <= 0 || max_cols <= 0 || max_rows <= group * QG) return;
+  const int ct = (max_cols + QGT - 1) / QGT;
+  const int rc = (max_rows - group * QG + QR_RC - 1) / QR_RC;
+  hipLaunchKernelGGL(k_qrg_s, dim3(ct, rc, ng), dim3(256), 0, st, d, stage, group, apply);
+  hipLaunchKernelGGL(k_qrg_y, dim3(ct, ng), dim3(256), 0, st, d, stage, group, apply);
+  hipLaunchKernelGGL(k_qrg_b, dim3(ct, rc, ng), dim3(256), 0, st, d, stage, group, apply);
+}
+
+// T factor of a group of QG reflectors (compact WY, forward, columnwise):
+// T(i, i) = tau_i (from the panels' factors), T(0:i, i) = -tau_i T(0:i, 0:i)
+// (V(:, 0:i)^H v_i), with the Gram V^H V summed over the group's rows.
+__global__ __launch_bounds__(256) void k_qr_tgroup(const GateDesc *descs, int stage, int group) {
+  const GateDesc &d = descs[blockIdx.x];
+  if (!d.qr) return;
+  const QrView q = qr_view(d, stage);
+  const int j0 = group * QG;
+  if (j0 >= q.cols) return;
+  const int w = min(QG, q.cols - j0);
+  const double2 *V = q.A + (size_t)j0 * q.ld;
+  __shared__ double2 Vs[QU_ROWS][QG + 1];
+  __shared__ double2 G[QG][QG + 1];
+  __shared__ double2 Ts[QG][QG + 1];
+  const int tid = threadIdx.x;
+  constexpr int EPT = QG * QG / 256;
+  double2 acc[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; e++) acc[e] = make_double2(0.0, 0.0);
+  for (int r0 = j0; r0 < q.rows; r0 += QU_ROWS) {
+    for (int e = tid; e < QU_ROWS * QG; e += 256) {
+      const int r = e % QU_ROWS, p = e / QU_ROWS, gr = r0 + r, dr = gr - (j0 + p);
+      double2 v = make_double2(0.0, 0.0);
+      if (p < w && gr < q.rows && dr >= 0)
+        v = dr == 0 ? make_double2(1.0, 0.0) : V[(size_t)p * q.ld + gr];
+      Vs[r][p] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < EPT; e++) {
+      const int id = tid + 256 * e, p = id / QG, l = id % QG;
+#pragma unroll 8
+      for (int r = 0; r < QU_ROWS; r++) cfmac(acc[e], Vs[r][p], Vs[r][l]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int e = 0; e < EPT; e++) {
+    const int id = tid + 256 * e;
+    G[id / QG][id % QG] = acc[e];
+    Ts[id / QG][id % QG] = make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int i = 0; i < w; i++) {
+    const double2 *Tp = qr_tfac(d, stage, (j0 + i) / QNB);
+    const double2 tau = Tp[(i % QNB) * QNB + (i % QNB)];
+    if (tid < i) {
+      double2 sum = make_double2(0.0, 0.0);
+      for (int l = tid; l < i; l++) sum = cadd(sum, cmul(Ts[tid][l], G[l][i]));
+      Ts[tid][i] = cmul(make_double2(-tau.x, -tau.y), sum);
+    }
+    if (tid == i) Ts[i][i] = tau;
+    __syncthreads();
+  }
+  double2 *Tg = qr_tgrp(d, stage, group);
+  for (int e = tid; e < QG * QG; e += 256) Tg[e] = Ts[e / QG][e % QG];
+}
+
+void launch_qr_tgroup(hipStream_t st, const GateDesc *d, int ng, int stage, int group) {
+  if (ng <= 0) return;
+  hipLaunchKernelGGL(k_qr_tgroup, dim3(ng), dim3(256), 0, st, d, stage, group);
 }
 
 // ---------------------------------------------------------------- triangular transposes

@@ -95,11 +95,19 @@ Layout make_layout(const tnsim_config &c) {
   L.ldx_max = pad_to(L.cmax, 4);
   L.cols_pad_max = pad_to(L.cmax, PW);
   L.npairs_max = L.cols_pad_max / PW;
+  // with QR preconditioning, J and U also serve as scratch for the group
+  // updates: partial sums and Y, (row chunks + 1) x QG rows of cols_pad_max
+  const size_t xj_elems = (size_t)L.ldx_max * L.cols_pad_max;
+  size_t scr_elems = 0;
+  if (c.svd_precondition) {
+    const int rchunks = (std::min(L.cmax, QR_MAX_ROWS) + QR_RC - 1) / QR_RC;
+    scr_elems = (size_t)(rchunks + 1) * QG * L.cols_pad_max;
+  }
   size_t s = 0;
   L.x_off = s;
-  s = align_up(s + sizeof(double2) * (size_t)L.ldx_max * L.cols_pad_max);
+  s = align_up(s + sizeof(double2) * xj_elems);
   L.j_off = s;
-  s = align_up(s + sizeof(double2) * (size_t)L.ldx_max * L.cols_pad_max);
+  s = align_up(s + sizeof(double2) * std::max(xj_elems, scr_elems));
   L.t_off = s;
   s = align_up(s + sizeof(double2) * (size_t)L.cmax * L.cmax);
   L.v_off = s;
@@ -118,9 +126,11 @@ Layout make_layout(const tnsim_config &c) {
   s = align_up(s + sizeof(SlotScalars));
   if (c.svd_precondition) {  // U_k and the panels' T factors of both QR stages
     L.u_off = s;
-    s = align_up(s + sizeof(double2) * (size_t)L.ldx_max * L.cols_pad_max);
+    s = align_up(s + sizeof(double2) * std::max(xj_elems, scr_elems));
     L.tq_off = s;
-    s = align_up(s + sizeof(double2) * 2 * (size_t)(L.cols_pad_max / QNB) * QNB * QNB);
+    s = align_up(s + sizeof(double2) * 2 *
+                         ((size_t)(L.cols_pad_max / QNB) * QNB * QNB +
+                          (size_t)(L.cols_pad_max / QG) * QG * QG));
   }
   L.slot_bytes = s;
   L.slot0_off = off;
@@ -453,21 +463,30 @@ tnsim_status run_2q_items(tnsim_mps o, const BatchItem *items, int ng, bool forc
   }
   // QR preconditioning of the gates that take it: M = Q1 R1 (stage 0),
   // R1^H = Q2 R2 (stage 1), then the Jacobi matrix X = R2^H.
-  int qrN = 0;
+  int qrN = 0, qrMr = 0;
   double qr_flop = 0.0;
   for (int g = 0; g < ng; g++)
     if (D[g].qr) {
       const double mm = D[g].m, nn = D[g].n;
       qrN = std::max(qrN, D[g].n);
+      qrMr = std::max(qrMr, D[g].m);
       qr_flop += 8.0 * (mm * nn * nn - nn * nn * nn / 3.0) + 16.0 * nn * nn * nn / 3.0;
     }
-  const int qrPanels = (qrN + QNB - 1) / QNB;
+  // Panels are factored one group of QG columns at a time (each panel's
+  // reflectors applied inside the group), then the group's reflectors update
+  // the rest of the matrix in one pass.
+  const int qrGroups = (qrN + QG - 1) / QG;
   if (qrN > 0) {
     ProfScope p(h, TNSIM_K_QR, qr_flop, 0.0);
     for (int stage = 0; stage < 2; stage++) {
-      for (int pnl = 0; pnl < qrPanels; pnl++) {
-        launch_qr_panel(st, ddev, ng, stage, pnl);
-        launch_qr_update(st, ddev, ng, stage, pnl, 0, qrN - (pnl + 1) * QNB);
+      for (int grp = 0; grp < qrGroups; grp++) {
+        const int gend = (grp + 1) * QG;
+        for (int pnl = grp * (QG / QNB); pnl < (grp + 1) * (QG / QNB) && pnl * QNB < qrN; pnl++) {
+          launch_qr_panel(st, ddev, ng, stage, pnl);
+          launch_qr_update(st, ddev, ng, stage, pnl, gend, gend - (pnl + 1) * QNB);
+        }
+        launch_qr_tgroup(st, ddev, ng, stage, grp);
+        launch_qr_update_group(st, ddev, ng, stage, grp, 0, qrN - gend, stage ? qrN : qrMr);
       }
       if (stage == 0) launch_qr_r1h(st, ddev, ng, qrN);
     }
@@ -687,7 +706,8 @@ tnsim_status run_2q_items(tnsim_mps o, const BatchItem *items, int ng, bool forc
   if (qrK > 0) {
     ProfScope p(h, TNSIM_K_QR, qa_flop, 0.0);
     launch_qr_gather(st, ddev, ng, qrM, qrK);
-    for (int pnl = qrPanels - 1; pnl >= 0; pnl--) launch_qr_update(st, ddev, ng, 0, pnl, 1, qrK);
+    for (int grp = qrGroups - 1; grp >= 0; grp--)
+      launch_qr_update_group(st, ddev, ng, 0, grp, 1, qrK, qrM);
     LAUNCHCHK(h, "qr apply");
   }
   {

@@ -16,6 +16,8 @@ constexpr int KSPLIT_MAX = 16;
 // QR_MAX_ROWS rows is held in the registers of one 512-thread workgroup
 // (4 rows x 8 complex128 columns per thread).
 constexpr int QNB = 8;
+constexpr int QG = 32;  // reflectors applied together to the rest of the matrix (4 panels)
+constexpr int QR_RC = 256;  // rows per workgroup in a group update
 constexpr int QR_MAX_ROWS = 2048;
 
 // Scalars per gate slot (device memory).
@@ -106,10 +108,15 @@ void launch_rot(hipStream_t st, const GateDesc *d, int ng, int round, int max_pa
                 int max_rows, int max_m, int rot_rows);
 void launch_trunc(hipStream_t st, const GateDesc *d, int ng);
 // QR preconditioning (k_qr.hip).  stage 0 factors M (in Qm), stage 1 factors
-// R1^H (in X); apply = 1 multiplies U by Q1 instead of a factor's trailing part.
+// R1^H (in X).  Panels of QNB columns are factored and applied inside their
+// group of QG columns; a group's reflectors then update the rest at once
+// (apply = 1: multiply U by Q1 instead).
 void launch_qr_panel(hipStream_t st, const GateDesc *d, int ng, int stage, int panel);
-void launch_qr_update(hipStream_t st, const GateDesc *d, int ng, int stage, int panel, int apply,
-                      int max_cols);
+void launch_qr_update(hipStream_t st, const GateDesc *d, int ng, int stage, int panel,
+                      int col_end, int max_cols);
+void launch_qr_tgroup(hipStream_t st, const GateDesc *d, int ng, int stage, int group);
+void launch_qr_update_group(hipStream_t st, const GateDesc *d, int ng, int stage, int group,
+                            int apply, int max_cols, int max_rows);
 void launch_qr_r1h(hipStream_t st, const GateDesc *d, int ng, int max_n);
 void launch_qr_r2h(hipStream_t st, const GateDesc *d, int ng, int max_n);
 void launch_qr_gather(hipStream_t st, const GateDesc *d, int ng, int max_m, int max_k);
