@@ -206,14 +206,15 @@ __device__ __forceinline__ d4_t mfma64(double a, double b, d4_t c) {
 
 // Same pair Gram on float64 matrix cores (v_mfma_f64_16x16x4).  G is
 // Hermitian, so only the 10 upper 16x16 tiles (TI <= TJ) are computed; the
-// pair solve mirrors the lower triangle.  Wavefronts take 3, 3, 2 and 2 tiles.
-__constant__ int kGramTiles[4][3][2] = {{{0, 0}, {0, 1}, {0, 2}},
-                                        {{0, 3}, {1, 1}, {1, 2}},
-                                        {{1, 3}, {2, 2}, {-1, -1}},
-                                        {{2, 3}, {3, 3}, {-1, -1}}};
+// pair solve mirrors the lower triangle.  Five wavefronts take two tiles each;
+// the first four load the rows.
+constexpr int GRAM_WAVES = 5;
+__constant__ int kGramTiles[GRAM_WAVES][2][2] = {{{0, 0}, {0, 1}}, {{0, 2}, {0, 3}},
+                                                 {{1, 1}, {1, 2}}, {{1, 3}, {2, 2}},
+                                                 {{2, 3}, {3, 3}}};
 
-__global__ __launch_bounds__(256) void k_gram_mfma(const GateDesc *descs, int round,
-                                                   int ksplit) {
+__global__ __launch_bounds__(64 * GRAM_WAVES) void k_gram_mfma(const GateDesc *descs, int round,
+                                                               int ksplit) {
   const GateDesc &d = descs[blockIdx.y];
   const int pairIdx = blockIdx.x / ksplit, kc = blockIdx.x % ksplit;
   if (!d.sc->active || round >= d.nblk - 1 || pairIdx >= d.nblk / 2) return;
@@ -228,32 +229,36 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const GateDesc *descs, int ro
   __shared__ double2 Xs[GK][PW + 1];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int l16 = lane & 15, lg = lane >> 4;
-  const int nt = wave < 2 ? 3 : 2;
-  int tI[3], tJ[3];
+  const bool loader = tid < 256;  // 64 columns x 4 groups of 8 rows
+  int tI[2], tJ[2];
 #pragma unroll
-  for (int t = 0; t < 3; t++) {
+  for (int t = 0; t < 2; t++) {
     tI[t] = kGramTiles[wave][t][0];
     tJ[t] = kGramTiles[wave][t][1];
   }
-  d4_t accR[3], accI[3];
+  d4_t accR[2], accI[2];
 #pragma unroll
-  for (int t = 0; t < 3; t++) {
+  for (int t = 0; t < 2; t++) {
     accR[t] = d4_t{0.0, 0.0, 0.0, 0.0};
     accI[t] = d4_t{0.0, 0.0, 0.0, 0.0};
   }
-  const int lcol = tid >> 2, lr = (tid & 3) * 8;
+  const int lcol = (tid >> 2) & (PW - 1), lr = (tid & 3) * 8;
   const double2 *xcol = d.X + (size_t)pair_col(I, J, lcol) * d.ldx;
   double2 pre[8];  // next row tile, loaded while the current one is multiplied
+  if (loader) {
 #pragma unroll
-  for (int j = 0; j < 8; j++) {
-    int r = rbeg + lr + j;
-    pre[j] = r < rend ? xcol[r] : make_double2(0.0, 0.0);
+    for (int j = 0; j < 8; j++) {
+      int r = rbeg + lr + j;
+      pre[j] = r < rend ? xcol[r] : make_double2(0.0, 0.0);
+    }
   }
   for (int r0 = rbeg; r0 < rend; r0 += GK) {
+    if (loader) {
 #pragma unroll
-    for (int j = 0; j < 8; j++) Xs[lr + j][lcol] = pre[j];
+      for (int j = 0; j < 8; j++) Xs[lr + j][lcol] = pre[j];
+    }
     __syncthreads();
-    if (r0 + GK < rend) {
+    if (loader && r0 + GK < rend) {
 #pragma unroll
       for (int j = 0; j < 8; j++) {
         int r = r0 + GK + lr + j;
@@ -265,15 +270,13 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const GateDesc *descs, int ro
       const int row = kk + lg;
       // G_pq = sum_r conj(x_rp) x_rq
 #pragma unroll
-      for (int t = 0; t < 3; t++) {
-        if (t < nt) {
-          const double2 xa = Xs[row][tI[t] * 16 + l16];
-          const double2 xb = Xs[row][tJ[t] * 16 + l16];
-          accR[t] = mfma64(xa.x, xb.x, accR[t]);
-          accR[t] = mfma64(xa.y, xb.y, accR[t]);
-          accI[t] = mfma64(xa.x, xb.y, accI[t]);
-          accI[t] = mfma64(-xa.y, xb.x, accI[t]);
-        }
+      for (int t = 0; t < 2; t++) {
+        const double2 xa = Xs[row][tI[t] * 16 + l16];
+        const double2 xb = Xs[row][tJ[t] * 16 + l16];
+        accR[t] = mfma64(xa.x, xb.x, accR[t]);
+        accR[t] = mfma64(xa.y, xb.y, accR[t]);
+        accI[t] = mfma64(xa.x, xb.y, accI[t]);
+        accI[t] = mfma64(-xa.y, xb.x, accI[t]);
       }
     }
     __syncthreads();
@@ -284,13 +287,12 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const GateDesc *descs, int ro
   }
   double2 *G = d.Gp + ((size_t)kc * d.gpStride + pairIdx) * (PW * PW);
 #pragma unroll
-  for (int t = 0; t < 3; t++)
-    if (t < nt)
+  for (int t = 0; t < 2; t++)
 #pragma unroll
-      for (int e = 0; e < 4; e++) {
-        int p = tI[t] * 16 + lg + 4 * e, q = tJ[t] * 16 + l16;
-        G[p * PW + q] = make_double2(accR[t][e], accI[t][e]);
-      }
+    for (int e = 0; e < 4; e++) {
+      int p = tI[t] * 16 + lg + 4 * e, q = tJ[t] * 16 + l16;
+      G[p * PW + q] = make_double2(accR[t][e], accI[t][e]);
+    }
 }
 
 // ---------------------------------------------------------------- 64x64 Hermitian Jacobi
@@ -722,12 +724,110 @@ __global__ __launch_bounds__(256) void k_rot_mfma2(const GateDesc *descs, int ro
   }
 }
 
-int g_rot_variant = -1;  // -1: read TNSIM_ROT_KERNEL once ("1" selects the LDS-staged kernel)
+// Pair rotation, variant 3: the transposed product (X V)^T = V^T X^T, so that
+// the X operand of v_mfma_f64_16x16x4 (B: 16 lanes = 16 consecutive rows of
+// one column) and the result (16 lanes = 16 consecutive rows of one column)
+// are both contiguous 256-byte segments.  A wavefront owns whole 16-row tiles
+// (all 64 columns), so it overwrites exactly the rows it read and needs no
+// barrier; two workgroups per CU hide the load latency.
+__global__ __launch_bounds__(256, 2) void k_rot_mfma3(const GateDesc *descs, int round) {
+  const GateDesc &d = descs[blockIdx.y];
+  if (!d.sc->active || round >= d.nblk - 1) return;
+  const int npairs = d.nblk / 2;
+  const int RRW = d.rotRows;
+  const int xchunks = (d.rows + RRW - 1) / RRW;
+  const int jchunks = d.trans ? (d.m + RRW - 1) / RRW : 0;
+  const int per = xchunks + jchunks;
+  const int pairIdx = blockIdx.x / per, chunk = blockIdx.x % per;
+  if (pairIdx >= npairs) return;
+  if (!d.pairFlag[pairIdx]) return;
+  int I, J;
+  rr_pair(round, pairIdx, d.nblk, I, J);
+  double2 *base;
+  int ld, nrows, r0;
+  if (chunk < xchunks) {
+    base = d.X;
+    ld = d.ldx;
+    nrows = d.rows;
+    r0 = chunk * RRW;
+  } else {
+    base = d.J;
+    ld = d.ldj;
+    nrows = d.m;
+    r0 = (chunk - xchunks) * RRW;
+  }
+  const int r1 = min(nrows, r0 + RRW);
+  __shared__ double2 Vs[PW * LDG];  // [k][col]
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int l16 = lane & 15, lg = lane >> 4;
+  const double2 *V = d.V + (size_t)pairIdx * (PW * PW);
+  for (int e = tid; e < PW * PW; e += 256) Vs[(e / PW) * LDG + e % PW] = V[e];
+  if (tid == 0 && d.ctr) {
+    unsigned long long nr = (unsigned long long)(r1 - r0);
+    atomicAdd(&d.ctr[CTR_ROT_FLOP], 8ull * nr * PW * PW);
+    atomicAdd(&d.ctr[CTR_ROT_BYTE], 32ull * nr * PW + 16ull * PW * PW);
+  }
+  __syncthreads();
+  // the lane's column for k-step s is pair column 4 s + lg (block I for s < 8)
+  const double2 *xI = base + (size_t)(I * BW + lg) * ld;
+  const double2 *xJ = base + (size_t)(J * BW + lg) * ld;
+  // k-steps 0..7 read block I, 8..15 block J
+  auto load_half = [&](double2 *xv, int half, int rt) {
+    const int r = rt + l16;
+    const double2 *c0 = (half ? xJ : xI);
+#pragma unroll
+    for (int s = 0; s < BW / 4; s++)
+      xv[s] = r < r1 ? c0[(size_t)(4 * s) * ld + r] : make_double2(0.0, 0.0);
+  };
+  int rt = r0 + wave * 16;
+  double2 xb[PW / 4];
+  if (rt < r1) load_half(xb, 0, rt);
+  for (; rt < r1; rt += 64) {
+    // block J of this tile, needed after the block-I steps; block I of the
+    // wave's next tile, needed in the next iteration
+    load_half(xb + BW / 4, 1, rt);
+    double2 xn[BW / 4];
+    if (rt + 64 < r1) load_half(xn, 0, rt + 64);
+    d4_t accR[4], accI[4];
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+      accR[t] = d4_t{0.0, 0.0, 0.0, 0.0};
+      accI[t] = d4_t{0.0, 0.0, 0.0, 0.0};
+    }
+#pragma unroll
+    for (int s = 0; s < PW / 4; s++) {
+      const double2 b = xb[s];  // X^T[k][row]
+#pragma unroll
+      for (int t = 0; t < 4; t++) {
+        const double2 a = Vs[(4 * s + lg) * LDG + t * 16 + l16];  // V^T[col][k]
+        accR[t] = mfma64(a.x, b.x, accR[t]);
+        accR[t] = mfma64(-a.y, b.y, accR[t]);
+        accI[t] = mfma64(a.x, b.y, accI[t]);
+        accI[t] = mfma64(a.y, b.x, accI[t]);
+      }
+      __builtin_amdgcn_sched_barrier(0);  // keep each step's V reads in that step
+    }
+    const int r = rt + l16;
+    if (r < r1) {
+#pragma unroll
+      for (int t = 0; t < 4; t++)
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+          const int c = t * 16 + lg + 4 * v;
+          base[(size_t)pair_col(I, J, c) * ld + r] = make_double2(accR[t][v], accI[t][v]);
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < BW / 4; s++) xb[s] = xn[s];
+  }
+}
+
+int g_rot_variant = -1;  // -1: read TNSIM_ROT_KERNEL once
 
 static int rot_variant() {
   if (g_rot_variant < 0) {
-    const char *e = getenv("TNSIM_ROT_KERNEL");
-    g_rot_variant = (e && e[0] == '1') ? 1 : 2;
+    const char *e = getenv("TNSIM_ROT_KERNEL");  // "1", "2": earlier variants
+    g_rot_variant = (e && (e[0] == '1' || e[0] == '2')) ? e[0] - '0' : 3;
   }
   return g_rot_variant;
 }
@@ -746,8 +846,8 @@ void launch_gram(hipStream_t st, const GateDesc *d, int ng, int round, int max_p
                  int ksplit) {
   if (ng <= 0) return;
   if (use_mfma())
-    hipLaunchKernelGGL(k_gram_mfma, dim3(max_pairs * ksplit, ng), dim3(256), 0, st, d, round,
-                       ksplit);
+    hipLaunchKernelGGL(k_gram_mfma, dim3(max_pairs * ksplit, ng), dim3(64 * GRAM_WAVES), 0, st, d,
+                       round, ksplit);
   else
     hipLaunchKernelGGL(k_gram, dim3(max_pairs * ksplit, ng), dim3(256), 0, st, d, round, ksplit);
 }
@@ -772,9 +872,12 @@ void launch_rot(hipStream_t st, const GateDesc *d, int ng, int round, int max_pa
                 int max_rows, int max_m, int rot_rows) {
   if (ng <= 0) return;
   int per = (max_rows + RR - 1) / RR + (max_m + RR - 1) / RR;
-  if (use_mfma() && rot_variant() == 2) {
+  if (use_mfma() && rot_variant() >= 2) {
     int per2 = (max_rows + rot_rows - 1) / rot_rows + (max_m + rot_rows - 1) / rot_rows;
-    hipLaunchKernelGGL(k_rot_mfma2, dim3(max_pairs * per2, ng), dim3(256), 0, st, d, round);
+    if (rot_variant() == 3)
+      hipLaunchKernelGGL(k_rot_mfma3, dim3(max_pairs * per2, ng), dim3(256), 0, st, d, round);
+    else
+      hipLaunchKernelGGL(k_rot_mfma2, dim3(max_pairs * per2, ng), dim3(256), 0, st, d, round);
   } else if (use_mfma())
     hipLaunchKernelGGL(k_rot_mfma, dim3(max_pairs * per, ng), dim3(256), 0, st, d, round);
   else
