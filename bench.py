@@ -43,7 +43,7 @@ HBM_PEAK_GBS = 8000.0
 # kernel class -> (bound, device kernel name): the Gram and rotation kernels
 # are float64 matrix-core contractions, the pair solve and the Householder
 # panels float64 vector arithmetic
-KERNEL_BOUND = {"rot": ("mfma", "k_rot_mfma3"), "gram": ("mfma", "k_gram_mfma"),
+KERNEL_BOUND = {"rot": ("mfma", "k_rot_mfma3"), "gram": ("mfma", "k_gram_mfma2"),
                 "eig": ("alu", "k_eig"), "qr": ("alu", "k_qr_update")}
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "jacobi_traffic_chi1024_batched.md")
 JACOBI_SRC = os.path.join(ROOT, "paper_2601_04422_amd", "csrc", "k_jacobi.hip")

@@ -184,7 +184,7 @@ __global__ __launch_bounds__(256) void k_gram(const GateDesc *descs, int round, 
     __syncthreads();
   }
   if (tid == 0 && d.ctr && rend > rbeg) {
-    atomicAdd(&d.ctr[CTR_GRAM_FLOP], 8ull * (rend - rbeg) * PW * PW);
+    atomicAdd(&d.ctr[CTR_GRAM_FLOP], 8ull * (rend - rbeg) * (PW * (PW + 1) / 2));
     atomicAdd(&d.ctr[CTR_GRAM_BYTE], 16ull * (rend - rbeg) * PW + 16ull * PW * PW);
   }
   double2 *G = d.Gp + ((size_t)kc * d.gpStride + pairIdx) * (PW * PW);
@@ -209,6 +209,7 @@ __device__ __forceinline__ d4_t mfma64(double a, double b, d4_t c) {
 // pair solve mirrors the lower triangle.  Five wavefronts take two tiles each;
 // the first four load the rows.
 constexpr int GRAM_WAVES = 5;
+constexpr int GKM = 32;  // rows per LDS tile
 __constant__ int kGramTiles[GRAM_WAVES][2][2] = {{{0, 0}, {0, 1}}, {{0, 2}, {0, 3}},
                                                  {{1, 1}, {1, 2}}, {{1, 3}, {2, 2}},
                                                  {{2, 3}, {3, 3}}};
@@ -222,11 +223,11 @@ __global__ __launch_bounds__(64 * GRAM_WAVES) void k_gram_mfma(const GateDesc *d
   rr_pair(round, pairIdx, d.nblk, I, J);
   if (pair_known_orthogonal(d, I, J)) return;
   int chunk = (d.rows + ksplit - 1) / ksplit;
-  chunk = (chunk + GK - 1) / GK * GK;
+  chunk = (chunk + GKM - 1) / GKM * GKM;
   const int rbeg = kc * chunk;
   const int rend = min(d.rows, rbeg + chunk);
 
-  __shared__ double2 Xs[GK][PW + 1];
+  __shared__ double2 Xs[GKM][PW + 1];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int l16 = lane & 15, lg = lane >> 4;
   const bool loader = tid < 256;  // 64 columns x 4 groups of 8 rows
@@ -242,31 +243,31 @@ __global__ __launch_bounds__(64 * GRAM_WAVES) void k_gram_mfma(const GateDesc *d
     accR[t] = d4_t{0.0, 0.0, 0.0, 0.0};
     accI[t] = d4_t{0.0, 0.0, 0.0, 0.0};
   }
-  const int lcol = (tid >> 2) & (PW - 1), lr = (tid & 3) * 8;
+  const int lcol = (tid >> 2) & (PW - 1), lr = (tid & 3) * (GKM / 4);
   const double2 *xcol = d.X + (size_t)pair_col(I, J, lcol) * d.ldx;
-  double2 pre[8];  // next row tile, loaded while the current one is multiplied
+  double2 pre[GKM / 4];  // next row tile, loaded while the current one is multiplied
   if (loader) {
 #pragma unroll
-    for (int j = 0; j < 8; j++) {
+    for (int j = 0; j < GKM / 4; j++) {
       int r = rbeg + lr + j;
       pre[j] = r < rend ? xcol[r] : make_double2(0.0, 0.0);
     }
   }
-  for (int r0 = rbeg; r0 < rend; r0 += GK) {
+  for (int r0 = rbeg; r0 < rend; r0 += GKM) {
     if (loader) {
 #pragma unroll
-      for (int j = 0; j < 8; j++) Xs[lr + j][lcol] = pre[j];
+      for (int j = 0; j < GKM / 4; j++) Xs[lr + j][lcol] = pre[j];
     }
     __syncthreads();
-    if (loader && r0 + GK < rend) {
+    if (loader && r0 + GKM < rend) {
 #pragma unroll
-      for (int j = 0; j < 8; j++) {
-        int r = r0 + GK + lr + j;
+      for (int j = 0; j < GKM / 4; j++) {
+        int r = r0 + GKM + lr + j;
         pre[j] = r < rend ? xcol[r] : make_double2(0.0, 0.0);
       }
     }
 #pragma unroll
-    for (int kk = 0; kk < GK; kk += 4) {
+    for (int kk = 0; kk < GKM; kk += 4) {
       const int row = kk + lg;
       // G_pq = sum_r conj(x_rp) x_rq
 #pragma unroll
@@ -282,7 +283,7 @@ __global__ __launch_bounds__(64 * GRAM_WAVES) void k_gram_mfma(const GateDesc *d
     __syncthreads();
   }
   if (tid == 0 && d.ctr && rend > rbeg) {
-    atomicAdd(&d.ctr[CTR_GRAM_FLOP], 8ull * (rend - rbeg) * PW * PW);
+    atomicAdd(&d.ctr[CTR_GRAM_FLOP], 8ull * (rend - rbeg) * (PW * (PW + 1) / 2));
     atomicAdd(&d.ctr[CTR_GRAM_BYTE], 16ull * (rend - rbeg) * PW + 16ull * PW * PW);
   }
   double2 *G = d.Gp + ((size_t)kc * d.gpStride + pairIdx) * (PW * PW);
@@ -293,6 +294,86 @@ __global__ __launch_bounds__(64 * GRAM_WAVES) void k_gram_mfma(const GateDesc *d
       int p = tI[t] * 16 + lg + 4 * e, q = tJ[t] * 16 + l16;
       G[p * PW + q] = make_double2(accR[t][e], accI[t][e]);
     }
+}
+
+// Pair Gram, variant 2: no LDS staging.  In one k-step (4 rows) lane l reads
+// row 4 s + l/16 of the pair's columns 16 t + l%16 (t = 0..3): that is both
+// the A operand (conjugated) and the B operand of v_mfma_f64_16x16x4 for
+// every tile, so four loads feed all 10 upper tiles (40 MFMAs).  Each
+// wavefront takes every fourth 16-row tile; the four partial Grams are summed
+// in LDS in a fixed order at the end.
+constexpr int GT_A[10] = {0, 0, 0, 0, 1, 1, 1, 2, 2, 3};
+constexpr int GT_B[10] = {0, 1, 2, 3, 1, 2, 3, 2, 3, 3};
+
+__global__ __launch_bounds__(256, 2) void k_gram_mfma2(const GateDesc *descs, int round,
+                                                       int ksplit) {
+  const GateDesc &d = descs[blockIdx.y];
+  const int pairIdx = blockIdx.x / ksplit, kc = blockIdx.x % ksplit;
+  if (!d.sc->active || round >= d.nblk - 1 || pairIdx >= d.nblk / 2) return;
+  int I, J;
+  rr_pair(round, pairIdx, d.nblk, I, J);
+  if (pair_known_orthogonal(d, I, J)) return;
+  int chunk = (d.rows + ksplit - 1) / ksplit;
+  chunk = (chunk + 15) / 16 * 16;
+  const int rbeg = kc * chunk;
+  const int rend = min(d.rows, rbeg + chunk);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int l16 = lane & 15, lg = lane >> 4;
+  const double2 *xc[4];
+#pragma unroll
+  for (int t = 0; t < 4; t++) xc[t] = d.X + (size_t)pair_col(I, J, t * 16 + l16) * d.ldx;
+  d4_t accR[10], accI[10];
+#pragma unroll
+  for (int u = 0; u < 10; u++) {
+    accR[u] = d4_t{0.0, 0.0, 0.0, 0.0};
+    accI[u] = d4_t{0.0, 0.0, 0.0, 0.0};
+  }
+  for (int rt = rbeg + wave * 16; rt < rend; rt += 64) {
+#pragma unroll
+    for (int ks = 0; ks < 4; ks++) {
+      const int r = rt + 4 * ks + lg;
+      double2 x[4];
+#pragma unroll
+      for (int t = 0; t < 4; t++) x[t] = r < rend ? xc[t][r] : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int u = 0; u < 10; u++) {
+        const double2 a = x[GT_A[u]], b = x[GT_B[u]];  // G_pq += conj(x_rp) x_rq
+        accR[u] = mfma64(a.x, b.x, accR[u]);
+        accR[u] = mfma64(a.y, b.y, accR[u]);
+        accI[u] = mfma64(a.x, b.y, accI[u]);
+        accI[u] = mfma64(-a.y, b.x, accI[u]);
+      }
+    }
+  }
+  // sum of the four wavefronts' partials, in wavefront order
+  __shared__ double red[10][4][64][2];
+  for (int w = 0; w < 4; w++) {
+    if (wave == w) {
+#pragma unroll
+      for (int u = 0; u < 10; u++)
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+          if (w == 0) {
+            red[u][v][lane][0] = accR[u][v];
+            red[u][v][lane][1] = accI[u][v];
+          } else {
+            red[u][v][lane][0] += accR[u][v];
+            red[u][v][lane][1] += accI[u][v];
+          }
+        }
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && d.ctr && rend > rbeg) {
+    atomicAdd(&d.ctr[CTR_GRAM_FLOP], 8ull * (rend - rbeg) * (PW * (PW + 1) / 2));
+    atomicAdd(&d.ctr[CTR_GRAM_BYTE], 16ull * (rend - rbeg) * PW + 16ull * PW * PW);
+  }
+  double2 *G = d.Gp + ((size_t)kc * d.gpStride + pairIdx) * (PW * PW);
+  for (int e = tid; e < 10 * 4 * 64; e += 256) {
+    const int u = e / 256, v = (e / 64) % 4, l = e % 64;
+    const int p = GT_A[u] * 16 + (l >> 4) + 4 * v, q = GT_B[u] * 16 + (l & 15);
+    G[p * PW + q] = make_double2(red[u][v][l][0], red[u][v][l][1]);
+  }
 }
 
 // ---------------------------------------------------------------- 64x64 Hermitian Jacobi
@@ -845,7 +926,15 @@ static bool use_mfma() {
 void launch_gram(hipStream_t st, const GateDesc *d, int ng, int round, int max_pairs,
                  int ksplit) {
   if (ng <= 0) return;
-  if (use_mfma())
+  static int variant = -1;  // TNSIM_GRAM_KERNEL=1 selects the LDS-staged kernel
+  if (variant < 0) {
+    const char *e = getenv("TNSIM_GRAM_KERNEL");
+    variant = (e && e[0] == '1') ? 1 : 2;
+  }
+  if (use_mfma() && variant == 2)
+    hipLaunchKernelGGL(k_gram_mfma2, dim3(max_pairs * ksplit, ng), dim3(256), 0, st, d, round,
+                       ksplit);
+  else if (use_mfma())
     hipLaunchKernelGGL(k_gram_mfma, dim3(max_pairs * ksplit, ng), dim3(64 * GRAM_WAVES), 0, st, d,
                        round, ksplit);
   else
