@@ -385,8 +385,11 @@ constexpr int EIG_THREADS = 512;  // 8 wavefronts hide the LDS latency of the pa
 // rotations accumulated in V.  A round applies the 32 disjoint rotations of
 // the round-robin pairing at once: G <- R^H G R, V <- V R.  Entries of G are
 // updated as 2x2 blocks (rows of one pair x columns of another), so every
-// entry is read and written once per round.  At most `inner_sweeps` sweeps;
-// the outer sweeps finish what a capped inner solve leaves.
+// entry is read and written once per round.  The rotations of round r + 1
+// are computed by the first wavefront while the others apply round r to V
+// (parameters double-buffered), so a round costs two barriers.  At most
+// `inner_sweeps` sweeps; the outer sweeps finish what a capped inner solve
+// leaves.
 __global__ __launch_bounds__(EIG_THREADS) void k_eig(const GateDesc *descs, int round, int ksplit) {
   const GateDesc &d = descs[blockIdx.y];
   const int pairIdx = blockIdx.x;
@@ -399,11 +402,12 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(const GateDesc *descs, int 
   }
   __shared__ double2 Gs[PW * LDG];
   __shared__ double2 Vs[PW * LDG];
-  __shared__ double rc[PW / 2];    // cos
-  __shared__ double2 rse[PW / 2];  // s * e^{i phi}
-  __shared__ double rdp[PW / 2], rdq[PW / 2];  // new diagonal entries
-  __shared__ int rp[PW / 2], rq[PW / 2], ract[PW / 2];
-  __shared__ int any_rot, sweep_rot, first_rot;
+  __shared__ double rc[2][PW / 2];    // cos
+  __shared__ double2 rse[2][PW / 2];  // s * e^{i phi}
+  __shared__ double rdp[2][PW / 2], rdq[2][PW / 2];  // new diagonal entries
+  __shared__ int rp[2][PW / 2], rq[2][PW / 2], ract[2][PW / 2];
+  __shared__ int anyr[2];  // some rotation in the round held by that buffer
+  __shared__ int sweep_rot, first_rot;
   const int tid = threadIdx.x;
   const double tol = d.tol;
   const double small = small_norm2(d);
@@ -414,83 +418,89 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(const GateDesc *descs, int 
     // the Gram kernels store the upper 16x16 tiles; lower ones are mirrored
     const bool lower = (r >> 4) > (c >> 4);
     const int src = lower ? c * PW + r : e;
-    double2 s = make_double2(0.0, 0.0);
+    double2 sm = make_double2(0.0, 0.0);
     for (int kc = 0; kc < ksplit; kc++) {
       double2 v = d.Gp[((size_t)kc * d.gpStride + pairIdx) * (PW * PW) + src];
-      s.x += v.x;
-      s.y += v.y;
+      sm.x += v.x;
+      sm.y += v.y;
     }
-    Gs[r * LDG + c] = lower ? cconj(s) : s;
+    Gs[r * LDG + c] = lower ? cconj(sm) : sm;
     Vs[r * LDG + c] = make_double2(r == c ? 1.0 : 0.0, 0.0);
   }
   if (tid == 0) first_rot = 0;
   __syncthreads();
 
+  // Rotations of round r into buffer b, from the current G (first wavefront
+  // only: lanes < 32 hold one pair each, the ballot gives the round's flag).
+  auto params = [&](int r, int b) {
+    int act = 0;
+    if (tid < PW / 2) {
+      int p, q;
+      rr_pair(r, tid, PW, p, q);
+      rp[b][tid] = p;
+      rq[b][tid] = q;
+      const double a = Gs[p * LDG + p].x, bb = Gs[q * LDG + q].x;
+      const double2 g = Gs[p * LDG + q];
+      const double ag = sqrt(cabs2(g));
+      double c = 1.0;
+      double2 se = make_double2(0.0, 0.0);
+      if (a > small && bb > small && ag > tol * sqrt(a) * sqrt(bb)) {
+        act = 1;
+        const double2 e = make_double2(g.x / ag, g.y / ag);  // e^{i phi}
+        const double zeta = (bb - a) / (2.0 * ag);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        c = 1.0 / sqrt(1.0 + t * t);
+        const double sn = c * t;
+        se = make_double2(sn * e.x, sn * e.y);
+        rdp[b][tid] = a - t * ag;
+        rdq[b][tid] = bb + t * ag;
+        nrot_local++;
+      }
+      rc[b][tid] = c;
+      rse[b][tid] = se;
+      ract[b][tid] = act;
+    }
+    const unsigned long long m = __ballot(act);
+    if (tid == 0) anyr[b] = m != 0ull;
+  };
+
   for (int sweep = 0; sweep < d.innerSweeps; sweep++) {
     if (tid == 0) sweep_rot = 0;
+    if (tid < 64) params(0, 0);
     __syncthreads();
     for (int r = 0; r < PW - 1; r++) {
-      if (tid == 0) any_rot = 0;
-      __syncthreads();
-      if (tid < PW / 2) {
-        int p, q;
-        rr_pair(r, tid, PW, p, q);
-        rp[tid] = p;
-        rq[tid] = q;
-        double a = Gs[p * LDG + p].x, b = Gs[q * LDG + q].x;
-        double2 g = Gs[p * LDG + q];
-        double ag = sqrt(cabs2(g));
-        int act = 0;
-        double c = 1.0;
-        double2 se = make_double2(0.0, 0.0);
-        if (a > small && b > small && ag > tol * sqrt(a) * sqrt(b)) {
-          act = 1;
-          double2 e = make_double2(g.x / ag, g.y / ag);  // e^{i phi}
-          double zeta = (b - a) / (2.0 * ag);
-          double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          c = 1.0 / sqrt(1.0 + t * t);
-          double sn = c * t;
-          se = make_double2(sn * e.x, sn * e.y);
-          rdp[tid] = a - t * ag;
-          rdq[tid] = b + t * ag;
-          any_rot = 1;  // benign race: every writer stores 1
-          nrot_local++;
-        }
-        rc[tid] = c;
-        rse[tid] = se;
-        ract[tid] = act;
-      }
-      __syncthreads();
-      if (any_rot) {
+      const int b = r & 1;
+      const bool any = anyr[b] != 0;
+      if (any) {
         // R = [[c, s e^{i phi}], [-s e^{-i phi}, c]] on columns (p, q);
         // block (row pair i, column pair j): B <- R_i^H B R_j
         for (int task = tid; task < (PW / 2) * (PW / 2); task += EIG_THREADS) {
           const int i = task >> 5, j = task & 31;
-          if (!ract[i] && !ract[j]) continue;
-          const int pi = rp[i], qi = rq[i], pj = rp[j], qj = rq[j];
+          if (!ract[b][i] && !ract[b][j]) continue;
+          const int pi = rp[b][i], qi = rq[b][i], pj = rp[b][j], qj = rq[b][j];
           double2 b00 = Gs[pi * LDG + pj], b01 = Gs[pi * LDG + qj];
           double2 b10 = Gs[qi * LDG + pj], b11 = Gs[qi * LDG + qj];
-          if (ract[j]) {  // columns: [x_p x_q] R
-            const double c = rc[j];
-            const double2 se = rse[j], sec = cconj(se);
+          if (ract[b][j]) {  // columns: [x_p x_q] R
+            const double c = rc[b][j];
+            const double2 se = rse[b][j], sec = cconj(se);
             double2 n00 = csub(cscale(b00, c), cmul(sec, b01));
             double2 n01 = cadd(cmul(se, b00), cscale(b01, c));
             double2 n10 = csub(cscale(b10, c), cmul(sec, b11));
             double2 n11 = cadd(cmul(se, b10), cscale(b11, c));
             b00 = n00; b01 = n01; b10 = n10; b11 = n11;
           }
-          if (ract[i]) {  // rows: R^H [row_p; row_q]
-            const double c = rc[i];
-            const double2 se = rse[i], sec = cconj(se);
+          if (ract[b][i]) {  // rows: R^H [row_p; row_q]
+            const double c = rc[b][i];
+            const double2 se = rse[b][i], sec = cconj(se);
             double2 n00 = csub(cscale(b00, c), cmul(se, b10));
             double2 n01 = csub(cscale(b01, c), cmul(se, b11));
             double2 n10 = cadd(cmul(sec, b00), cscale(b10, c));
             double2 n11 = cadd(cmul(sec, b01), cscale(b11, c));
             b00 = n00; b01 = n01; b10 = n10; b11 = n11;
           }
-          if (i == j && ract[i]) {  // the annihilated pair: exact values
-            b00 = make_double2(rdp[i], 0.0);
-            b11 = make_double2(rdq[i], 0.0);
+          if (i == j && ract[b][i]) {  // the annihilated pair: exact values
+            b00 = make_double2(rdp[b][i], 0.0);
+            b11 = make_double2(rdq[b][i], 0.0);
             b01 = make_double2(0.0, 0.0);
             b10 = make_double2(0.0, 0.0);
           }
@@ -499,22 +509,25 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(const GateDesc *descs, int 
           Gs[qi * LDG + pj] = b10;
           Gs[qi * LDG + qj] = b11;
         }
+      }
+      __syncthreads();  // G after round r
+      if (tid < 64 && r + 1 < PW - 1) params(r + 1, b ^ 1);
+      if (any) {
         // V <- V R (columns)
         for (int task = tid; task < PW * (PW / 2); task += EIG_THREADS) {
           const int j = task & 31, row = task >> 5;
-          if (!ract[j]) continue;
-          const int pj = rp[j], qj = rq[j];
-          const double c = rc[j];
-          const double2 se = rse[j];
+          if (!ract[b][j]) continue;
+          const int pj = rp[b][j], qj = rq[b][j];
+          const double c = rc[b][j];
+          const double2 se = rse[b][j];
           double2 xp = Vs[row * LDG + pj], xq = Vs[row * LDG + qj];
           Vs[row * LDG + pj] = csub(cscale(xp, c), cmul(cconj(se), xq));
           Vs[row * LDG + qj] = cadd(cmul(se, xp), cscale(xq, c));
         }
         if (tid == 0) sweep_rot = 1;
-        __syncthreads();
       }
+      __syncthreads();  // V after round r; rotations of round r + 1 ready
     }
-    __syncthreads();
     const int cont = sweep_rot;  // every thread reads before anyone clears it
     if (sweep == 0 && tid == 0) first_rot = cont;
     __syncthreads();
