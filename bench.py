@@ -340,6 +340,8 @@ def main():
 
     # --- batched mixed path from the snapshot
     mix = T.MPS(n, chi, 1e-12, precision=args.precision, storage=args.storage)
+    tuned = mix.autotune()
+    log(f"autotuned rows per rotation workgroup by pair-count class: {tuned}")
     mix.copy_from(ref)
     for l in range(P, P + Wu):
         run_layer_batched(mix, layers[l])
@@ -421,6 +423,7 @@ def main():
                                f"untimed (f64), {Wu} warmup + {K} timed layers",
                    "n_qubits": n, "chi_max": chi, "cutoff": 1e-12, "storage": args.storage,
                    "precision": args.precision, "timed_2q_gates": total2q,
+                   "autotuned_rot_rows": tuned,
                    "timed_gates_at_full_chi": full, "parallelism": "single gpu"},
         "all_2q_gates_per_s": total2q / mix_s,
         "pergate_fp64": pergate,

@@ -244,6 +244,19 @@ tnsim_status tnsim_profile(tnsim_mps mps, int32_t enable);
 /* out has TNSIM_K_COUNT entries (synchronising). */
 tnsim_status tnsim_profile_read(tnsim_mps mps, tnsim_kernel_stat *out);
 
+/* Launch-shape autotuner (synchronising).  Times the Jacobi rotation kernel
+   on this handle's workspace slots (zeroed scratch; the state is not touched)
+   for every candidate number of rows per workgroup (64, 128, 256, 512) in
+   each of TNSIM_TUNE_BUCKETS pair-count classes (<= 32, <= 128, <= 512 and
+   more pairs per launch, largest gate the handle can hold) and keeps the
+   fastest; later sweeps use the table instead of the built-in rule.  The
+   choice does not change any result: every row is computed the same way.
+   table_out (host, TNSIM_TUNE_BUCKETS entries, may be NULL) receives the rows
+   per workgroup chosen for each class.  Errors: TNSIM_E_ARG (bad handle),
+   TNSIM_E_DEVICE. */
+#define TNSIM_TUNE_BUCKETS 4
+tnsim_status tnsim_autotune(tnsim_mps mps, int32_t *table_out);
+
 const char *tnsim_status_string(tnsim_status st);
 const char *tnsim_last_error(tnsim_mps mps);
 

@@ -237,6 +237,8 @@ struct tnsim_mps_s {
   // captured Jacobi sweep (reused while the batch shape is unchanged)
   bool graphs = true;
   bool pair_skip = true;  // skip Grams of block pairs known orthogonal (TNSIM_PAIR_SKIP=0: off)
+  int gram_wg_target = 1024;  // K-split the pair Grams up to this many workgroups
+  int tune_rot_rows[TNSIM_TUNE_BUCKETS] = {0, 0, 0, 0};  // autotuned, 0 = built-in rule
   hipGraphExec_t sweep_exec = nullptr;
   long long sweep_key[7] = {-1, -1, -1, -1, -1, -1, -1};
   int64_t sw_gates = 0, sw_sum = 0;
@@ -360,6 +362,9 @@ struct BatchItem {
   int slot;
   const Pending *p;
 };
+
+// Pair-count class of a launch, for the autotuned rotation shape.
+int tune_bucket(int pairs) { return pairs <= 32 ? 0 : pairs <= 128 ? 1 : pairs <= 512 ? 2 : 3; }
 
 SlotScalars *pin_scalars(tnsim_mps o) {
   return reinterpret_cast<SlotScalars *>(o->pin + align_up(sizeof(GateDesc) * o->L.desc_cap));
@@ -528,7 +533,7 @@ tnsim_status run_2q_items(tnsim_mps o, const BatchItem *items, int ng, bool forc
       if (d.trans) P.maxMtrans = std::max(P.maxMtrans, d.m);
     }
     const int pairs = P.na * P.maxPairs;
-    int ks = (1024 + pairs - 1) / pairs;
+    int ks = (o->gram_wg_target + pairs - 1) / pairs;
     ks = std::min(ks, KSPLIT_MAX);
     ks = std::min(ks, std::max(1, (P.maxRows + 31) / 32));
     // each gate's partials go to its handle's pool, at its position among the
@@ -543,8 +548,13 @@ tnsim_status run_2q_items(tnsim_mps o, const BatchItem *items, int ng, bool forc
     }
     P.ksplit = std::max(ks, 1);
     const int rchunks = std::max(1, P.maxRows + P.maxMtrans);
-    while (P.rotRows > 64 && (long long)pairs * ((rchunks + P.rotRows - 1) / P.rotRows) < 1024)
-      P.rotRows /= 2;
+    const int tuned = o->tune_rot_rows[tune_bucket(pairs)];
+    if (tuned > 0) {
+      P.rotRows = tuned;
+    } else {
+      while (P.rotRows > 64 && (long long)pairs * ((rchunks + P.rotRows - 1) / P.rotRows) < 1024)
+        P.rotRows /= 2;
+    }
     GateDesc *stage = reinterpret_cast<GateDesc *>(o->pin);
     for (size_t a = 0; a < act.size(); a++) {
       const tnsim_mps hg = items[act[a]].h;
@@ -1280,6 +1290,10 @@ tnsim_status tnsim_mps_create(const tnsim_config *cfg, void *dev_arena, size_t a
   h->device = dev;
   if (const char *e = getenv("TNSIM_GRAPHS")) h->graphs = atoi(e) != 0;
   if (const char *e = getenv("TNSIM_PAIR_SKIP")) h->pair_skip = atoi(e) != 0;
+  if (const char *e = getenv("TNSIM_GRAM_WG_TARGET")) {
+    int v = atoi(e);
+    if (v >= 1 && v <= 1 << 20) h->gram_wg_target = v;
+  }
   if (const char *e = getenv("TNSIM_INNER_SWEEPS")) {
     int v = atoi(e);
     if (v >= 1 && v <= 60) h->inner_sweeps = v;
@@ -1843,6 +1857,81 @@ tnsim_status tnsim_profile_read(tnsim_mps h, tnsim_kernel_stat *out) {
   out[TNSIM_K_EIG].bytes = 0.0;
   out[TNSIM_K_ROT].flops = (double)ctr[CTR_ROT_FLOP];
   out[TNSIM_K_ROT].bytes = (double)ctr[CTR_ROT_BYTE];
+  return TNSIM_OK;
+}
+
+tnsim_status tnsim_autotune(tnsim_mps h, int32_t *table_out) {
+  tnsim_status s = check_handle(h);
+  if (s != TNSIM_OK) return s;
+  const Layout &L = h->L;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  prof_drain(h);
+  // Synthetic gates of the largest shape the handle holds: X (rows x cols)
+  // zeroed, every pair flagged for rotation, V zeroed.
+  const int cols = L.cols_pad_max, rows = L.cmax;
+  const int npairs = cols / PW;
+  const int want[TNSIM_TUNE_BUCKETS] = {32, 128, 512, 1600};
+  const int cand[4] = {64, 128, 256, 512};
+  std::vector<GateDesc> D(L.nslots);
+  for (int g = 0; g < L.nslots; g++) {
+    GateDesc &d = D[g];
+    memset(&d, 0, sizeof d);
+    char *sl = h->slot(g);
+    d.rows = rows;
+    d.cols = cols;
+    d.m = rows;
+    d.n = cols;
+    d.ldx = L.ldx_max;
+    d.colsPad = cols;
+    d.nblk = cols / BW;
+    d.X = (double2 *)(sl + L.x_off);
+    d.V = (double2 *)(sl + L.v_off);
+    d.pairFlag = (int *)(sl + L.pf_off);
+    d.sc = (SlotScalars *)(sl + L.sc_off);
+    launch_fill_zero(h->stream, d.X, sizeof(double2) * (size_t)L.ldx_max * cols);
+    launch_fill_zero(h->stream, d.V, sizeof(double2) * (size_t)npairs * PW * PW);
+  }
+  std::vector<int32_t> ones(npairs, 1);
+  SlotScalars act{};
+  act.active = 1;
+  for (int g = 0; g < L.nslots; g++) {
+    HIPCHK(h, hipMemcpyAsync(D[g].pairFlag, ones.data(), sizeof(int32_t) * npairs,
+                             hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(D[g].sc, &act, sizeof act, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));  // the host sources are reused
+  }
+  GateDesc *ddev = h->at<GateDesc>(L.desc_off);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(h, hipEventCreate(&e0));
+  HIPCHK(h, hipEventCreate(&e1));
+  for (int bk = 0; bk < TNSIM_TUNE_BUCKETS; bk++) {
+    const int ng = std::max(1, std::min(L.nslots, (want[bk] + npairs - 1) / npairs));
+    int best = 0;
+    float best_ms = 0.0f;
+    for (int ci = 0; ci < 4; ci++) {
+      const int rr = cand[ci];
+      for (int g = 0; g < ng; g++) D[g].rotRows = rr;
+      memcpy(h->pin, D.data(), sizeof(GateDesc) * ng);
+      HIPCHK(h, hipMemcpyAsync(ddev, h->pin, sizeof(GateDesc) * ng, hipMemcpyHostToDevice,
+                               h->stream));
+      launch_rot(h->stream, ddev, ng, 0, npairs, rows, 0, rr);  // warm-up
+      HIPCHK(h, hipEventRecord(e0, h->stream));
+      for (int r = 0; r < 3; r++) launch_rot(h->stream, ddev, ng, r, npairs, rows, 0, rr);
+      HIPCHK(h, hipEventRecord(e1, h->stream));
+      LAUNCHCHK(h, "autotune");
+      HIPCHK(h, hipEventSynchronize(e1));
+      float ms = 0.0f;
+      HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
+      if (best == 0 || ms < best_ms) {
+        best = rr;
+        best_ms = ms;
+      }
+    }
+    h->tune_rot_rows[bk] = best;
+    if (table_out) table_out[bk] = best;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
   return TNSIM_OK;
 }
 

@@ -75,6 +75,7 @@ _SIGS = {
     "tnsim_backward": (C.c_int, [_P, C.c_double, _P]),
     "tnsim_profile": (C.c_int, [_P, C.c_int32]),
     "tnsim_profile_read": (C.c_int, [_P, _P]),
+    "tnsim_autotune": (C.c_int, [_P, _P]),
     "tnsim_status_string": (C.c_char_p, [C.c_int]),
     "tnsim_last_error": (C.c_char_p, [_P]),
 }
@@ -339,6 +340,14 @@ class MPS:
         self._chk(lib().tnsim_profile_read(self._h, out.ctypes.data), "profile_read")
         return {k: {f: out[i][f].item() for f in KSTAT_DTYPE.names}
                 for i, k in enumerate(KERNEL_CLASSES)}
+
+    def autotune(self) -> list:
+        """Time the rotation kernel's launch shapes on this handle's scratch
+        slots and keep the fastest per pair-count class (results unchanged).
+        Returns the rows per workgroup chosen for each class."""
+        out = np.zeros(4, dtype=np.int32)
+        self._chk(lib().tnsim_autotune(self._h, out.ctypes.data), "autotune")
+        return out.tolist()
 
     def site(self, q: int) -> np.ndarray:
         a, b = C.c_int32(), C.c_int32()

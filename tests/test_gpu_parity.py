@@ -243,18 +243,20 @@ def test_multi_circuit_batch_vs_oracle(T):
             assert np.max(np.abs(ms[k].lam(b) - o.lam(b))) < 1e-10
 
 
-def test_graph_replay_matches_eager(T):
+@pytest.mark.parametrize("precision,storage", [("fp64", "c128"), ("bf16x6", "c64")])
+def test_graph_replay_matches_eager(T, precision, storage):
     """A non-default stream captures each batch's Jacobi sweep as a HIP graph
     and replays it once per sweep (with the host's convergence check and
     other eager work between replays); every result must equal the eager
-    launches bit for bit."""
+    launches bit for bit (float64 plain Jacobi, and the mixed path with the
+    QR-preconditioned SVD)."""
     import torch
 
     n = 16
     layers = W.brickwork_haar(n, 10, 77)
     s = torch.cuda.Stream()
-    g = T.MPS(n, 24, 1e-10, stream=s)
-    e = T.MPS(n, 24, 1e-10)
+    g = T.MPS(n, 24, 1e-10, precision=precision, storage=storage, stream=s)
+    e = T.MPS(n, 24, 1e-10, precision=precision, storage=storage)
     for layer in layers:
         assert g.apply_layer(layer) == T.OK
         assert e.apply_layer(layer) == T.OK
@@ -304,3 +306,20 @@ def test_qr_preconditioned_amplitudes(T):
         gates.append((j, j + 1, W.haar_u4(rng)) if rng.random() < 0.5 else (j + 1, j, W.haar_u4(rng)))
     g.run_gates(gates)
     assert np.max(np.abs(gpu_statevector(g) - statevector(9, gates))) < 1e-12
+
+
+def test_autotuned_launch_shapes_leave_results_unchanged(T):
+    """The autotuner only picks rows per rotation workgroup; a tuned handle
+    must give the same state bit for bit as one on the built-in rule."""
+    n = 16
+    layers = W.brickwork_haar(n, 10, 55)
+    a = T.MPS(n, 24, 1e-10, precision="bf16x6", storage="c64")
+    b = T.MPS(n, 24, 1e-10, precision="bf16x6", storage="c64")
+    table = a.autotune()
+    assert len(table) == 4 and all(t in (64, 128, 256, 512) for t in table)
+    a.run_layers(layers)
+    b.run_layers(layers)
+    for q in range(n):
+        assert np.array_equal(a.site(q), b.site(q))
+    for k in range(n - 1):
+        assert np.array_equal(a.lam(k), b.lam(k))
