@@ -473,29 +473,45 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(const GateDesc *descs, int 
       const bool any = anyr[b] != 0;
       if (any) {
         // R = [[c, s e^{i phi}], [-s e^{-i phi}, c]] on columns (p, q);
-        // block (row pair i, column pair j): B <- R_i^H B R_j
-        for (int task = tid; task < (PW / 2) * (PW / 2); task += EIG_THREADS) {
-          const int i = task >> 5, j = task & 31;
-          if (!ract[b][i] && !ract[b][j]) continue;
-          const int pi = rp[b][i], qi = rq[b][i], pj = rp[b][j], qj = rq[b][j];
-          double2 b00 = Gs[pi * LDG + pj], b01 = Gs[pi * LDG + qj];
-          double2 b10 = Gs[qi * LDG + pj], b11 = Gs[qi * LDG + qj];
-          if (ract[b][j]) {  // columns: [x_p x_q] R
-            const double c = rc[b][j];
-            const double2 se = rse[b][j], sec = cconj(se);
-            double2 n00 = csub(cscale(b00, c), cmul(sec, b01));
-            double2 n01 = cadd(cmul(se, b00), cscale(b01, c));
-            double2 n10 = csub(cscale(b10, c), cmul(sec, b11));
-            double2 n11 = cadd(cmul(se, b10), cscale(b11, c));
+        // block (row pair i, column pair j): B <- R_i^H B R_j.  A pair that
+        // does not rotate has c = 1, s = 0, which leaves its entries exactly
+        // as they are, so every block is updated without branches; each
+        // thread loads both of its blocks before computing.
+        static_assert((PW / 2) * (PW / 2) == 2 * EIG_THREADS, "two blocks per thread");
+        const int j = tid & 31, i0 = tid >> 5;
+        const int pj = rp[b][j], qj = rq[b][j];
+        const double cj = rc[b][j];
+        const double2 sej = rse[b][j], secj = cconj(sej);
+        double2 blk[2][4];
+        int pis[2], qis[2];
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+          const int i = i0 + 16 * h;
+          pis[h] = rp[b][i];
+          qis[h] = rq[b][i];
+          blk[h][0] = Gs[pis[h] * LDG + pj];
+          blk[h][1] = Gs[pis[h] * LDG + qj];
+          blk[h][2] = Gs[qis[h] * LDG + pj];
+          blk[h][3] = Gs[qis[h] * LDG + qj];
+        }
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+          const int i = i0 + 16 * h;
+          double2 b00 = blk[h][0], b01 = blk[h][1], b10 = blk[h][2], b11 = blk[h][3];
+          {  // columns: [x_p x_q] R_j
+            double2 n00 = csub(cscale(b00, cj), cmul(secj, b01));
+            double2 n01 = cadd(cmul(sej, b00), cscale(b01, cj));
+            double2 n10 = csub(cscale(b10, cj), cmul(secj, b11));
+            double2 n11 = cadd(cmul(sej, b10), cscale(b11, cj));
             b00 = n00; b01 = n01; b10 = n10; b11 = n11;
           }
-          if (ract[b][i]) {  // rows: R^H [row_p; row_q]
-            const double c = rc[b][i];
-            const double2 se = rse[b][i], sec = cconj(se);
-            double2 n00 = csub(cscale(b00, c), cmul(se, b10));
-            double2 n01 = csub(cscale(b01, c), cmul(se, b11));
-            double2 n10 = cadd(cmul(sec, b00), cscale(b10, c));
-            double2 n11 = cadd(cmul(sec, b01), cscale(b11, c));
+          {  // rows: R_i^H [row_p; row_q]
+            const double ci = rc[b][i];
+            const double2 sei = rse[b][i], seci = cconj(sei);
+            double2 n00 = csub(cscale(b00, ci), cmul(sei, b10));
+            double2 n01 = csub(cscale(b01, ci), cmul(sei, b11));
+            double2 n10 = cadd(cmul(seci, b00), cscale(b10, ci));
+            double2 n11 = cadd(cmul(seci, b01), cscale(b11, ci));
             b00 = n00; b01 = n01; b10 = n10; b11 = n11;
           }
           if (i == j && ract[b][i]) {  // the annihilated pair: exact values
@@ -504,25 +520,33 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(const GateDesc *descs, int 
             b01 = make_double2(0.0, 0.0);
             b10 = make_double2(0.0, 0.0);
           }
-          Gs[pi * LDG + pj] = b00;
-          Gs[pi * LDG + qj] = b01;
-          Gs[qi * LDG + pj] = b10;
-          Gs[qi * LDG + qj] = b11;
+          Gs[pis[h] * LDG + pj] = b00;
+          Gs[pis[h] * LDG + qj] = b01;
+          Gs[qis[h] * LDG + pj] = b10;
+          Gs[qis[h] * LDG + qj] = b11;
         }
       }
       __syncthreads();  // G after round r
       if (tid < 64 && r + 1 < PW - 1) params(r + 1, b ^ 1);
       if (any) {
-        // V <- V R (columns)
-        for (int task = tid; task < PW * (PW / 2); task += EIG_THREADS) {
-          const int j = task & 31, row = task >> 5;
-          if (!ract[b][j]) continue;
-          const int pj = rp[b][j], qj = rq[b][j];
-          const double c = rc[b][j];
-          const double2 se = rse[b][j];
-          double2 xp = Vs[row * LDG + pj], xq = Vs[row * LDG + qj];
-          Vs[row * LDG + pj] = csub(cscale(xp, c), cmul(cconj(se), xq));
-          Vs[row * LDG + qj] = cadd(cmul(se, xp), cscale(xq, c));
+        // V <- V R (columns); four rows per thread, loads first
+        static_assert(PW * (PW / 2) == 4 * EIG_THREADS, "four rows per thread");
+        const int j = tid & 31, row0 = tid >> 5;
+        const int pj = rp[b][j], qj = rq[b][j];
+        const double c = rc[b][j];
+        const double2 se = rse[b][j], sec = cconj(se);
+        double2 xp[4], xq[4];
+#pragma unroll
+        for (int h = 0; h < 4; h++) {
+          const int row = row0 + 16 * h;
+          xp[h] = Vs[row * LDG + pj];
+          xq[h] = Vs[row * LDG + qj];
+        }
+#pragma unroll
+        for (int h = 0; h < 4; h++) {
+          const int row = row0 + 16 * h;
+          Vs[row * LDG + pj] = csub(cscale(xp[h], c), cmul(sec, xq[h]));
+          Vs[row * LDG + qj] = cadd(cmul(se, xp[h]), cscale(xq[h], c));
         }
         if (tid == 0) sweep_rot = 1;
       }
