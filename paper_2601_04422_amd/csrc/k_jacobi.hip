@@ -379,7 +379,7 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma2(const GateDesc *descs, in
 // ---------------------------------------------------------------- 64x64 Hermitian Jacobi
 
 constexpr int LDG = PW + 1;
-constexpr int EIG_THREADS = 512;  // 8 wavefronts hide the LDS latency of the pair solve
+constexpr int EIG_THREADS = 1024;  // 16 wavefronts hide the LDS latency of the pair solve
 
 // Cyclic two-sided Jacobi on the pair Gram G (64x64, in LDS) with the
 // rotations accumulated in V.  A round applies the 32 disjoint rotations of
@@ -477,16 +477,17 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(const GateDesc *descs, int 
         // does not rotate has c = 1, s = 0, which leaves its entries exactly
         // as they are, so every block is updated without branches; each
         // thread loads both of its blocks before computing.
-        static_assert((PW / 2) * (PW / 2) == 2 * EIG_THREADS, "two blocks per thread");
+        constexpr int GPT = (PW / 2) * (PW / 2) / EIG_THREADS;  // blocks per thread
+        static_assert(GPT * EIG_THREADS == (PW / 2) * (PW / 2), "whole blocks per thread");
         const int j = tid & 31, i0 = tid >> 5;
         const int pj = rp[b][j], qj = rq[b][j];
         const double cj = rc[b][j];
         const double2 sej = rse[b][j], secj = cconj(sej);
-        double2 blk[2][4];
-        int pis[2], qis[2];
+        double2 blk[GPT][4];
+        int pis[GPT], qis[GPT];
 #pragma unroll
-        for (int h = 0; h < 2; h++) {
-          const int i = i0 + 16 * h;
+        for (int h = 0; h < GPT; h++) {
+          const int i = i0 + (EIG_THREADS / 32) * h;
           pis[h] = rp[b][i];
           qis[h] = rq[b][i];
           blk[h][0] = Gs[pis[h] * LDG + pj];
@@ -495,8 +496,8 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(const GateDesc *descs, int 
           blk[h][3] = Gs[qis[h] * LDG + qj];
         }
 #pragma unroll
-        for (int h = 0; h < 2; h++) {
-          const int i = i0 + 16 * h;
+        for (int h = 0; h < GPT; h++) {
+          const int i = i0 + (EIG_THREADS / 32) * h;
           double2 b00 = blk[h][0], b01 = blk[h][1], b10 = blk[h][2], b11 = blk[h][3];
           {  // columns: [x_p x_q] R_j
             double2 n00 = csub(cscale(b00, cj), cmul(secj, b01));
@@ -529,22 +530,23 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(const GateDesc *descs, int 
       __syncthreads();  // G after round r
       if (tid < 64 && r + 1 < PW - 1) params(r + 1, b ^ 1);
       if (any) {
-        // V <- V R (columns); four rows per thread, loads first
-        static_assert(PW * (PW / 2) == 4 * EIG_THREADS, "four rows per thread");
+        // V <- V R (columns); VPT rows per thread, loads first
+        constexpr int VPT = PW * (PW / 2) / EIG_THREADS;
+        static_assert(VPT * EIG_THREADS == PW * (PW / 2), "whole rows per thread");
         const int j = tid & 31, row0 = tid >> 5;
         const int pj = rp[b][j], qj = rq[b][j];
         const double c = rc[b][j];
         const double2 se = rse[b][j], sec = cconj(se);
-        double2 xp[4], xq[4];
+        double2 xp[VPT], xq[VPT];
 #pragma unroll
-        for (int h = 0; h < 4; h++) {
-          const int row = row0 + 16 * h;
+        for (int h = 0; h < VPT; h++) {
+          const int row = row0 + (EIG_THREADS / 32) * h;
           xp[h] = Vs[row * LDG + pj];
           xq[h] = Vs[row * LDG + qj];
         }
 #pragma unroll
-        for (int h = 0; h < 4; h++) {
-          const int row = row0 + 16 * h;
+        for (int h = 0; h < VPT; h++) {
+          const int row = row0 + (EIG_THREADS / 32) * h;
           Vs[row * LDG + pj] = csub(cscale(xp[h], c), cmul(sec, xq[h]));
           Vs[row * LDG + qj] = cadd(cmul(se, xp[h]), cscale(xq[h], c));
         }
