@@ -328,22 +328,40 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma2(const GateDesc *descs, in
     accR[u] = d4_t{0.0, 0.0, 0.0, 0.0};
     accI[u] = d4_t{0.0, 0.0, 0.0, 0.0};
   }
-  for (int rt = rbeg + wave * 16; rt < rend; rt += 64) {
+  // k-steps 0 and 1 of the wave's next 16-row tile are loaded while the
+  // current tile is multiplied; steps 2 and 3 while steps 0 and 1 are
+  auto load_step = [&](double2 *x, int r) {
 #pragma unroll
-    for (int ks = 0; ks < 4; ks++) {
-      const int r = rt + 4 * ks + lg;
-      double2 x[4];
+    for (int t = 0; t < 4; t++) x[t] = r < rend ? xc[t][r] : make_double2(0.0, 0.0);
+  };
+  auto mfma_step = [&](const double2 *x) {
 #pragma unroll
-      for (int t = 0; t < 4; t++) x[t] = r < rend ? xc[t][r] : make_double2(0.0, 0.0);
-#pragma unroll
-      for (int u = 0; u < 10; u++) {
-        const double2 a = x[GT_A[u]], b = x[GT_B[u]];  // G_pq += conj(x_rp) x_rq
-        accR[u] = mfma64(a.x, b.x, accR[u]);
-        accR[u] = mfma64(a.y, b.y, accR[u]);
-        accI[u] = mfma64(a.x, b.y, accI[u]);
-        accI[u] = mfma64(-a.y, b.x, accI[u]);
-      }
+    for (int u = 0; u < 10; u++) {
+      const double2 a = x[GT_A[u]], b = x[GT_B[u]];  // G_pq += conj(x_rp) x_rq
+      accR[u] = mfma64(a.x, b.x, accR[u]);
+      accR[u] = mfma64(a.y, b.y, accR[u]);
+      accI[u] = mfma64(a.x, b.y, accI[u]);
+      accI[u] = mfma64(-a.y, b.x, accI[u]);
     }
+  };
+  double2 xa[4], xb[4];  // steps 0, 1 of the current tile
+  int rt = rbeg + wave * 16;
+  if (rt < rend) {
+    load_step(xa, rt + lg);
+    load_step(xb, rt + 4 + lg);
+  }
+  for (; rt < rend; rt += 64) {
+    double2 xc2[4], xd[4];  // steps 2, 3
+    load_step(xc2, rt + 8 + lg);
+    load_step(xd, rt + 12 + lg);
+    mfma_step(xa);
+    mfma_step(xb);
+    if (rt + 64 < rend) {  // next tile's steps 0, 1
+      load_step(xa, rt + 64 + lg);
+      load_step(xb, rt + 68 + lg);
+    }
+    mfma_step(xc2);
+    mfma_step(xd);
   }
   // sum of the four wavefronts' partials, in wavefront order
   __shared__ double red[10][4][64][2];
