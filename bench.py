@@ -102,6 +102,9 @@ def parse():
     ap.add_argument("--storage", default="c64", choices=["c128", "c64"])
     ap.add_argument("--chi", type=int, default=1024)
     ap.add_argument("--no-pergate", action="store_true")
+    ap.add_argument("--circuit", action="store_true",
+                    help="batched path: the timed layers as one dependency-scheduled "
+                         "circuit call instead of one call per sublayer")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=16)
     ap.add_argument("--workload", default="chi1024",
@@ -353,16 +356,28 @@ def main():
     per_layer = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for l in range(P + Wu, P + Wu + K):
-        tl = time.perf_counter()
-        full += count_full(mix, layers[l][2], chi)
-        total2q += len(layers[l][2])
-        run_layer_batched(mix, layers[l])
-        per_layer.append(time.perf_counter() - tl)
+    if not args.circuit:
+        for l in range(P + Wu, P + Wu + K):
+            tl = time.perf_counter()
+            full += count_full(mix, layers[l][2], chi)
+            total2q += len(layers[l][2])
+            run_layer_batched(mix, layers[l])
+            per_layer.append(time.perf_counter() - tl)
+            lb = mix.last_batch()
+            worst = lb[np.argsort(-lb[:, 5])[:4]]
+            log(f"mixed layer {l}: {per_layer[-1]:.2f} s; sweeps mean {lb[:, 5].mean():.1f}, "
+                f"slowest (i,chiL,chiM,chiR,k,sweeps): {worst.tolist()}")
+    else:
+        # the timed layers as one circuit: gates start when their qubits are
+        # free, so the next layer's gates fill the sweeps of the last ones
+        circ = [g for l in range(P + Wu, P + Wu + K) for sub in layers[l] for g in sub]
+        mix.run_circuit(circ)
         lb = mix.last_batch()
-        worst = lb[np.argsort(-lb[:, 5])[:4]]
-        log(f"mixed layer {l}: {per_layer[-1]:.2f} s; sweeps mean {lb[:, 5].mean():.1f}, "
-            f"slowest (i,chiL,chiM,chiR,k,sweeps): {worst.tolist()}")
+        full = int(np.sum((lb[:, 1] == chi) & (lb[:, 2] == chi) & (lb[:, 3] == chi)))
+        total2q = len(lb)
+        per_layer.append(time.perf_counter() - t0)
+        log(f"mixed circuit, layers {P + Wu}-{P + Wu + K - 1}: {per_layer[-1]:.2f} s; "
+            f"sweeps mean {lb[:, 5].mean():.1f}")
     torch.cuda.synchronize()
     mix_s = time.perf_counter() - t0
     prof = mix.profile_read()
@@ -420,7 +435,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"n=100 circuit, layers of Rx,Rz on every qubit then CNOT on "
                                f"alternating bonds; chi_max={chi}, cutoff 1e-12; layers 0-{P-1} "
-                               f"untimed (f64), {Wu} warmup + {K} timed layers",
+                               f"untimed (f64), {Wu} warmup + {K} timed layers"
+                               + (" (one dependency-scheduled circuit call)" if args.circuit
+                                  else " (one call per sublayer)"),
                    "n_qubits": n, "chi_max": chi, "cutoff": 1e-12, "storage": args.storage,
                    "precision": args.precision, "timed_2q_gates": total2q,
                    "autotuned_rot_rows": tuned,

@@ -135,6 +135,20 @@ tnsim_status tnsim_apply_2q(tnsim_mps mps, int32_t q0, int32_t q1, const tnsim_c
    the same launches (batched over gates). */
 tnsim_status tnsim_apply_layer(tnsim_mps mps, const tnsim_gate *gates, int32_t n_gates);
 
+/* A whole circuit of local gates, in order (gates may share qubits; a gate
+   given as (q, q-1) is applied as SWAP G SWAP on (q-1, q), as in
+   tnsim_apply_2q).  The result equals applying the gates one by one (Sec.
+   III.A, gate application; Sec. IV.B, gates of a layer on disjoint qubits run
+   in parallel): a gate starts once the gates before it on its qubits are
+   done, and two-qubit gates in flight, from any layer, share the launches of
+   every Jacobi sweep.  gates: host array of n_gates entries, read during the
+   call only.  Errors: TNSIM_E_ARG (qubit out of range, q0 == q1),
+   TNSIM_E_NONLOCAL (validated before any work, state unchanged);
+   TNSIM_E_NOCONV (a Jacobi ran out of sweeps: the gates completed by then
+   stay applied, each one whole and in an order consistent with the circuit,
+   the others are not; the MPS stays valid); TNSIM_E_DEVICE. */
+tnsim_status tnsim_apply_circuit(tnsim_mps mps, const tnsim_gate *gates, int32_t n_gates);
+
 /* Independent circuits: layer l of every handle, batched together.  All
    handles must share one stream and one configuration class (precision and
    storage); gates[i] has n_gates[i] entries for handle i. */

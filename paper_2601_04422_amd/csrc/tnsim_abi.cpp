@@ -370,116 +370,118 @@ SlotScalars *pin_scalars(tnsim_mps o) {
   return reinterpret_cast<SlotScalars *>(o->pin + align_up(sizeof(GateDesc) * o->L.desc_cap));
 }
 
-// Run a batch of two-qubit gates (possibly of several handles) through the
-// whole path in the same launches.  `o` owns the descriptors, the stream and
-// the profiling; every gate works in its own handle's state and slot.
-tnsim_status run_2q_items(tnsim_mps o, const BatchItem *items, int ng, bool force_trans) {
-  const tnsim_config &c = o->cfg;
-  std::vector<GateDesc> D(ng);
-  int maxM = 0, maxN = 0, maxColsPad = 0, maxChiR = 0;
+// Descriptor of one two-qubit gate from its handle's current bond dimensions.
+// `o` owns the launches (profiling counters, the inner-sweep cap).
+GateDesc make_desc(tnsim_mps o, const BatchItem &it, bool force_trans) {
+  GateDesc d;
+  memset(&d, 0, sizeof d);
+  const tnsim_mps h = it.h;
+  const Layout &L = h->L;
+  const int i = it.p->i;
+  d.i = i;
+  d.chiL = h->dims[i];
+  d.chiM = h->dims[i + 1];
+  d.chiR = h->dims[i + 2];
+  d.m = 2 * d.chiL;
+  d.n = 2 * d.chiR;
+  // X = M^H (with the left vectors accumulated in J) when M is wide, or
+  // always when the caller needs the full left basis (the adjoint)
+  d.trans = force_trans || d.n > d.m;
+  // QR-preconditioned SVD for square or tall M that fits one panel workgroup
+  d.qr = h->cfg.svd_precondition && !d.trans && d.m <= QR_MAX_ROWS;
+  d.rows = d.qr ? d.n : (d.trans ? d.n : d.m);
+  d.cols = d.trans ? d.m : d.n;
+  d.ldx = pad_to(d.rows, 4);
+  d.ldj = pad_to(d.m, 4);
+  d.colsPad = pad_to(d.cols, PW);
+  d.nblk = d.colsPad / BW;
+  d.chiMax = h->cfg.chi_max;
+  d.storage = h->cfg.storage;
+  d.tfp32 = o->cfg.precision != TNSIM_FP64;
+  d.innerSweeps = o->inner_sweeps;
+  d.tol = h->cfg.jacobi_tol > 0 ? h->cfg.jacobi_tol : std::max(d.rows, 16) * 0x1p-53;
+  d.cutoff = h->cfg.cutoff;
+  d.A0 = h->site(i);
+  d.A1 = h->site(i + 1);
+  d.lamR = (i + 1 <= L.n - 2) ? h->lam(i + 1) : nullptr;
+  d.lamOut = h->lam(i);
+  char *sl = h->slot(it.slot);
+  d.X = (double2 *)(sl + L.x_off);
+  d.J = (double2 *)(sl + L.j_off);
+  if (d.qr) {  // M and Q1's reflectors in the X buffer; the Jacobi on R2^H in J's
+    d.Qm = d.X;
+    d.ldq = pad_to(d.m, 4);
+    d.X = d.J;
+    d.J = nullptr;
+    d.U = (double2 *)(sl + L.u_off);
+    d.ldu = pad_to(d.m, 4);
+    d.Tq = (double2 *)(sl + L.tq_off);
+  }
+  d.T = sl + L.t_off;
+  d.V = (double2 *)(sl + L.v_off);
+  d.pairFlag = (int *)(sl + L.pf_off);
+  d.blkVer = o->pair_skip ? (int *)(sl + L.ver_off) : nullptr;
+  d.pairSeen = o->pair_skip ? (int2 *)(sl + L.seen_off) : nullptr;
+  d.sig2 = (double *)(sl + L.sig_off);
+  d.perm = (int *)(sl + L.perm_off);
+  d.sc = (SlotScalars *)(sl + L.sc_off);
+  for (int e = 0; e < 16; e++) d.g[e] = it.p->g[e];
+  d.gpStride = L.npairs_max;
+  d.dimsDev = h->dims_dev();
+  d.ctr = o->prof ? o->at<unsigned long long>(o->L.ctr_off) : nullptr;
+  return d;
+}
+
+// Copy descriptors into the owner's descriptor array.  Waits for the stream
+// first: the pinned staging buffer may still feed an earlier copy.
+tnsim_status put_descs(tnsim_mps o, const GateDesc *D, int n) {
+  HIPCHK(o, hipStreamSynchronize(o->stream));
+  prof_drain(o);
+  memcpy(o->pin, D, sizeof(GateDesc) * n);
+  HIPCHK(o, hipMemcpyAsync(o->at<GateDesc>(o->L.desc_off), o->pin, sizeof(GateDesc) * n,
+                           hipMemcpyHostToDevice, o->stream));
+  return TNSIM_OK;
+}
+
+// Everything before the Jacobi sweeps: merge, gate and weight, QR
+// preconditioning, column norms, the per-gate scalars.
+tnsim_status gates_prepare(tnsim_mps o, const GateDesc *D, int ng) {
+  tnsim_mps h = o;
+  int maxM = 0, maxColsPad = 0, maxChiR = 0, qrN = 0, qrMr = 0;
+  double theta_flop = 0.0, theta_byte = 0.0, colnorm_byte = 0.0, qr_flop = 0.0;
   for (int g = 0; g < ng; g++) {
-    GateDesc &d = D[g];
-    memset(&d, 0, sizeof d);
-    const tnsim_mps h = items[g].h;
-    const Layout &L = h->L;
-    const int i = items[g].p->i;
-    d.i = i;
-    d.chiL = h->dims[i];
-    d.chiM = h->dims[i + 1];
-    d.chiR = h->dims[i + 2];
-    d.m = 2 * d.chiL;
-    d.n = 2 * d.chiR;
-    // X = M^H (with the left vectors accumulated in J) when M is wide, or
-    // always when the caller needs the full left basis (the adjoint)
-    d.trans = force_trans || d.n > d.m;
-    // QR-preconditioned SVD for square or tall M that fits one panel workgroup
-    d.qr = h->cfg.svd_precondition && !d.trans && d.m <= QR_MAX_ROWS;
-    d.rows = d.qr ? d.n : (d.trans ? d.n : d.m);
-    d.cols = d.trans ? d.m : d.n;
-    d.ldx = pad_to(d.rows, 4);
-    d.ldj = pad_to(d.m, 4);
-    d.colsPad = pad_to(d.cols, PW);
-    d.nblk = d.colsPad / BW;
-    d.chiMax = h->cfg.chi_max;
-    d.storage = h->cfg.storage;
-    d.tfp32 = c.precision != TNSIM_FP64;
-    d.innerSweeps = o->inner_sweeps;
-    d.tol = h->cfg.jacobi_tol > 0 ? h->cfg.jacobi_tol : std::max(d.rows, 16) * 0x1p-53;
-    d.cutoff = h->cfg.cutoff;
-    d.A0 = h->site(i);
-    d.A1 = h->site(i + 1);
-    d.lamR = (i + 1 <= L.n - 2) ? h->lam(i + 1) : nullptr;
-    d.lamOut = h->lam(i);
-    char *sl = h->slot(items[g].slot);
-    d.X = (double2 *)(sl + L.x_off);
-    d.J = (double2 *)(sl + L.j_off);
-    if (d.qr) {  // M and Q1's reflectors in the X buffer; the Jacobi on R2^H in J's
-      d.Qm = d.X;
-      d.ldq = pad_to(d.m, 4);
-      d.X = d.J;
-      d.J = nullptr;
-      d.U = (double2 *)(sl + L.u_off);
-      d.ldu = pad_to(d.m, 4);
-      d.Tq = (double2 *)(sl + L.tq_off);
-    }
-    d.T = sl + L.t_off;
-    d.V = (double2 *)(sl + L.v_off);
-    d.pairFlag = (int *)(sl + L.pf_off);
-    d.blkVer = o->pair_skip ? (int *)(sl + L.ver_off) : nullptr;
-    d.pairSeen = o->pair_skip ? (int2 *)(sl + L.seen_off) : nullptr;
-    d.sig2 = (double *)(sl + L.sig_off);
-    d.perm = (int *)(sl + L.perm_off);
-    d.sc = (SlotScalars *)(sl + L.sc_off);
-    for (int e = 0; e < 16; e++) d.g[e] = items[g].p->g[e];
-    d.gpStride = L.npairs_max;
-    d.dimsDev = h->dims_dev();
+    const GateDesc &d = D[g];
     maxM = std::max(maxM, d.m);
-    maxN = std::max(maxN, d.n);
     maxColsPad = std::max(maxColsPad, d.colsPad);
     maxChiR = std::max(maxChiR, d.chiR);
-  }
-  unsigned long long *ctr = o->prof ? o->at<unsigned long long>(o->L.ctr_off) : nullptr;
-  double theta_flop = 0.0, theta_byte = 0.0, colnorm_byte = 0.0;
-  for (int g = 0; g < ng; g++) {
-    D[g].ctr = ctr;
-    const GateDesc &d = D[g];
     const double eb = d.storage == 0 ? 16.0 : 8.0, tb = d.tfp32 ? 8.0 : 16.0;
     theta_flop += 8.0 * d.m * d.chiM * d.n + 32.0 * d.m * d.n;
     theta_byte += eb * ((double)d.m * d.chiM + (double)d.chiM * d.n) + (tb + 16.0) * d.m * d.n;
     colnorm_byte += 16.0 * d.rows * d.cols;
+    if (d.qr) {
+      const double mm = d.m, nn = d.n;
+      qrN = std::max(qrN, d.n);
+      qrMr = std::max(qrMr, d.m);
+      qr_flop += 8.0 * (mm * nn * nn - nn * nn * nn / 3.0) + 16.0 * nn * nn * nn / 3.0;
+    }
   }
-
-  tnsim_mps h = o;  // launches, errors and profiling belong to the owner
+  tnsim_status s = put_descs(o, D, ng);
+  if (s != TNSIM_OK) return s;
   GateDesc *ddev = o->at<GateDesc>(o->L.desc_off);
-  SlotScalars *scg = o->at<SlotScalars>(o->L.scg_off);
-  HIPCHK(h, hipStreamSynchronize(h->stream));  // the staging buffer is free
-  prof_drain(h);
-  memcpy(h->pin, D.data(), sizeof(GateDesc) * ng);
-  HIPCHK(h, hipMemcpyAsync(ddev, h->pin, sizeof(GateDesc) * ng, hipMemcpyHostToDevice,
-                           h->stream));
-  hipStream_t st = h->stream;
+  hipStream_t st = o->stream;
   {
     ProfScope p(h, TNSIM_K_OTHER);
     launch_setup_slots(st, ddev, ng, maxColsPad, 0);
   }
   {
     ProfScope p(h, TNSIM_K_THETA, theta_flop, theta_byte);
-    launch_theta(st, ddev, ng, c.precision, maxM, maxChiR);
+    launch_theta(st, ddev, ng, o->cfg.precision, maxM, maxChiR);
   }
   // QR preconditioning of the gates that take it: M = Q1 R1 (stage 0),
-  // R1^H = Q2 R2 (stage 1), then the Jacobi matrix X = R2^H.
-  int qrN = 0, qrMr = 0;
-  double qr_flop = 0.0;
-  for (int g = 0; g < ng; g++)
-    if (D[g].qr) {
-      const double mm = D[g].m, nn = D[g].n;
-      qrN = std::max(qrN, D[g].n);
-      qrMr = std::max(qrMr, D[g].m);
-      qr_flop += 8.0 * (mm * nn * nn - nn * nn * nn / 3.0) + 16.0 * nn * nn * nn / 3.0;
-    }
-  // Panels are factored one group of QG columns at a time (each panel's
-  // reflectors applied inside the group), then the group's reflectors update
-  // the rest of the matrix in one pass.
+  // R1^H = Q2 R2 (stage 1), then the Jacobi matrix X = R2^H.  Panels are
+  // factored one group of QG columns at a time (each panel's reflectors
+  // applied inside the group), then the group's reflectors update the rest
+  // of the matrix in one pass.
   const int qrGroups = (qrN + QG - 1) / QG;
   if (qrN > 0) {
     ProfScope p(h, TNSIM_K_QR, qr_flop, 0.0);
@@ -506,31 +508,27 @@ tnsim_status run_2q_items(tnsim_mps o, const BatchItem *items, int ng, bool forc
     launch_gate_init(st, ddev, ng);
   }
   LAUNCHCHK(h, "theta");
+  return TNSIM_OK;
+}
 
-  const int max_sweeps = c.jacobi_max_sweeps > 0 ? c.jacobi_max_sweeps : 60;
-  SlotScalars *sc_pin = pin_scalars(o);
-  bool converged = false;
-  int sweeps = 0;
-  std::vector<int> done_at(ng, 0);
-
-  // Launch plan of the sweeps: only the gates still sweeping are launched
-  // (their descriptors packed at the front of the descriptor array), and the
-  // row dimension of the pair Grams (K-split) and of the rotations is cut
-  // finer when those gates alone cannot fill the GPU.
+// Jacobi sweeps over a changing set of gates.  A plan covers only the gates
+// still sweeping (their descriptors packed at the front of the descriptor
+// array); the row dimension of the pair Grams (K-split) and of the rotations
+// is cut finer when those gates alone cannot fill the GPU.
+struct SweepRunner {
+  tnsim_mps o;
   struct Plan {
     int na = 0, maxPairs = 0, maxNblk = 0, maxRows = 0, maxMtrans = 0, ksplit = 1, rotRows = 256;
   } P;
-  std::vector<int> act(ng);
-  for (int g = 0; g < ng; g++) act[g] = g;
-  auto make_plan = [&]() -> tnsim_status {
+
+  tnsim_status plan(const std::vector<const GateDesc *> &D, const std::vector<tnsim_mps> &hs) {
     P = Plan{};
-    P.na = (int)act.size();
-    for (int g : act) {
-      const GateDesc &d = D[g];
-      P.maxPairs = std::max(P.maxPairs, d.nblk / 2);
-      P.maxNblk = std::max(P.maxNblk, d.nblk);
-      P.maxRows = std::max(P.maxRows, d.rows);
-      if (d.trans) P.maxMtrans = std::max(P.maxMtrans, d.m);
+    P.na = (int)D.size();
+    for (const GateDesc *d : D) {
+      P.maxPairs = std::max(P.maxPairs, d->nblk / 2);
+      P.maxNblk = std::max(P.maxNblk, d->nblk);
+      P.maxRows = std::max(P.maxRows, d->rows);
+      if (d->trans) P.maxMtrans = std::max(P.maxMtrans, d->m);
     }
     const int pairs = P.na * P.maxPairs;
     int ks = (o->gram_wg_target + pairs - 1) / pairs;
@@ -538,12 +536,12 @@ tnsim_status run_2q_items(tnsim_mps o, const BatchItem *items, int ng, bool forc
     ks = std::min(ks, std::max(1, (P.maxRows + 31) / 32));
     // each gate's partials go to its handle's pool, at its position among the
     // active gates of that handle
-    std::vector<int> pos(act.size());
-    for (size_t a = 0; a < act.size(); a++) {
+    std::vector<int> pos(D.size());
+    for (size_t a = 0; a < D.size(); a++) {
       int p = 0;
-      for (size_t b = 0; b < a; b++) p += items[act[b]].h == items[act[a]].h;
+      for (size_t b = 0; b < a; b++) p += hs[b] == hs[a];
       pos[a] = p;
-      const Layout &L = items[act[a]].h->L;
+      const Layout &L = hs[a]->L;
       ks = std::min(ks, std::max(1, L.gp_blocks / ((p + 1) * L.npairs_max)));
     }
     P.ksplit = std::max(ks, 1);
@@ -555,23 +553,22 @@ tnsim_status run_2q_items(tnsim_mps o, const BatchItem *items, int ng, bool forc
       while (P.rotRows > 64 && (long long)pairs * ((rchunks + P.rotRows - 1) / P.rotRows) < 1024)
         P.rotRows /= 2;
     }
-    GateDesc *stage = reinterpret_cast<GateDesc *>(o->pin);
-    for (size_t a = 0; a < act.size(); a++) {
-      const tnsim_mps hg = items[act[a]].h;
-      stage[a] = D[act[a]];
-      stage[a].Gp = hg->at<double2>(hg->L.gp_off) +
-                    (size_t)pos[a] * P.ksplit * hg->L.npairs_max * PW * PW;
+    std::vector<GateDesc> stage(D.size());
+    for (size_t a = 0; a < D.size(); a++) {
+      stage[a] = *D[a];
+      stage[a].Gp = hs[a]->at<double2>(hs[a]->L.gp_off) +
+                    (size_t)pos[a] * P.ksplit * hs[a]->L.npairs_max * PW * PW;
       stage[a].rotRows = P.rotRows;
     }
-    HIPCHK(o, hipMemcpyAsync(ddev, o->pin, sizeof(GateDesc) * P.na, hipMemcpyHostToDevice, st));
-    return TNSIM_OK;
-  };
+    return put_descs(o, stage.data(), P.na);
+  }
 
-  // One sweep: every round of the round-robin tournament, then the scalars
-  // gathered for the host's convergence test.  With a non-default stream and
-  // profiling off, the sweep is captured once per plan as a HIP graph and
-  // replayed.
-  auto enqueue_sweep = [&]() {
+  // Every round of the round-robin tournament, then the scalars gathered for
+  // the host's convergence test.
+  void enqueue() {
+    tnsim_mps h = o;
+    hipStream_t st = o->stream;
+    GateDesc *ddev = o->at<GateDesc>(o->L.desc_off);
     {
       ProfScope p(h, TNSIM_K_OTHER);
       launch_begin_sweep(st, ddev, P.na);
@@ -590,10 +587,14 @@ tnsim_status run_2q_items(tnsim_mps o, const BatchItem *items, int ng, bool forc
         launch_rot(st, ddev, P.na, r, P.maxPairs, P.maxRows, P.maxMtrans, P.rotRows);
       }
     }
-    launch_gather_sc(st, ddev, P.na, scg);
-  };
-  const bool use_graph = h->graphs && !h->prof && st != nullptr;
-  auto prepare_graph = [&]() -> tnsim_status {
+    launch_gather_sc(st, ddev, P.na, o->at<SlotScalars>(o->L.scg_off));
+  }
+
+  // With a non-default stream and profiling off, the sweep of a plan shape
+  // is captured once as a HIP graph and replayed.
+  tnsim_status graph() {
+    tnsim_mps h = o;
+    hipStream_t st = o->stream;
     const long long key[7] = {P.na, P.maxPairs, P.ksplit, P.maxNblk, P.maxRows, P.maxMtrans,
                               P.rotRows};
     if (h->sweep_exec && memcmp(key, h->sweep_key, sizeof key) == 0) return TNSIM_OK;
@@ -601,78 +602,75 @@ tnsim_status run_2q_items(tnsim_mps o, const BatchItem *items, int ng, bool forc
       hipGraphExecDestroy(h->sweep_exec);
       h->sweep_exec = nullptr;
     }
-    hipGraph_t graph = nullptr;
+    hipGraph_t g = nullptr;
     HIPCHK(h, hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
-    enqueue_sweep();
+    enqueue();
     hipError_t e1 = hipGetLastError();
-    hipError_t e2 = hipStreamEndCapture(st, &graph);
+    hipError_t e2 = hipStreamEndCapture(st, &g);
     if (e1 != hipSuccess) return fail(h, e1, "sweep capture");
     if (e2 != hipSuccess) return fail(h, e2, "hipStreamEndCapture");
-    hipError_t e3 = hipGraphInstantiate(&h->sweep_exec, graph, nullptr, nullptr, 0);
-    hipGraphDestroy(graph);
+    hipError_t e3 = hipGraphInstantiate(&h->sweep_exec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
     if (e3 != hipSuccess) {
       h->sweep_exec = nullptr;
       return fail(h, e3, "hipGraphInstantiate");
     }
     memcpy(h->sweep_key, key, sizeof key);
     return TNSIM_OK;
-  };
+  }
 
-  tnsim_status ps = make_plan();
-  if (ps != TNSIM_OK) return ps;
-  for (int sweep = 1; sweep <= max_sweeps; sweep++) {
-    if (use_graph) {
-      tnsim_status gs = prepare_graph();
+  // One sweep of the current plan; rot[a] = some pair of planned gate a rotated.
+  tnsim_status run(std::vector<char> &rot) {
+    tnsim_mps h = o;
+    hipStream_t st = o->stream;
+    if (h->graphs && !h->prof && st != nullptr) {
+      tnsim_status gs = graph();
       if (gs != TNSIM_OK) return gs;
       HIPCHK(h, hipGraphLaunch(h->sweep_exec, st));
     } else {
-      enqueue_sweep();
+      enqueue();
     }
     LAUNCHCHK(h, "jacobi round");
-    HIPCHK(h, hipMemcpyAsync(sc_pin, scg, sizeof(SlotScalars) * P.na, hipMemcpyDeviceToHost, st));
+    SlotScalars *sc_pin = pin_scalars(o);
+    HIPCHK(h, hipMemcpyAsync(sc_pin, o->at<SlotScalars>(o->L.scg_off),
+                             sizeof(SlotScalars) * P.na, hipMemcpyDeviceToHost, st));
     HIPCHK(h, hipStreamSynchronize(st));
     prof_drain(h);
-    sweeps = sweep;
-    std::vector<int> still;
-    for (int a = 0; a < P.na; a++) {
-      if (sc_pin[a].rot)
-        still.push_back(act[a]);
-      else if (!done_at[act[a]])
-        done_at[act[a]] = sweep;
-    }
-    if (still.empty()) {
-      converged = true;
-      break;
-    }
-    // re-plan once the active set has shrunk by a quarter (a converged gate
-    // left in the plan only costs early-exiting workgroups)
-    if (4 * (int)still.size() <= 3 * P.na) {
-      act.swap(still);
-      ps = make_plan();
-      if (ps != TNSIM_OK) return ps;
-    }
+    rot.assign(P.na, 0);
+    for (int a = 0; a < P.na; a++) rot[a] = sc_pin[a].rot != 0;
+    return TNSIM_OK;
   }
-  // the descriptors of the whole batch again, for the truncation and write-back
-  // (the staging buffer is free once the stream is idle)
-  HIPCHK(h, hipStreamSynchronize(st));
-  memcpy(h->pin, D.data(), sizeof(GateDesc) * ng);
-  HIPCHK(h, hipMemcpyAsync(ddev, h->pin, sizeof(GateDesc) * ng, hipMemcpyHostToDevice, st));
-  std::vector<size_t> rec_at(ng);
+};
+
+// Record a finished (or failed) gate in its handle's statistics.
+void record_gate(const BatchItem &it, const GateDesc &d, int k, int sweeps) {
+  tnsim_mps hg = it.h;
+  hg->last_sweeps = std::max(hg->last_sweeps, sweeps);
+  hg->last_batch.insert(hg->last_batch.end(), {d.i, d.chiL, d.chiM, d.chiR, k, sweeps});
+  hg->sw_gates += 1;
+  hg->sw_sum += sweeps;
+  hg->sw_max = std::max(hg->sw_max, sweeps);
+}
+
+// Everything after convergence: norms, sort and truncation, U_k, the
+// write-back; updates each handle's bond dimensions and statistics.
+tnsim_status gates_finish(tnsim_mps o, const BatchItem *items, const GateDesc *D,
+                          const int *sweeps, int ng) {
+  tnsim_mps h = o;
+  hipStream_t st = o->stream;
+  int maxM = 0, maxN = 0, maxColsPad = 0, qrN = 0;
+  double colnorm_byte = 0.0;
   for (int g = 0; g < ng; g++) {
-    tnsim_mps hg = items[g].h;
-    int sw = done_at[g] ? done_at[g] : sweeps;
-    hg->last_sweeps = std::max(hg->last_sweeps, sweeps);
-    rec_at[g] = hg->last_batch.size();
-    hg->last_batch.insert(hg->last_batch.end(),
-                          {D[g].i, D[g].chiL, D[g].chiM, D[g].chiR, 0, sw});
-    hg->sw_gates += 1;
-    hg->sw_sum += sw;
-    hg->sw_max = std::max(hg->sw_max, sw);
+    maxM = std::max(maxM, D[g].m);
+    maxN = std::max(maxN, D[g].n);
+    maxColsPad = std::max(maxColsPad, D[g].colsPad);
+    colnorm_byte += 16.0 * D[g].rows * D[g].cols;
+    if (D[g].qr) qrN = std::max(qrN, D[g].n);
   }
-  if (!converged) {
-    h->err = "Jacobi SVD did not converge within jacobi_max_sweeps";
-    return TNSIM_E_NOCONV;
-  }
+  tnsim_status s = put_descs(o, D, ng);
+  if (s != TNSIM_OK) return s;
+  GateDesc *ddev = o->at<GateDesc>(o->L.desc_off);
+  SlotScalars *scg = o->at<SlotScalars>(o->L.scg_off);
   {
     ProfScope p(h, TNSIM_K_COLNORM, 0.0, colnorm_byte);
     launch_colnorm(st, ddev, ng, maxColsPad);
@@ -683,16 +681,17 @@ tnsim_status run_2q_items(tnsim_mps o, const BatchItem *items, int ng, bool forc
   }
   launch_gather_sc(st, ddev, ng, scg);
   LAUNCHCHK(h, "truncate");
+  SlotScalars *sc_pin = pin_scalars(o);
   HIPCHK(h, hipMemcpyAsync(sc_pin, scg, sizeof(SlotScalars) * ng, hipMemcpyDeviceToHost, st));
   HIPCHK(h, hipStreamSynchronize(st));
   prof_drain(h);
-  int maxK = 0;
-  double wbl_byte = 0.0, wbr_flop = 0.0, wbr_byte = 0.0;
+  int maxK = 0, qrK = 0, qrM = 0;
+  double wbl_byte = 0.0, wbr_flop = 0.0, wbr_byte = 0.0, qa_flop = 0.0;
   for (int g = 0; g < ng; g++) {
     const SlotScalars &sv = sc_pin[g];
     const GateDesc &d = D[g];
     tnsim_mps hg = items[g].h;
-    hg->last_batch[rec_at[g] + 4] = sv.k;
+    record_gate(items[g], d, sv.k, sweeps[g]);
     hg->dims[d.i + 1] = sv.k;
     hg->sum_eps += sv.eps;
     hg->prod_keep *= (1.0 - sv.eps);
@@ -702,21 +701,18 @@ tnsim_status run_2q_items(tnsim_mps o, const BatchItem *items, int ng, bool forc
     wbl_byte += (16.0 + eb) * d.m * sv.k;
     wbr_flop += 8.0 * sv.k * d.m * d.n;
     wbr_byte += 16.0 * d.m * sv.k + tb * (double)d.m * d.n + eb * (double)sv.k * d.n;
-  }
-  // U_k = Q1 [W_k; 0] for the QR-preconditioned gates: the panels' reflectors
-  // in reverse order
-  int qrK = 0, qrM = 0;
-  double qa_flop = 0.0;
-  for (int g = 0; g < ng; g++)
-    if (D[g].qr) {
-      qrK = std::max(qrK, sc_pin[g].k);
-      qrM = std::max(qrM, D[g].m);
-      qa_flop += 8.0 * (2.0 * D[g].m * D[g].n - (double)D[g].n * D[g].n) * sc_pin[g].k;
+    if (d.qr) {
+      qrK = std::max(qrK, sv.k);
+      qrM = std::max(qrM, d.m);
+      qa_flop += 8.0 * (2.0 * d.m * d.n - (double)d.n * d.n) * sv.k;
     }
+  }
+  // U_k = Q1 [W_k; 0] for the QR-preconditioned gates: the groups'
+  // reflectors in reverse order
   if (qrK > 0) {
     ProfScope p(h, TNSIM_K_QR, qa_flop, 0.0);
     launch_qr_gather(st, ddev, ng, qrM, qrK);
-    for (int grp = qrGroups - 1; grp >= 0; grp--)
+    for (int grp = (qrN + QG - 1) / QG - 1; grp >= 0; grp--)
       launch_qr_update_group(st, ddev, ng, 0, grp, 1, qrK, qrM);
     LAUNCHCHK(h, "qr apply");
   }
@@ -726,10 +722,70 @@ tnsim_status run_2q_items(tnsim_mps o, const BatchItem *items, int ng, bool forc
   }
   {
     ProfScope p(h, TNSIM_K_WB_RIGHT, wbr_flop, wbr_byte);
-    launch_wb_right(st, ddev, ng, c.precision, maxK, maxN);
+    launch_wb_right(st, ddev, ng, o->cfg.precision, maxK, maxN);
   }
   LAUNCHCHK(h, "write-back");
   return TNSIM_OK;
+}
+
+// Run a batch of two-qubit gates (possibly of several handles) through the
+// whole path in the same launches.  `o` owns the descriptors, the stream and
+// the profiling; every gate works in its own handle's state and slot.
+tnsim_status run_2q_items(tnsim_mps o, const BatchItem *items, int ng, bool force_trans) {
+  std::vector<GateDesc> D(ng);
+  for (int g = 0; g < ng; g++) D[g] = make_desc(o, items[g], force_trans);
+  tnsim_status s = gates_prepare(o, D.data(), ng);
+  if (s != TNSIM_OK) return s;
+
+  const int max_sweeps = o->cfg.jacobi_max_sweeps > 0 ? o->cfg.jacobi_max_sweeps : 60;
+  std::vector<int> done_at(ng, 0), act(ng);
+  for (int g = 0; g < ng; g++) act[g] = g;
+  SweepRunner sw{o};
+  auto replan = [&]() {
+    std::vector<const GateDesc *> pd;
+    std::vector<tnsim_mps> hs;
+    for (int g : act) {
+      pd.push_back(&D[g]);
+      hs.push_back(items[g].h);
+    }
+    return sw.plan(pd, hs);
+  };
+  s = replan();
+  if (s != TNSIM_OK) return s;
+  bool converged = false;
+  int sweeps = 0;
+  std::vector<char> rot;
+  for (int sweep = 1; sweep <= max_sweeps; sweep++) {
+    s = sw.run(rot);
+    if (s != TNSIM_OK) return s;
+    sweeps = sweep;
+    std::vector<int> still;
+    for (int a = 0; a < sw.P.na; a++) {
+      if (rot[a])
+        still.push_back(act[a]);
+      else if (!done_at[act[a]])
+        done_at[act[a]] = sweep;
+    }
+    if (still.empty()) {
+      converged = true;
+      break;
+    }
+    // re-plan once the active set has shrunk by a quarter (a converged gate
+    // left in the plan only costs early-exiting workgroups)
+    if (4 * (int)still.size() <= 3 * sw.P.na) {
+      act.swap(still);
+      s = replan();
+      if (s != TNSIM_OK) return s;
+    }
+  }
+  std::vector<int> swp(ng);
+  for (int g = 0; g < ng; g++) swp[g] = done_at[g] ? done_at[g] : sweeps;
+  if (!converged) {
+    for (int g = 0; g < ng; g++) record_gate(items[g], D[g], 0, swp[g]);
+    o->err = "Jacobi SVD did not converge within jacobi_max_sweeps";
+    return TNSIM_E_NOCONV;
+  }
+  return gates_finish(o, items, D.data(), swp.data(), ng);
 }
 
 
@@ -817,6 +873,163 @@ tnsim_status validate_layer(tnsim_mps h, const tnsim_gate *gates, int ng,
       Pending p;
       orient(gates[k].q0, gates[k].q1, gates[k].m, p);
       g2.push_back(p);
+    }
+  }
+  return TNSIM_OK;
+}
+
+// Dependency-driven execution of a circuit of local gates on one handle.
+// A gate depends on the previous gate on each of its sites (a two-qubit gate
+// on (i, i+1) also reads lambda_{i+1} and the bond dimensions around it, but
+// every gate that writes those shares a site with it), so the results equal
+// those of applying the gates in order.  Two-qubit gates whose predecessors
+// are done are admitted into free workspace slots and prepared together; all
+// gates in flight share each Jacobi sweep; a gate that converges is truncated
+// and written back at once, which releases its successors.  Gates of
+// consecutive layers thus overlap: the next layer's gates fill the sweeps in
+// which the last gates of a layer converge.
+constexpr int kAdmitGroup = 16;
+
+tnsim_status run_circuit(tnsim_mps h, const tnsim_gate *gates, int ng) {
+  struct Op {
+    int kind = 0;  // 1 or 2 qubits
+    int q = 0;     // site (1q)
+    Pending p{};   // oriented gate (2q)
+    const tnsim_c128 *m = nullptr;
+    int npred = 0;
+    std::vector<int> succ;
+  };
+  const int n = h->L.n;
+  std::vector<Op> ops(ng);
+  std::vector<int> last(n, -1);
+  for (int k = 0; k < ng; k++) {
+    Op &op = ops[k];
+    int sites[2], ns = 1;
+    if (gates[k].q1 < 0) {
+      op.kind = 1;
+      op.q = gates[k].q0;
+      op.m = gates[k].m;
+      sites[0] = op.q;
+    } else {
+      op.kind = 2;
+      orient(gates[k].q0, gates[k].q1, gates[k].m, op.p);
+      sites[0] = op.p.i;
+      sites[1] = op.p.i + 1;
+      ns = 2;
+    }
+    int prev[2] = {-1, -1};
+    for (int e = 0; e < ns; e++) {
+      const int j = last[sites[e]];
+      if (j >= 0 && j != prev[0]) {
+        ops[j].succ.push_back(k);
+        op.npred++;
+        prev[e] = j;
+      }
+      last[sites[e]] = k;
+    }
+  }
+  std::vector<int> ready1, ready2;  // kept in circuit order
+  for (int k = 0; k < ng; k++)
+    if (ops[k].npred == 0) (ops[k].kind == 1 ? ready1 : ready2).push_back(k);
+  auto release = [&](int k) {
+    for (int j : ops[k].succ)
+      if (--ops[j].npred == 0) {
+        auto &r = ops[j].kind == 1 ? ready1 : ready2;
+        r.insert(std::upper_bound(r.begin(), r.end(), j), j);
+      }
+  };
+
+  struct Flight {
+    BatchItem it;
+    GateDesc d;
+    int op, sweeps;
+  };
+  std::vector<Flight> fl;
+  std::vector<int> free_slots;
+  for (int sl = h->L.nslots - 1; sl >= 0; sl--) free_slots.push_back(sl);
+  const int max_sweeps = h->cfg.jacobi_max_sweeps > 0 ? h->cfg.jacobi_max_sweeps : 60;
+  SweepRunner sw{h};
+  bool dirty = true;
+  std::vector<char> rot;
+  for (;;) {
+    // one-qubit gates: all ready ones at once (they are on distinct sites)
+    while (!ready1.empty()) {
+      std::vector<std::pair<int, const tnsim_c128 *>> g1;
+      std::vector<int> done = ready1;
+      ready1.clear();
+      for (int k : done) g1.push_back({ops[k].q, ops[k].m});
+      tnsim_status s = run_1q(h, g1);
+      if (s != TNSIM_OK) return s;
+      for (int k : done) release(k);
+    }
+    // two-qubit gates into free slots, in groups: a preparation (merge and
+    // QR) costs about the same latency for one gate as for many, so ready
+    // gates wait until there are enough of them or the GPU runs short of work
+    std::vector<GateDesc> nd;
+    std::vector<BatchItem> ni;
+    size_t taken = 0;
+    const bool admit = (int)ready2.size() >= kAdmitGroup || (int)fl.size() < kAdmitGroup;
+    for (; admit && taken < ready2.size() && !free_slots.empty(); taken++) {
+      const int k = ready2[taken];
+      BatchItem it{h, free_slots.back(), &ops[k].p};
+      free_slots.pop_back();
+      ni.push_back(it);
+      nd.push_back(make_desc(h, it, false));
+      fl.push_back(Flight{it, nd.back(), k, 0});
+    }
+    ready2.erase(ready2.begin(), ready2.begin() + taken);
+    if (!nd.empty()) {
+      tnsim_status s = gates_prepare(h, nd.data(), (int)nd.size());
+      if (s != TNSIM_OK) return s;
+      dirty = true;
+    }
+    if (fl.empty()) {
+      if (ready1.empty() && ready2.empty()) break;
+      continue;
+    }
+    // one Jacobi sweep over every gate in flight
+    if (dirty) {
+      std::vector<const GateDesc *> pd;
+      std::vector<tnsim_mps> hs;
+      for (const Flight &f : fl) {
+        pd.push_back(&f.d);
+        hs.push_back(h);
+      }
+      tnsim_status s = sw.plan(pd, hs);
+      if (s != TNSIM_OK) return s;
+      dirty = false;
+    }
+    tnsim_status s = sw.run(rot);
+    if (s != TNSIM_OK) return s;
+    std::vector<Flight> keep, fin;
+    for (size_t a = 0; a < fl.size(); a++) {
+      fl[a].sweeps++;
+      if (!rot[a])
+        fin.push_back(fl[a]);
+      else if (fl[a].sweeps >= max_sweeps) {
+        record_gate(fl[a].it, fl[a].d, 0, fl[a].sweeps);
+        h->err = "Jacobi SVD did not converge within jacobi_max_sweeps";
+        return TNSIM_E_NOCONV;
+      } else
+        keep.push_back(fl[a]);
+    }
+    if (!fin.empty()) {
+      std::vector<BatchItem> fi;
+      std::vector<GateDesc> fd;
+      std::vector<int> fs;
+      for (const Flight &f : fin) {
+        fi.push_back(f.it);
+        fd.push_back(f.d);
+        fs.push_back(f.sweeps);
+      }
+      s = gates_finish(h, fi.data(), fd.data(), fs.data(), (int)fin.size());
+      if (s != TNSIM_OK) return s;
+      for (const Flight &f : fin) {
+        free_slots.push_back(f.it.slot);
+        release(f.op);
+      }
+      fl.swap(keep);
+      dirty = true;
     }
   }
   return TNSIM_OK;
@@ -1373,6 +1586,21 @@ tnsim_status tnsim_apply_layer(tnsim_mps h, const tnsim_gate *gates, int32_t n_g
   s = run_1q(h, g1);
   if (s != TNSIM_OK) return s;
   return run_2q(h, g2);
+}
+
+tnsim_status tnsim_apply_circuit(tnsim_mps h, const tnsim_gate *gates, int32_t n_gates) {
+  tnsim_status s = check_handle(h);
+  if (s != TNSIM_OK) return s;
+  const int n = h->L.n;
+  if (n_gates < 0 || (n_gates > 0 && !gates)) return TNSIM_E_ARG;
+  for (int k = 0; k < n_gates; k++) {
+    const int a = gates[k].q0, b = gates[k].q1;
+    if (a < 0 || a >= n || b < -1 || b >= n || a == b) return TNSIM_E_ARG;
+    if (b >= 0 && std::abs(a - b) != 1) return TNSIM_E_NONLOCAL;
+  }
+  h->last_sweeps = 0;
+  h->last_batch.clear();
+  return run_circuit(h, gates, n_gates);
 }
 
 tnsim_status tnsim_apply_layer_multi(tnsim_mps const *mps, const tnsim_gate *const *gates,

@@ -50,6 +50,7 @@ _SIGS = {
     "tnsim_apply_2q": (C.c_int, [_P, C.c_int32, C.c_int32, _P]),
     "tnsim_apply_layer": (C.c_int, [_P, _P, C.c_int32]),
     "tnsim_apply_layer_multi": (C.c_int, [_P, _P, _P, C.c_int32]),
+    "tnsim_apply_circuit": (C.c_int, [_P, _P, C.c_int32]),
     "tnsim_layerise": (C.c_int, [_P, C.c_int32, C.c_int32, _P, C.POINTER(C.c_int32)]),
     "tnsim_expect_pauli": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_double),
                                      C.POINTER(C.c_double)]),
@@ -231,6 +232,16 @@ class MPS:
     def run_layers(self, layers: Iterable[Sequence]) -> None:
         for layer in layers:
             self._chk(self.apply_layer(layer), "apply_layer")
+
+    def apply_circuit(self, gates: Sequence) -> int:
+        """A whole circuit in one call: gates start when the gates before them
+        on their qubits are done, two-qubit gates of different layers share
+        the Jacobi sweeps.  Returns the status."""
+        arr = pack_gates(gates)
+        return lib().tnsim_apply_circuit(self._h, arr.ctypes.data, len(gates))
+
+    def run_circuit(self, gates: Sequence) -> None:
+        self._chk(self.apply_circuit(list(gates)), "apply_circuit")
 
     def run_gates(self, gates: Iterable) -> None:
         """One gate per call (the per-gate path)."""

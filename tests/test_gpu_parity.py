@@ -323,3 +323,48 @@ def test_autotuned_launch_shapes_leave_results_unchanged(T):
         assert np.array_equal(a.site(q), b.site(q))
     for k in range(n - 1):
         assert np.array_equal(a.lam(k), b.lam(k))
+
+
+# ---------------------------------------------------------------- circuit scheduler
+
+@pytest.mark.parametrize("precision,storage,tol,ltol", [("fp64", "c128", 1e-10, 1e-10),
+                                                        ("bf16x6", "c64", 1e-9, 1e-6)])
+def test_circuit_scheduler_vs_oracle(T, precision, storage, tol, ltol):
+    """The whole circuit in one call (gates of consecutive layers overlap)
+    against the oracle applying it gate by gate: same bond dimensions and
+    spectra, fidelity at the path's tolerance."""
+    n, depth, chi = 18, 14, 40
+    layers = W.brickwork_haar(n, depth, 4321)
+    gates = [g for layer in layers for g in layer]
+    m = T.MPS(n, chi, 1e-10, precision=precision, storage=storage)
+    m.run_circuit(gates)
+    o = O.OracleMPS(n, chi, 1e-10)
+    o.run_layers(layers)
+    assert list(m.bond_dims()) == list(o.bond_dims())
+    for b in range(n - 1):
+        assert np.max(np.abs(m.lam(b) - o.lam(b))) < ltol
+    assert 1 - _oracle_fid(m, o) < tol
+    lb = m.last_batch()
+    assert len(lb) == sum(1 for g in gates if g[1] >= 0)
+
+
+def test_circuit_scheduler_mixed_gates_amplitudes(T):
+    """Interleaved one- and two-qubit gates on shared qubits, both
+    orientations, without truncation: amplitudes against brute force."""
+    rng = np.random.default_rng(99)
+    n = 9
+    gates = []
+    for _ in range(60):
+        if rng.random() < 0.35:
+            q = int(rng.integers(0, n))
+            gates.append((q, -1, W.rot("XYZ"[int(rng.integers(0, 3))], rng.uniform(0, 6.3))))
+        else:
+            j = int(rng.integers(0, n - 1))
+            g = W.haar_u4(rng)
+            gates.append((j, j + 1, g) if rng.random() < 0.5 else (j + 1, j, g))
+    m = T.MPS(n, 64)
+    m.run_circuit(gates)
+    assert np.max(np.abs(gpu_statevector(m) - statevector(n, gates))) < 1e-12
+    c = T.MPS(n, 64)
+    assert c.apply_circuit([(0, 2, W.cnot())]) == T.E_NONLOCAL
+    assert c.apply_circuit([(0, n, W.cnot())]) == T.E_ARG
