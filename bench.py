@@ -101,6 +101,8 @@ def parse():
     ap.add_argument("--precision", default="bf16x6", choices=["fp64", "f32acc", "bf16x3", "bf16x6"])
     ap.add_argument("--storage", default="c64", choices=["c128", "c64"])
     ap.add_argument("--chi", type=int, default=1024)
+    ap.add_argument("--jacobi-tol", type=float, default=0.0,
+                    help="relative Jacobi tolerance of the batched path (0: the library default)")
     ap.add_argument("--no-pergate", action="store_true")
     ap.add_argument("--circuit", action="store_true",
                     help="batched path: the timed layers as one dependency-scheduled "
@@ -342,7 +344,8 @@ def main():
     prep_s = time.perf_counter() - t0
 
     # --- batched mixed path from the snapshot
-    mix = T.MPS(n, chi, 1e-12, precision=args.precision, storage=args.storage)
+    mix = T.MPS(n, chi, 1e-12, precision=args.precision, storage=args.storage,
+                jacobi_tol=args.jacobi_tol)
     tuned = mix.autotune()
     log(f"autotuned rows per rotation workgroup by pair-count class: {tuned}")
     mix.copy_from(ref)

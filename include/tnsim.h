@@ -92,7 +92,8 @@ typedef struct {
   int32_t precision;         /* tnsim_precision */
   int32_t storage;           /* tnsim_storage */
   int32_t jacobi_max_sweeps; /* <= 0 selects 60 */
-  double jacobi_tol;         /* <= 0 selects max(rows, 16) * 2^-53 */
+  double jacobi_tol;         /* <= 0 selects max(rows, 16) * 2^-53 with complex128 sites,
+                                2^-30 with complex64 sites (64 times below their rounding) */
   int32_t max_layer_gates;   /* two-qubit gates processed together; <= 0 selects n/2 */
   /* 0: one-sided Jacobi on M.  1: QR preconditioning before the Jacobi
      (Drmac and Veselic, SIAM J. Matrix Anal. Appl. 29(4), 2008): M = Q1 R1,

@@ -399,7 +399,13 @@ GateDesc make_desc(tnsim_mps o, const BatchItem &it, bool force_trans) {
   d.storage = h->cfg.storage;
   d.tfp32 = o->cfg.precision != TNSIM_FP64;
   d.innerSweeps = o->inner_sweeps;
-  d.tol = h->cfg.jacobi_tol > 0 ? h->cfg.jacobi_tol : std::max(d.rows, 16) * 0x1p-53;
+  // default Jacobi tolerance: float64 level for complex128 sites; for
+  // complex64 sites 2^-30, a factor 64 below the rounding of the stored
+  // vectors (U_k is written in complex64, so orthogonality beyond that is lost)
+  d.tol = h->cfg.jacobi_tol > 0 ? h->cfg.jacobi_tol
+                                : (h->cfg.storage == TNSIM_STORE_C64
+                                       ? 0x1p-30
+                                       : std::max(d.rows, 16) * 0x1p-53);
   d.cutoff = h->cfg.cutoff;
   d.A0 = h->site(i);
   d.A1 = h->site(i + 1);

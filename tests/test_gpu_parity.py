@@ -368,3 +368,24 @@ def test_circuit_scheduler_mixed_gates_amplitudes(T):
     c = T.MPS(n, 64)
     assert c.apply_circuit([(0, 2, W.cnot())]) == T.E_NONLOCAL
     assert c.apply_circuit([(0, n, W.cnot())]) == T.E_ARG
+
+
+@pytest.mark.parametrize("precision,storage", [("fp64", "c128"), ("bf16x6", "c64")])
+def test_degenerate_sizes_vs_oracle(T, precision, storage):
+    """Smallest shapes: two qubits, and chi_max = 1 (every two-qubit gate
+    truncates to one Schmidt value), on the plain and the preconditioned SVD."""
+    tol = 1e-12 if storage == "c128" else 1e-6
+    rng = np.random.default_rng(17)
+    gates = [(0, 1, W.haar_u4(rng)), (1, 0, W.haar_u4(rng)), (0, -1, W.rot("Y", 0.7))]
+    m = T.MPS(2, 2, precision=precision, storage=storage)
+    m.run_gates(gates)
+    assert np.max(np.abs(gpu_statevector(m) - statevector(2, gates))) < tol
+    layers = W.brickwork_haar(8, 6, 23)
+    g = T.MPS(8, 1, 0.0, precision=precision, storage=storage)
+    g.run_layers(layers)
+    o = O.OracleMPS(8, 1, 0.0)
+    o.run_layers(layers)
+    assert list(g.bond_dims()) == [1] * 7
+    # complex64 sites carry about 6e-8 relative rounding into the weights
+    assert abs(g.stats()["sum_eps"] - o.stats()["sum_eps"]) < (1e-9 if storage == "c128" else 1e-6)
+    assert 1 - _oracle_fid(g, o) < (1e-10 if storage == "c128" else 1e-6)
