@@ -88,6 +88,37 @@ def roofline(prof):
             "launches": d["launches"], "avg_launch_ms": d["ms"] / launches}
 
 
+BF16_PEAK_TFLOPS = 2500.0
+FP32_PEAK_TFLOPS = 157.3
+
+
+def kernel_rates(prof, precision):
+    """Achieved algorithmic rates per kernel class over the timed region:
+    TFLOP/s against the peak of the unit the class runs on, and GB/s against
+    HBM.  The merge and the right-site write-back count their complex
+    products once (the split products on bf16 matrix cores are not counted)."""
+    unit = {"theta": precision, "wb_right": precision}
+    out = {}
+    for k, v in prof.items():
+        if not v["launches"] or v["ms"] <= 0:
+            continue
+        sec = v["ms"] * 1e-3
+        r = {"ms": round(v["ms"], 3)}
+        if v["flops"] > 0:
+            tf = v["flops"] / sec / 1e12
+            pk = FP64_PEAK_TFLOPS
+            if unit.get(k) in ("bf16x3", "bf16x6"):
+                pk = BF16_PEAK_TFLOPS
+            elif unit.get(k) == "f32acc":
+                pk = FP32_PEAK_TFLOPS
+            r.update({"tflops": round(tf, 2), "peak_tflops": pk, "frac": round(tf / pk, 3)})
+        if v["bytes"] > 0:
+            gb = v["bytes"] / sec / 1e9
+            r.update({"gbs": round(gb, 1), "hbm_frac": round(gb / HBM_PEAK_GBS, 3)})
+        out[k] = r
+    return out
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -453,6 +484,7 @@ def main():
         "prep_s": prep_s,
         "layer_s": [round(x, 3) for x in per_layer],
         "kernel_ms": {k: round(v["ms"], 3) for k, v in prof.items() if v["launches"]},
+        "kernel_rates": kernel_rates(prof, args.precision),
         "roofline": roof,
         "cpu_baseline": cpu,
     }
