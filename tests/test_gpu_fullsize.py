@@ -85,3 +85,27 @@ def test_full_size_layer_vs_oracle(T, chi, precision, storage, tol):
     po = _block(o.site(i), o.site(i + 1))
     assert np.linalg.norm(pg - po) / np.linalg.norm(po) < tol
     assert st["last_eps"] > 0
+
+
+def test_gate_beyond_qr_rows_vs_oracle(T):
+    """chi = 1100: M is 2200 x 2200, more rows than one QR panel workgroup
+    holds, so even the mixed path takes the plain Jacobi on M.  One gate
+    against the oracle (k, spectrum, two-site product)."""
+    chi, tol = 1100, 1e-5
+    dims, sites, lams = _state(chi, 77)
+    i = N_SITES // 2 - 1
+    assert dims[i] == dims[i + 1] == dims[i + 2] == chi
+    g = W.cnot() @ np.kron(W.rz(0.4) @ W.rx(1.2), W.rz(2.2) @ W.rx(0.3))
+    m = T.MPS(N_SITES, chi, 1e-12, precision="bf16x6", storage="c64")
+    m.import_state(sites, lams)
+    assert m.apply_2q(i, i + 1, g) == T.OK
+    O.set_threads(16)
+    o = O.OracleMPS(N_SITES, chi, 1e-12)
+    o.set_state(sites, lams)
+    assert o.apply_2q(i, i + 1, g) == O.OK
+    assert m.bond_dims()[i] == o.bond_dims()[i]
+    lam_g, lam_o = m.lam(i), o.lam(i)
+    assert np.max(np.abs(lam_g - lam_o)) / lam_o[0] < tol
+    pg = _block(m.site(i), m.site(i + 1))
+    po = _block(o.site(i), o.site(i + 1))
+    assert np.linalg.norm(pg - po) / np.linalg.norm(po) < tol
