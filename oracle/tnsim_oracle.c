@@ -488,21 +488,42 @@ static int apply_2q_local(om_mps *m, int i, const cplx *G) {
   return OM_OK;
 }
 
+static int apply_2q_adjacent(om_mps *m, int q0, int q1, const cplx *G) {
+  if (q1 == q0 + 1) return apply_2q_local(m, q0, G);
+  /* same gate with the two qubits listed in the other order: SWAP G SWAP */
+  cplx Gs[16];
+  for (int sp = 0; sp < 2; sp++)
+    for (int tp = 0; tp < 2; tp++)
+      for (int s = 0; s < 2; s++)
+        for (int t = 0; t < 2; t++)
+          Gs[(2 * sp + tp) * 4 + 2 * s + t] = G[(2 * tp + sp) * 4 + 2 * t + s];
+  return apply_2q_local(m, q1, Gs);
+}
+
+/* A gate on distant qubits (Sec. IV.A): SWAP gates bring the qubit with the
+   larger index next to the other one, the gate acts there, and the SWAPs are
+   undone in reverse order.  Every SWAP is an ordinary two-qubit gate, with
+   its own truncation. */
 int om_apply_2q(om_mps *m, int q0, int q1, const double *g_ri) {
   if (q0 < 0 || q0 >= m->n || q1 < 0 || q1 >= m->n || q0 == q1) return OM_E_ARG;
   const cplx *G = (const cplx *)g_ri;
-  if (q1 == q0 + 1) return apply_2q_local(m, q0, G);
-  if (q1 == q0 - 1) {
-    /* same gate with the two qubits listed in the other order: SWAP G SWAP */
-    cplx Gs[16];
-    for (int sp = 0; sp < 2; sp++)
-      for (int tp = 0; tp < 2; tp++)
-        for (int s = 0; s < 2; s++)
-          for (int t = 0; t < 2; t++)
-            Gs[(2 * sp + tp) * 4 + 2 * s + t] = G[(2 * tp + sp) * 4 + 2 * t + s];
-    return apply_2q_local(m, q1, Gs);
+  if (q1 == q0 + 1 || q1 == q0 - 1) return apply_2q_adjacent(m, q0, q1, G);
+  cplx S[16] = {0};
+  for (int s = 0; s < 2; s++)
+    for (int t = 0; t < 2; t++) S[(2 * t + s) * 4 + 2 * s + t] = 1.0;
+  const int a = q0 < q1 ? q0 : q1, b = q0 < q1 ? q1 : q0;
+  for (int j = b - 1; j > a; j--) {
+    int r = apply_2q_local(m, j, S);
+    if (r != OM_OK) return r;
   }
-  return OM_E_NONLOCAL;
+  /* the qubit from b now sits at a + 1 */
+  int r = q0 == a ? apply_2q_adjacent(m, a, a + 1, G) : apply_2q_adjacent(m, a + 1, a, G);
+  if (r != OM_OK) return r;
+  for (int j = a + 1; j < b; j++) {
+    r = apply_2q_local(m, j, S);
+    if (r != OM_OK) return r;
+  }
+  return OM_OK;
 }
 
 /* Gates of one layer: q1[g] = -1 marks a one-qubit gate (matrix in the first

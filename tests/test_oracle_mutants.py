@@ -39,6 +39,10 @@ MUTANTS = {
     "householder reflector factor": ("cplx f = 2.0 * d / vnorm2;", "cplx f = d / vnorm2;"),
     "M^H not conjugated": ("Y[(size_t)i * cols + j] = conj(M[(size_t)j * rows + i]);",
                            "Y[(size_t)i * cols + j] = M[(size_t)j * rows + i];"),
+    "swap chain not undone": ("for (int j = a + 1; j < b; j++) {", "for (int j = b; j < b; j++) {"),
+    "far qubit orientation lost": (
+        "q0 == a ? apply_2q_adjacent(m, a, a + 1, G) : apply_2q_adjacent(m, a + 1, a, G);",
+        "apply_2q_adjacent(m, a, a + 1, G);"),
 }
 
 PIN_CALLS = [
@@ -52,6 +56,8 @@ PIN_CALLS = [
     lambda: pins.test_jacobi_svd_against_numpy((64, 64)),
     pins.test_truncation_rule,
     pins.test_layer_order_independence,
+    pins.test_nonlocal_gates_match_statevector,
+    pins.test_nonlocal_ghz_closed_form,
 ]
 
 
