@@ -141,7 +141,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=16)
     ap.add_argument("--workload", default="chi1024",
-                    choices=["chi1024", "wide", "ansatz", "batch"],
+                    choices=["chi1024", "wide", "ansatz", "batch", "nonlocal"],
                     help="chi1024: the headline metric; the others measure the secondary "
                          "workloads (one JSON line each)")
     return ap.parse_args()
@@ -346,6 +346,56 @@ def bench_batch(args):
             "max_fidelity_err_vs_oracle": max(fids) if fids else None}
 
 
+def bench_nonlocal(args):
+    """Gates on distant qubits (SWAP chains): n=48, 400 gates, 60% two-qubit
+    gates (Haar U(4)) on random pairs up to 8 apart, chi_max=128, cutoff 1e-10.
+    The mixed path takes the whole circuit in one scheduled call; the float64
+    path one gate per call.  Rates count the circuit's two-qubit gates (not
+    the SWAPs they expand into)."""
+    import torch
+
+    from paper_2601_04422_amd import tnsim as T
+    from paper_2601_04422_amd import workloads as W
+
+    n, chi, count = 48, 128, 400
+    rng = np.random.default_rng(1006)
+    gates = []
+    for _ in range(count):
+        if rng.random() < 0.4:
+            q = int(rng.integers(0, n))
+            gates.append((q, -1, W.rot("XYZ"[int(rng.integers(0, 3))], rng.uniform(0, 2 * np.pi))))
+        else:
+            a = int(rng.integers(0, n))
+            d = int(rng.integers(1, 9)) * (1 if rng.random() < 0.5 else -1)
+            b = min(max(a + d, 0), n - 1)
+            if b == a:
+                b = a + 1 if a + 1 < n else a - 1
+            gates.append((a, b, W.haar_u4(rng)))
+    n2q = sum(1 for g in gates if g[1] >= 0)
+    swaps = sum(2 * (abs(g[0] - g[1]) - 1) for g in gates if g[1] >= 0)
+    m = T.MPS(n, chi, 1e-10, precision=args.precision, storage=args.storage)
+    ref = T.MPS(n, chi, 1e-10, precision="fp64", storage="c128")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m.run_circuit(gates)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    ref.run_gates(gates)
+    torch.cuda.synchronize()
+    dt_ref = time.perf_counter() - t1
+    fid = abs(m.overlap(ref)) ** 2 / (m.norm2() * ref.norm2())
+    return {"metric": "non-local 2q gates/s, n=48 random pairs up to 8 apart, chi_max=128",
+            "value": n2q / dt, "unit": "2q gates/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+            "ms_per_step": 1e3 * dt, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": f"{args.precision} contraction, f64 svd",
+            "data": "synthetic",
+            "config": {"workload": f"{count} gates, {n2q} two-qubit ({swaps} SWAPs added), "
+                                   f"cutoff 1e-10, {args.storage}"},
+            "fp64_per_gate_gates_per_s": n2q / dt_ref, "fidelity_err_vs_fp64": 1 - fid,
+            "max_bond": int(max(m.bond_dims()))}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -353,7 +403,8 @@ def main():
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
     if args.workload != "chi1024":
-        fn = {"wide": bench_wide, "ansatz": bench_ansatz, "batch": bench_batch}[args.workload]
+        fn = {"wide": bench_wide, "ansatz": bench_ansatz, "batch": bench_batch,
+              "nonlocal": bench_nonlocal}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return
     import torch

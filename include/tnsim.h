@@ -126,25 +126,29 @@ tnsim_status tnsim_mps_reset(tnsim_mps mps);
 /* One-qubit gate A'[a,s',b] = sum_s U[s',s] A[a,s,b]  (Sec. II, eq. 3). */
 tnsim_status tnsim_apply_1q(tnsim_mps mps, int32_t q, const tnsim_c128 u[4]);
 
-/* Local two-qubit gate, one gate per launch sequence: merge the two sites
-   (Sec. IV.A, Fig. 2), contract with the gate, Jacobi SVD, truncate, write
-   back (Sec. III.A). |q0-q1| must be 1. */
+/* Two-qubit gate, one gate per launch sequence: merge the two sites (Sec.
+   IV.A, Fig. 2), contract with the gate, Jacobi SVD, truncate, write back
+   (Sec. III.A).  Qubits further apart than neighbours are brought together
+   by SWAP gates and moved back afterwards (Sec. IV.A): the qubit with the
+   larger index is swapped down next to the other one, every SWAP being an
+   ordinary truncated two-qubit gate. */
 tnsim_status tnsim_apply_2q(tnsim_mps mps, int32_t q0, int32_t q1, const tnsim_c128 g[16]);
 
 /* All gates of one layer of gates on disjoint qubits (Sec. IV.B): the
    one-qubit gates in one launch, then every two-qubit gate of the layer in
-   the same launches (batched over gates). */
+   the same launches (batched over gates).  Two-qubit gates must act on
+   neighbouring qubits (TNSIM_E_NONLOCAL otherwise, state unchanged). */
 tnsim_status tnsim_apply_layer(tnsim_mps mps, const tnsim_gate *gates, int32_t n_gates);
 
-/* A whole circuit of local gates, in order (gates may share qubits; a gate
-   given as (q, q-1) is applied as SWAP G SWAP on (q-1, q), as in
-   tnsim_apply_2q).  The result equals applying the gates one by one (Sec.
+/* A whole circuit, in order (gates may share qubits; a gate given as
+   (q, q-1) is applied as SWAP G SWAP on (q-1, q), and a gate on distant
+   qubits through the SWAP chain of tnsim_apply_2q).  The result equals applying the gates one by one (Sec.
    III.A, gate application; Sec. IV.B, gates of a layer on disjoint qubits run
    in parallel): a gate starts once the gates before it on its qubits are
    done, and two-qubit gates in flight, from any layer, share the launches of
    every Jacobi sweep.  gates: host array of n_gates entries, read during the
-   call only.  Errors: TNSIM_E_ARG (qubit out of range, q0 == q1),
-   TNSIM_E_NONLOCAL (validated before any work, state unchanged);
+   call only.  Errors: TNSIM_E_ARG (qubit out of range, q0 == q1; validated
+   before any work, state unchanged);
    TNSIM_E_NOCONV (a Jacobi ran out of sweeps: the gates completed by then
    stay applied, each one whole and in an order consistent with the circuit,
    the others are not; the MPS stays valid); TNSIM_E_DEVICE. */

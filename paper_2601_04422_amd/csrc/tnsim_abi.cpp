@@ -857,6 +857,36 @@ void orient(int q0, int q1, const tnsim_c128 *g, Pending &p) {
   }
 }
 
+// A gate on distant qubits as local gates (Sec. IV.A): SWAP gates bring the
+// qubit with the larger index next to the other one, the gate acts there, and
+// the SWAPs are undone in reverse order.  Local and one-qubit gates pass
+// through unchanged.
+void expand_gate(const tnsim_gate &g, std::vector<tnsim_gate> &out) {
+  if (g.q1 < 0 || std::abs(g.q0 - g.q1) == 1) {
+    out.push_back(g);
+    return;
+  }
+  tnsim_gate sw;
+  memset(&sw, 0, sizeof sw);
+  for (int s = 0; s < 2; s++)
+    for (int t = 0; t < 2; t++) sw.m[(2 * t + s) * 4 + 2 * s + t].re = 1.0;
+  const int a = std::min(g.q0, g.q1), b = std::max(g.q0, g.q1);
+  for (int j = b - 1; j > a; j--) {
+    sw.q0 = j;
+    sw.q1 = j + 1;
+    out.push_back(sw);
+  }
+  tnsim_gate moved = g;  // the qubit from b now sits at a + 1
+  moved.q0 = g.q0 == a ? a : a + 1;
+  moved.q1 = g.q0 == a ? a + 1 : a;
+  out.push_back(moved);
+  for (int j = a + 1; j < b; j++) {
+    sw.q0 = j;
+    sw.q1 = j + 1;
+    out.push_back(sw);
+  }
+}
+
 // Validate a layer; fills 1q and 2q lists.
 tnsim_status validate_layer(tnsim_mps h, const tnsim_gate *gates, int ng,
                             std::vector<std::pair<int, const tnsim_c128 *>> &g1,
@@ -1572,11 +1602,19 @@ tnsim_status tnsim_apply_2q(tnsim_mps h, int32_t q0, int32_t q1, const tnsim_c12
   tnsim_status s = check_handle(h);
   if (s != TNSIM_OK) return s;
   if (!g || q0 < 0 || q1 < 0 || q0 >= h->L.n || q1 >= h->L.n || q0 == q1) return TNSIM_E_ARG;
-  if (std::abs(q0 - q1) != 1) return TNSIM_E_NONLOCAL;
-  Pending p;
-  orient(q0, q1, g, p);
   h->last_sweeps = 0;
   h->last_batch.clear();
+  if (std::abs(q0 - q1) != 1) {  // a SWAP chain, one local gate after the other
+    tnsim_gate gt;
+    gt.q0 = q0;
+    gt.q1 = q1;
+    memcpy(gt.m, g, sizeof gt.m);
+    std::vector<tnsim_gate> chain;
+    expand_gate(gt, chain);
+    return run_circuit(h, chain.data(), (int)chain.size());
+  }
+  Pending p;
+  orient(q0, q1, g, p);
   return run_2q_batch(h, &p, 1);
 }
 
@@ -1599,14 +1637,15 @@ tnsim_status tnsim_apply_circuit(tnsim_mps h, const tnsim_gate *gates, int32_t n
   if (s != TNSIM_OK) return s;
   const int n = h->L.n;
   if (n_gates < 0 || (n_gates > 0 && !gates)) return TNSIM_E_ARG;
+  std::vector<tnsim_gate> local;
   for (int k = 0; k < n_gates; k++) {
     const int a = gates[k].q0, b = gates[k].q1;
     if (a < 0 || a >= n || b < -1 || b >= n || a == b) return TNSIM_E_ARG;
-    if (b >= 0 && std::abs(a - b) != 1) return TNSIM_E_NONLOCAL;
+    expand_gate(gates[k], local);
   }
   h->last_sweeps = 0;
   h->last_batch.clear();
-  return run_circuit(h, gates, n_gates);
+  return run_circuit(h, local.data(), (int)local.size());
 }
 
 tnsim_status tnsim_apply_layer_multi(tnsim_mps const *mps, const tnsim_gate *const *gates,

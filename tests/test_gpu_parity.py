@@ -176,7 +176,7 @@ def test_errors_leave_state_unchanged(T):
     assert m.apply_layer([(0, 1, g), (1, 2, g)]) == T.E_OVERLAP
     assert m.apply_layer([(0, 2, g)]) == T.E_NONLOCAL
     assert m.apply_layer([(5, 6, g)]) == T.E_ARG
-    assert m.apply_2q(0, 3, g) == T.E_NONLOCAL
+    assert m.apply_2q(0, 6, g) == T.E_ARG
     assert list(m.bond_dims()) == [1] * (n - 1)
     nc = T.MPS(n, 8, jacobi_max_sweeps=1)
     rng = np.random.default_rng(2)
@@ -366,7 +366,6 @@ def test_circuit_scheduler_mixed_gates_amplitudes(T):
     m.run_circuit(gates)
     assert np.max(np.abs(gpu_statevector(m) - statevector(n, gates))) < 1e-12
     c = T.MPS(n, 64)
-    assert c.apply_circuit([(0, 2, W.cnot())]) == T.E_NONLOCAL
     assert c.apply_circuit([(0, n, W.cnot())]) == T.E_ARG
 
 
@@ -389,3 +388,40 @@ def test_degenerate_sizes_vs_oracle(T, precision, storage):
     # complex64 sites carry about 6e-8 relative rounding into the weights
     assert abs(g.stats()["sum_eps"] - o.stats()["sum_eps"]) < (1e-9 if storage == "c128" else 1e-6)
     assert 1 - _oracle_fid(g, o) < (1e-10 if storage == "c128" else 1e-6)
+
+
+# ---------------------------------------------------------------- non-local gates
+
+@pytest.mark.parametrize("mode", ["per_gate", "circuit"])
+@pytest.mark.parametrize("precision,storage,tol", [("fp64", "c128", 1e-12), ("bf16x6", "c64", 1e-6)])
+def test_nonlocal_gates_vs_statevector(T, mode, precision, storage, tol):
+    """Gates on distant qubits (SWAP chains, Sec. IV.A), one call per gate and
+    as one scheduled circuit, without truncation: amplitudes against brute force."""
+    from test_oracle_pins import nonlocal_circuit
+
+    n = 7
+    gates = nonlocal_circuit(n, 30, 314)
+    m = T.MPS(n, 256, precision=precision, storage=storage)
+    if mode == "per_gate":
+        m.run_gates(gates)
+    else:
+        m.run_circuit(gates)
+    assert np.max(np.abs(gpu_statevector(m) - statevector(n, gates))) < tol
+
+
+def test_nonlocal_truncating_vs_oracle(T):
+    """Distant gates with truncation: every SWAP is a truncated gate, so the
+    GPU must take the oracle's SWAP chain to match it."""
+    from test_oracle_pins import nonlocal_circuit
+
+    n, chi = 14, 16
+    gates = nonlocal_circuit(n, 50, 2718)
+    m = T.MPS(n, chi, 1e-10)
+    m.run_circuit(gates)
+    o = O.OracleMPS(n, chi, 1e-10)
+    o.run(gates)
+    assert list(m.bond_dims()) == list(o.bond_dims())
+    for b in range(n - 1):
+        assert np.max(np.abs(m.lam(b) - o.lam(b))) < 1e-10
+    assert 1 - _oracle_fid(m, o) < 1e-10
+    assert abs(m.stats()["sum_eps"] - o.stats()["sum_eps"]) < 1e-10
