@@ -79,6 +79,7 @@ def lib():
         L.om_overlap.argtypes = [P, P, dp, dp]
         L.om_amplitude.argtypes = [P, C.POINTER(C.c_uint8), dp, dp]
         L.om_statevector.argtypes = [P, dp]
+        L.om_sample.argtypes = [P, C.c_int, dp, C.POINTER(C.c_uint8), dp]
         L.om_set_threads.argtypes = [C.c_int]
         L.om_get_threads.restype = C.c_int
         _lib = L
@@ -229,6 +230,20 @@ class OracleMPS:
         self._check(lib().om_amplitude(self._h, b.ctypes.data_as(C.POINTER(C.c_uint8)),
                                        C.byref(re), C.byref(im)), "amplitude")
         return complex(re.value, im.value)
+
+    def sample(self, u: np.ndarray):
+        """Perfect sampling: u is shots x n uniforms in [0, 1) (u[shot, q]
+        decides qubit q; qubits drawn from n-1 down to 0).  Returns
+        (bits uint8 shots x n, log-probability of each drawn string)."""
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        if u.ndim != 2 or u.shape[1] != self.n:
+            raise ValueError("u must be shots x n")
+        bits = np.zeros(u.shape, dtype=np.uint8)
+        logp = np.zeros(u.shape[0], dtype=np.float64)
+        self._check(lib().om_sample(self._h, u.shape[0], _dp(u),
+                                    bits.ctypes.data_as(C.POINTER(C.c_uint8)), _dp(logp)),
+                    "sample")
+        return bits, logp
 
     def statevector(self) -> np.ndarray:
         out = np.zeros(2 ** self.n, dtype=np.complex128)

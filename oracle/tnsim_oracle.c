@@ -14,7 +14,8 @@
  *     with the gate, decompose by SVD, put the left singular vectors on the
  *     left (control) site and the singular values with the right singular
  *     vectors on the right (target) site (Sec. III.A), truncating the bond
- *     (Sec. II, best low-rank approximation; Sec. IV.A, truncation in the SVD).
+ *     (Sec. II, best low-rank approximation; Sec. IV.A, truncation in the SVD);
+ *   - perfect sampling of all qubits (Sec. III.A; see the sampling section).
  *
  * Readings where the paper is silent (each is listed in the design notes):
  *   - Gauge: every site is kept left-canonical and lambda_q holds the Schmidt
@@ -693,5 +694,112 @@ int om_statevector(const om_mps *m, double *out) {
   }
   memcpy(out, T, sizeof(cplx) * cur);
   free(T);
+  return OM_OK;
+}
+
+/* ----------------------------------------------------------------- sampling
+ * Perfect sampling ("measure all", Sec. III.A; Ferris and Vidal, Phys. Rev. B
+ * 85, 165146 (2012)): the qubits are drawn one at a time, each from its
+ * marginal given the bits already drawn, and the drawn bit is projected out
+ * and the rest renormalised before the next qubit.
+ *
+ * Order (a reading; the paper does not fix it): qubit n-1 first, then n-2,
+ * ..., 0.  With v the contraction A_{q+1}^{s_{q+1}} ... A_{n-1}^{s_{n-1}} of the
+ * drawn sites and
+ *   E_q = sum over s_0..s_{q-1} of L^H L,  L = A_0^{s_0} ... A_{q-1}^{s_{q-1}}
+ * (the Gram matrix of the left block; E_0 = 1), the weight of s_q = s is
+ * p_s = w_s^H E_q w_s with w_s = A_q^s v.  Bit 0 is taken when
+ * u < p_0 / (p_0 + p_1), else bit 1; then v = w_bit / sqrt(p_bit).  E_q keeps
+ * the marginals exact in any gauge (it is the identity when the left block is
+ * orthonormal).
+ *
+ * u: shots x n uniforms in [0, 1); u[shot * n + q] decides qubit q.
+ * bits: shots x n bytes (bits[shot * n + q] = s_q).
+ * logp (may be NULL): per shot, the sum over qubits of log(p_bit / (p_0 + p_1)),
+ * i.e. log(|<x|psi>|^2 / <psi|psi>) for the drawn string x.
+ */
+
+/* E[q] for q = 0..n-1, each dim[q] x dim[q] row-major. */
+static cplx **left_envs(const om_mps *m) {
+  const int n = m->n;
+  cplx **E = (cplx **)xalloc(sizeof(cplx *) * n);
+  E[0] = (cplx *)xalloc(sizeof(cplx));
+  E[0][0] = 1.0;
+  for (int q = 0; q + 1 < n; q++) {
+    const int la = m->dim[q], rb = m->dim[q + 1];
+    const cplx *A = m->A[q];
+    cplx *F = (cplx *)xalloc(sizeof(cplx) * (size_t)la * 2 * rb); /* F = E_q A_q */
+    for (int a = 0; a < la; a++)
+      for (int ap = 0; ap < la; ap++) {
+        cplx e = E[q][(size_t)a * la + ap];
+        for (int sb = 0; sb < 2 * rb; sb++) F[(size_t)a * 2 * rb + sb] += e * A[(size_t)ap * 2 * rb + sb];
+      }
+    cplx *En = (cplx *)xalloc(sizeof(cplx) * (size_t)rb * rb); /* A_q^H F */
+    for (int a = 0; a < la; a++)
+      for (int s = 0; s < 2; s++)
+        for (int b = 0; b < rb; b++) {
+          cplx w = conj(A[((size_t)a * 2 + s) * rb + b]);
+          const cplx *f = F + ((size_t)a * 2 + s) * rb;
+          for (int bp = 0; bp < rb; bp++) En[(size_t)b * rb + bp] += w * f[bp];
+        }
+    free(F);
+    E[q + 1] = En;
+  }
+  return E;
+}
+
+/* w^H E w for an la x la matrix E */
+static double env_weight(const cplx *E, const cplx *w, int la) {
+  cplx acc = 0.0;
+  for (int a = 0; a < la; a++) {
+    cplx t = 0.0;
+    for (int ap = 0; ap < la; ap++) t += E[(size_t)a * la + ap] * w[ap];
+    acc += conj(w[a]) * t;
+  }
+  return creal(acc);
+}
+
+int om_sample(const om_mps *m, int shots, const double *u, uint8_t *bits, double *logp) {
+  if (shots < 0) return OM_E_ARG;
+  const int n = m->n;
+  for (size_t i = 0; i < (size_t)shots * n; i++)
+    if (!(u[i] >= 0.0 && u[i] < 1.0)) return OM_E_ARG;
+  cplx **E = left_envs(m);
+  int chi = 1;
+  for (int q = 0; q <= n; q++) chi = m->dim[q] > chi ? m->dim[q] : chi;
+#pragma omp parallel for schedule(dynamic) if (shots >= 8)
+  for (int shot = 0; shot < shots; shot++) {
+    cplx *v = (cplx *)xalloc(sizeof(cplx) * chi);
+    cplx *w0 = (cplx *)xalloc(sizeof(cplx) * chi), *w1 = (cplx *)xalloc(sizeof(cplx) * chi);
+    double lp = 0.0;
+    v[0] = 1.0;
+    for (int q = n - 1; q >= 0; q--) {
+      const int la = m->dim[q], rb = m->dim[q + 1];
+      const cplx *A = m->A[q];
+      for (int a = 0; a < la; a++) {
+        cplx t0 = 0.0, t1 = 0.0;
+        for (int b = 0; b < rb; b++) {
+          t0 += A[((size_t)a * 2 + 0) * rb + b] * v[b];
+          t1 += A[((size_t)a * 2 + 1) * rb + b] * v[b];
+        }
+        w0[a] = t0;
+        w1[a] = t1;
+      }
+      const double p0 = env_weight(E[q], w0, la), p1 = env_weight(E[q], w1, la);
+      const int bit = u[(size_t)shot * n + q] < p0 / (p0 + p1) ? 0 : 1;
+      const double pb = bit ? p1 : p0;
+      bits[(size_t)shot * n + q] = (uint8_t)bit;
+      lp += log(pb / (p0 + p1));
+      const cplx *wb = bit ? w1 : w0;
+      const double r = 1.0 / sqrt(pb);
+      for (int a = 0; a < la; a++) v[a] = wb[a] * r;
+    }
+    if (logp) logp[shot] = lp;
+    free(v);
+    free(w0);
+    free(w1);
+  }
+  for (int q = 0; q < n; q++) free(E[q]);
+  free(E);
   return OM_OK;
 }

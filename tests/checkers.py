@@ -4,6 +4,8 @@ the GPU library and are used to pin both.
 * ``statevector``      brute-force state vector, index x = sum_q b_q 2^q
                        (direct contraction of the circuit, Sec. II.A eq. 1).
 * ``schmidt_values``   singular values of the state reshaped at a cut.
+* ``sample_dense``      sequential sampling from a state vector: each qubit's
+                       conditional from marginals summed over the full |psi|^2.
 * ``pauli_expect_clifford``  <0|U^dag P U|0> by Heisenberg-picture Pauli
                        propagation for Clifford circuits (each gate maps a
                        Pauli string to a signed Pauli string; the map is found
@@ -150,3 +152,25 @@ def stabilizer_generator(n: int, gates: Sequence, q: int) -> Tuple[complex, str]
         for x, l in zip(qs, new):
             p[x] = l
     return phase, "".join(p)
+
+
+def sample_dense(psi: np.ndarray, n: int, u: np.ndarray):
+    """Draw qubits n-1, n-2, ..., 0 in turn; qubit q gets bit 0 when
+    u[shot, q] < P(s_q = 0 | bits drawn so far), every marginal summed over
+    the whole probability vector.  Returns (bits shots x n, log P(x))."""
+    prob = np.abs(psi) ** 2
+    total = prob.sum()
+    shots = u.shape[0]
+    bits = np.zeros((shots, n), dtype=np.uint8)
+    logp = np.zeros(shots)
+    # marg[q][key]: total probability of the strings whose bits q..n-1 read key
+    marg = [prob.reshape(2 ** (n - q), 2 ** q).sum(axis=1) for q in range(n + 1)]
+    for shot in range(shots):
+        key = 0
+        for q in range(n - 1, -1, -1):
+            m0, m1 = marg[q][2 * key], marg[q][2 * key + 1]
+            b = 0 if u[shot, q] < m0 / (m0 + m1) else 1
+            bits[shot, q] = b
+            key = 2 * key + b
+        logp[shot] = np.log(prob[key] / total)
+    return bits, logp

@@ -43,6 +43,12 @@ MUTANTS = {
     "far qubit orientation lost": (
         "q0 == a ? apply_2q_adjacent(m, a, a + 1, G) : apply_2q_adjacent(m, a + 1, a, G);",
         "apply_2q_adjacent(m, a, a + 1, G);"),
+    "sampling ignores the environment": ("for (int ap = 0; ap < la; ap++) t += E[(size_t)a * la + ap] * w[ap];",
+                                         "for (int ap = 0; ap < la; ap++) t += (a == ap) * w[ap];"),
+    "sampling threshold on the other bit": ("u[(size_t)shot * n + q] < p0 / (p0 + p1) ? 0 : 1",
+                                            "u[(size_t)shot * n + q] < p1 / (p0 + p1) ? 0 : 1"),
+    "sampling projects the other outcome": ("const cplx *wb = bit ? w1 : w0;",
+                                            "const cplx *wb = bit ? w0 : w1;"),
 }
 
 PIN_CALLS = [
@@ -58,6 +64,10 @@ PIN_CALLS = [
     pins.test_layer_order_independence,
     pins.test_nonlocal_gates_match_statevector,
     pins.test_nonlocal_ghz_closed_form,
+    pins.test_sampling_matches_brute_force,
+    pins.test_sampling_in_any_gauge,
+    pins.test_sampling_product_state_closed_form,
+    pins.test_sampling_ghz_closed_form,
 ]
 
 

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 from checkers import (amplitude_index, expect_dense, fidelity_dense, pauli_expect_clifford,
-                      schmidt_values, stabilizer_generator, statevector)
+                      sample_dense, schmidt_values, stabilizer_generator, statevector)
 from oracle import oracle as O
 from paper_2601_04422_amd import workloads as W
 
@@ -403,3 +403,106 @@ def test_nonlocal_ghz_closed_form():
     assert abs(m.amplitude([0] * n) - 1 / math.sqrt(2)) < 1e-14
     assert abs(m.amplitude([1] * n) - 1 / math.sqrt(2)) < 1e-14
     assert int(max(m.bond_dims())) == 2
+
+
+# ---------------------------------------------------------------- P: perfect sampling
+
+def _assert_same_draws(bits, ref_bits, u, psi, n, margin=1e-9):
+    """Bits must agree wherever the draw was not a near-tie of u with the
+    conditional probability (none is expected with these seeds)."""
+    prob = np.abs(psi) ** 2
+    marg = [prob.reshape(2 ** (n - q), 2 ** q).sum(axis=1) for q in range(n + 1)]
+    for shot in np.nonzero((bits != ref_bits).any(axis=1))[0]:
+        key = 0
+        for q in range(n - 1, -1, -1):
+            m0, m1 = marg[q][2 * key], marg[q][2 * key + 1]
+            if bits[shot, q] != ref_bits[shot, q]:
+                assert abs(u[shot, q] - m0 / (m0 + m1)) < margin, (shot, q)
+                break
+            key = 2 * key + int(ref_bits[shot, q])
+
+
+def test_sampling_matches_brute_force():
+    """Sec. III.A perfect sampling: with the same uniforms, every drawn string
+    equals sequential sampling from the brute-force state vector, and the
+    returned log-probability is log(|<x|psi>|^2)."""
+    n = 8
+    gates = nonlocal_circuit(n, 40, 2718)
+    m = O.run_gates(n, 256, 0.0, gates)
+    psi = statevector(n, gates)
+    u = np.random.default_rng(17).random((300, n))
+    bits, logp = m.sample(u)
+    ref_bits, ref_logp = sample_dense(psi, n, u)
+    assert np.array_equal(bits, ref_bits)
+    assert np.max(np.abs(logp - ref_logp)) < 1e-10
+    assert len({tuple(b) for b in bits}) > 100  # a spread distribution, not one string
+
+
+def test_sampling_in_any_gauge():
+    """The marginals use the left block's Gram matrix, so a state stored in a
+    non-canonical gauge (random invertible matrices on every bond) and with
+    a norm other than 1 samples exactly like the canonical one."""
+    n = 7
+    gates = nonlocal_circuit(n, 30, 99)
+    m = O.run_gates(n, 256, 0.0, gates)
+    rng = np.random.default_rng(3)
+    sites = [m.site(q) for q in range(n)]
+    for q in range(n - 1):
+        chi = sites[q].shape[2]
+        X = np.eye(chi) + 0.4 * (rng.normal(size=(chi, chi)) + 1j * rng.normal(size=(chi, chi)))
+        sites[q] = np.einsum("asb,bc->asc", sites[q], X)
+        sites[q + 1] = np.einsum("cb,bsd->csd", np.linalg.inv(X), sites[q + 1])
+    sites[0] = 1.7 * sites[0]
+    g = O.OracleMPS(n, 256)
+    g.set_state(sites, [m.lam(b) for b in range(n - 1)])
+    psi = statevector(n, gates)
+    u = np.random.default_rng(18).random((200, n))
+    bits, logp = g.sample(u)
+    ref_bits, ref_logp = sample_dense(psi, n, u)
+    _assert_same_draws(bits, ref_bits, u, psi, n)
+    assert np.array_equal(bits, ref_bits)
+    assert np.max(np.abs(logp - ref_logp)) < 1e-9
+
+
+def test_sampling_product_state_closed_form():
+    """Ry(theta_q)|0> on every qubit: qubit q reads 0 with probability
+    cos^2(theta_q / 2), independently of the others."""
+    n = 10
+    rng = np.random.default_rng(4)
+    th = rng.uniform(0.2, 2.9, n)
+    m = O.OracleMPS(n, 4)
+    for q in range(n):
+        m.apply((q, -1, W.ry(th[q])))
+    u = rng.random((100, n))
+    bits, logp = m.sample(u)
+    p0 = np.cos(th / 2) ** 2
+    assert np.array_equal(bits, (u >= p0[None, :]).astype(np.uint8))
+    ref = np.where(bits == 0, np.log(p0)[None, :], np.log1p(-p0)[None, :]).sum(axis=1)
+    assert np.max(np.abs(logp - ref)) < 1e-12
+
+
+def test_sampling_ghz_closed_form():
+    """GHZ: every string is all zeros or all ones with probability 1/2, and
+    the first qubit drawn (n-1) decides which."""
+    n = 16
+    gates = [(0, -1, W.hadamard())] + [(j, j + 1, W.cnot()) for j in range(n - 1)]
+    m = O.run_gates(n, 4, 0.0, gates)
+    u = np.random.default_rng(6).random((64, n))
+    bits, logp = m.sample(u)
+    want = (u[:, n - 1] >= 0.5).astype(np.uint8)
+    assert np.array_equal(bits, np.repeat(want[:, None], n, axis=1))
+    assert np.max(np.abs(logp - math.log(0.5))) < 1e-13
+
+
+def test_sampling_frequencies():
+    """Frequencies of 20000 draws from a 5-qubit state against |psi|^2
+    (total variation well inside the sampling noise of ~0.02)."""
+    n = 5
+    gates = nonlocal_circuit(n, 20, 7)
+    m = O.run_gates(n, 64, 0.0, gates)
+    u = np.random.default_rng(8).random((20000, n))
+    bits, _ = m.sample(u)
+    idx = bits.astype(np.int64) @ (1 << np.arange(n))
+    freq = np.bincount(idx, minlength=2 ** n) / len(idx)
+    prob = np.abs(statevector(n, gates)) ** 2
+    assert 0.5 * np.abs(freq - prob).sum() < 0.03
