@@ -206,6 +206,31 @@ tnsim_status tnsim_export_lambda(tnsim_mps mps, int32_t bond, double *host, int3
 tnsim_status tnsim_import_state(tnsim_mps mps, const tnsim_c128 *const *sites,
                                 const double *const *lambdas, const int32_t *chis);
 
+/* ---- perfect sampling ("measure all" shots, Sec. III.A; Ferris and Vidal,
+   Phys. Rev. B 85, 165146 (2012)) ----
+   Draws `shots` bit strings x with probability |<x|psi>|^2 / <psi|psi>.
+   Qubits are drawn from n-1 down to 0; qubit q of shot i takes bit 0 when
+   dev_u[i*n + q] < P(s_q = 0 | bits drawn so far), else bit 1.  The
+   conditionals come from the left-block Gram matrices E_q, so they are exact
+   in any gauge (E_q = I for a left-orthonormal block).  Shots that drew the
+   same bits so far share one partial contraction (the memo of drawn
+   prefixes), so each step contracts at most min(2^(n-1-q), shots) vectors.
+   All arithmetic is float64.  The state is not modified.
+     dev_ws     device workspace of tnsim_sample_workspace_bytes(cfg, m) bytes
+                for some m >= shots, 256-byte aligned, owned by the caller;
+     dev_u      device, shots x n float64 uniforms in [0, 1), row-major by shot;
+     dev_bits   device, shots x n bytes (0/1), written;
+     dev_logp   device, shots float64 (log of each drawn string's probability),
+                written, or NULL.
+   The call runs on the handle's stream and returns after it has finished.
+   Errors: TNSIM_E_ARG for a bad pointer or shot count, or (found on the
+   device, after the draws) a uniform outside [0, 1) -- dev_bits is then
+   unspecified; TNSIM_E_CAPACITY when ws_bytes is too small.  shots = 0 does
+   nothing. */
+size_t tnsim_sample_workspace_bytes(const tnsim_config *cfg, int32_t max_shots);
+tnsim_status tnsim_sample(tnsim_mps mps, void *dev_ws, size_t ws_bytes, int32_t shots,
+                          const double *dev_u, uint8_t *dev_bits, double *dev_logp);
+
 /* ---- gradients of a Pauli-sum loss with respect to rotation angles ----
    Loss L = sum_t coeffs[t] <psi|P_t|psi>/<psi|psi>, psi = circuit |0...0>.
    Gate g of `circuit` with param_of_gate[g] = p >= 0 is the rotation

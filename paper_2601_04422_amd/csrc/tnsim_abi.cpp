@@ -1800,6 +1800,118 @@ tnsim_status tnsim_amplitude(tnsim_mps h, const uint8_t *bits, tnsim_c128 *out) 
   return TNSIM_OK;
 }
 
+// Workspace of tnsim_sample: the left-block Gram matrices E_q of every site
+// and the node tables of one step (see k_sample.hip).
+struct SampleLayout {
+  std::vector<size_t> env;  // E_q, dimcap[q]^2 complex128
+  size_t F = 0, V0 = 0, V1 = 0, W = 0, Y = 0, p = 0, flag = 0, idx = 0, node = 0, key = 0,
+         logp = 0, ctr = 0, total = 0;
+};
+
+static SampleLayout sample_layout(const Layout &L, int max_shots) {
+  SampleLayout S;
+  const int n = L.n;
+  int dmax = 1;
+  for (int q = 0; q <= n; q++) dmax = std::max(dmax, L.dimcap[q]);
+  const size_t ms = (size_t)std::max(max_shots, 1);
+  size_t off = 0;
+  S.env.resize(n);
+  for (int q = 0; q < n; q++) {
+    S.env[q] = off;
+    off = align_up(off + sizeof(double2) * (size_t)L.dimcap[q] * L.dimcap[q]);
+  }
+  S.F = off;
+  off = align_up(off + sizeof(double2) * (size_t)dmax * 2 * dmax);
+  S.V0 = off;
+  off = align_up(off + sizeof(double2) * ms * dmax);
+  S.V1 = off;
+  off = align_up(off + sizeof(double2) * ms * dmax);
+  S.W = off;
+  off = align_up(off + sizeof(double2) * 2 * ms * dmax);
+  S.Y = off;
+  off = align_up(off + sizeof(double2) * 2 * ms * dmax);
+  S.p = off;
+  off = align_up(off + sizeof(double) * 2 * ms);
+  S.flag = off;
+  off = align_up(off + sizeof(int) * (2 * ms + 1));
+  S.idx = off;
+  off = align_up(off + sizeof(int) * (2 * ms + 1));
+  S.node = off;
+  off = align_up(off + sizeof(int) * ms);
+  S.key = off;
+  off = align_up(off + sizeof(int) * ms);
+  S.logp = off;
+  off = align_up(off + sizeof(double) * ms);
+  S.ctr = off;
+  off = align_up(off + sizeof(int) * 4);
+  S.total = off;
+  return S;
+}
+
+size_t tnsim_sample_workspace_bytes(const tnsim_config *cfg, int32_t max_shots) {
+  if (!valid_config(cfg) || max_shots < 1 || max_shots > (1 << 28)) return 0;
+  return sample_layout(make_layout(*cfg), max_shots).total;
+}
+
+tnsim_status tnsim_sample(tnsim_mps h, void *dev_ws, size_t ws_bytes, int32_t shots,
+                          const double *dev_u, uint8_t *dev_bits, double *dev_logp) {
+  tnsim_status s = check_handle(h);
+  if (s != TNSIM_OK) return s;
+  if (shots < 0 || shots > (1 << 28)) return TNSIM_E_ARG;
+  if (shots == 0) return TNSIM_OK;
+  if (!dev_ws || !dev_u || !dev_bits) return TNSIM_E_ARG;
+  if (reinterpret_cast<uintptr_t>(dev_ws) % ALIGN) return TNSIM_E_ARG;
+  const Layout &L = h->L;
+  const SampleLayout S = sample_layout(L, shots);
+  if (ws_bytes < S.total) return TNSIM_E_CAPACITY;
+  const int n = L.n, sto = L.storage;
+  hipStream_t st = h->stream;
+  char *ws = (char *)dev_ws;
+  auto E = [&](int q) { return (double2 *)(ws + S.env[q]); };
+  double2 *F = (double2 *)(ws + S.F), *V = (double2 *)(ws + S.V0), *Vn = (double2 *)(ws + S.V1);
+  double2 *Wb = (double2 *)(ws + S.W), *Yb = (double2 *)(ws + S.Y);
+  double *p = (double *)(ws + S.p), *logp = (double *)(ws + S.logp);
+  int *flag = (int *)(ws + S.flag), *idx = (int *)(ws + S.idx), *node = (int *)(ws + S.node),
+      *key = (int *)(ws + S.key), *ctr = (int *)(ws + S.ctr);
+  launch_smp_init(st, shots, node, logp, flag, V, E(0), ctr);
+  // E_{q+1} = sum_s A_q^{s H} E_q A_q^s, as F = E_q A_q, then A_q^H F
+  for (int q = 0; q + 1 < n; q++) {
+    const int la = h->dims[q], rb = h->dims[q + 1];
+    launch_gemm_nn(st, la, 2 * rb, la, E(q), la, h->site(q), 2 * rb, sto, F, 2 * rb);
+    launch_gemm_cn(st, rb, rb, 2 * la, h->site(q), rb, sto, F, rb, E(q + 1), rb);
+  }
+  LAUNCHCHK(h, "sample environments");
+  long long mb = 1;  // bound on the node count before the step
+  for (int q = n - 1; q >= 0; q--) {
+    const int la = h->dims[q], rb = h->dims[q + 1];
+    const int b1 = (int)std::min<long long>(mb, shots);
+    const char *A = (const char *)h->site(q);
+    for (int sb = 0; sb < 2; sb++)
+      launch_smp_gemm(st, la, rb, b1, ctr, 1, A + (size_t)sb * rb * L.elem, sto, 2LL * rb, V, rb,
+                      Wb + (size_t)sb * la, 2 * la);
+    launch_smp_gemm(st, la, la, 2 * b1, ctr, 2, E(q), 0, la, Wb, la, Yb, la);
+    launch_smp_prob(st, Wb, Yb, la, 2 * b1, ctr, p);
+    launch_smp_decide(st, shots, n, q, dev_u, p, node, key, flag, dev_bits, logp, ctr + 1);
+    launch_smp_scan(st, flag, idx, ctr);
+    launch_smp_gather(st, Wb, p, idx, ctr, 2 * b1, la, Vn);
+    launch_smp_relabel(st, shots, key, idx, node);
+    LAUNCHCHK(h, "sample step");
+    std::swap(V, Vn);
+    mb = std::min<long long>(2 * mb, shots);
+  }
+  if (dev_logp)
+    HIPCHK(h, hipMemcpyAsync(dev_logp, logp, sizeof(double) * shots, hipMemcpyDeviceToDevice, st));
+  HIPCHK(h, hipMemcpyAsync(h->pin, ctr, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(h, hipStreamSynchronize(st));
+  int c[4];
+  memcpy(c, h->pin, sizeof c);
+  if (c[1] || c[2]) {
+    h->err = c[1] ? "sample: a uniform outside [0, 1)" : "sample: a node of zero weight";
+    return TNSIM_E_ARG;
+  }
+  return TNSIM_OK;
+}
+
 tnsim_status tnsim_mps_copy(tnsim_mps dst, tnsim_mps src) {
   tnsim_status s = check_handle(dst);
   if (s != TNSIM_OK) return s;

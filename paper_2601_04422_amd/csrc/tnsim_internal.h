@@ -173,6 +173,21 @@ void launch_gemm_cn(hipStream_t st, int M, int N, int K, const void *A, int lda,
                     const double2 *B, int ldb, double2 *C, int ldc);
 void launch_pauli_phys(hipStream_t st, const double2 *F, double2 *F2, int chiA, int chiB,
                        double2 p00, double2 p01, double2 p10, double2 p11);
+// perfect sampling (k_sample.hip)
+void launch_smp_init(hipStream_t st, int shots, int *node, double *logp, int *flag, double2 *V,
+                     double2 *E0, int *ctr);
+void launch_smp_gemm(hipStream_t st, int M, int K, int bound, const int *mcount, int mult,
+                     const void *A, int a_storage, long long lda, const double2 *B, int ldb,
+                     double2 *C, int ldc);
+void launch_smp_prob(hipStream_t st, const double2 *W, const double2 *Y, int M, int bound,
+                     const int *mcount, double *p);
+void launch_smp_decide(hipStream_t st, int shots, int n, int q, const double *u, const double *p,
+                       const int *node, int *key, int *flag, uint8_t *bits, double *logp,
+                       int *err);
+void launch_smp_scan(hipStream_t st, int *flag, int *idx, int *ctr);
+void launch_smp_gather(hipStream_t st, const double2 *W, const double *p, const int *idx,
+                       const int *ctr, int bound, int M, double2 *Vn);
+void launch_smp_relabel(hipStream_t st, int shots, const int *key, const int *idx, int *node);
 void launch_amp_step(hipStream_t st, const double2 *v, double2 *w, const void *A, int storage,
                      int chiL, int chiR, int bit);
 

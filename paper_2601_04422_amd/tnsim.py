@@ -74,6 +74,8 @@ _SIGS = {
                                              C.c_int32, _P, C.c_int32, _P, _P, C.c_int32,
                                              C.POINTER(C.c_double)]),
     "tnsim_backward": (C.c_int, [_P, C.c_double, _P]),
+    "tnsim_sample_workspace_bytes": (C.c_size_t, [C.POINTER(Config), C.c_int32]),
+    "tnsim_sample": (C.c_int, [_P, _P, C.c_size_t, C.c_int32, _P, _P, _P]),
     "tnsim_profile": (C.c_int, [_P, C.c_int32]),
     "tnsim_profile_read": (C.c_int, [_P, _P]),
     "tnsim_autotune": (C.c_int, [_P, _P]),
@@ -335,6 +337,37 @@ class MPS:
         g = np.zeros(max(self._n_params, 1), dtype=np.float64)
         self._chk(lib().tnsim_backward(self._h, dloss, g.ctypes.data), "backward")
         return g[: self._n_params]
+
+    # ---------------------------------------------------------------- sampling
+    def sample(self, u):
+        """Perfect sampling of all qubits (tnsim_sample).  ``u`` holds
+        shots x n uniforms in [0, 1) (numpy or a torch tensor; u[i, q] decides
+        qubit q of shot i).  Returns (bits, logp) as torch tensors on the
+        device: uint8 shots x n, float64 shots."""
+        import torch
+
+        ut = torch.as_tensor(u, dtype=torch.float64).to(self.device).contiguous()
+        if ut.dim() != 2 or ut.shape[1] != self.n:
+            raise ValueError("u must be shots x n")
+        shots = ut.shape[0]
+        bits = torch.empty((shots, self.n), dtype=torch.uint8, device=self.device)
+        logp = torch.empty(shots, dtype=torch.float64, device=self.device)
+        if shots == 0:
+            return bits, logp
+        ws = lib().tnsim_sample_workspace_bytes(C.byref(self.cfg), shots)
+        if ws == 0:
+            raise TnsimError(E_ARG, "sample_workspace_bytes")
+        if getattr(self, "_smp_ws", None) is None or self._smp_ws.numel() < ws:
+            self._smp_ws = None
+            self._smp_ws = torch.empty(ws, dtype=torch.uint8, device=self.device)
+        # the uniforms and outputs were made on torch's stream; the library
+        # runs on the handle's stream and returns after it has finished
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        self._chk(lib().tnsim_sample(self._h, C.c_void_p(self._smp_ws.data_ptr()),
+                                     self._smp_ws.numel(), shots, C.c_void_p(ut.data_ptr()),
+                                     C.c_void_p(bits.data_ptr()), C.c_void_p(logp.data_ptr())),
+                  "sample")
+        return bits, logp
 
     def sweep_stats(self) -> dict:
         g, sm = C.c_int64(), C.c_int64()
