@@ -138,10 +138,11 @@ def parse():
     ap.add_argument("--circuit", action="store_true",
                     help="batched path: the timed layers as one dependency-scheduled "
                          "circuit call instead of one call per sublayer")
+    ap.add_argument("--shots", type=int, default=4096, help="sample workload: shots per call")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=16)
     ap.add_argument("--workload", default="chi1024",
-                    choices=["chi1024", "wide", "ansatz", "batch", "nonlocal"],
+                    choices=["chi1024", "wide", "ansatz", "batch", "nonlocal", "sample"],
                     help="chi1024: the headline metric; the others measure the secondary "
                          "workloads (one JSON line each)")
     return ap.parse_args()
@@ -396,6 +397,51 @@ def bench_nonlocal(args):
             "max_bond": int(max(m.bond_dims()))}
 
 
+def bench_sample(args):
+    """Perfect sampling from the chi=1024 benchmark state: the n=100 benchmark
+    circuit runs on the mixed path (untimed, --prep-layers layers) until the
+    bonds saturate, then each timed step draws --shots strings in one call,
+    uniforms already on the GPU.  The first strings' log-probabilities are
+    checked against |<x|psi>|^2 / <psi|psi> from the amplitude path."""
+    import torch
+
+    from paper_2601_04422_amd import tnsim as T
+
+    n, chi, S = 100, args.chi, args.shots
+    layers = circuit_layers(args.prep_layers)
+    m = T.MPS(n, chi, 1e-12, precision=args.precision, storage=args.storage)
+    t0 = time.perf_counter()
+    for l in range(args.prep_layers):
+        run_layer_batched(m, layers[l])
+        log(f"prep layer {l}: max chi {int(max(m.bond_dims()))}")
+    torch.cuda.synchronize()
+    log(f"state ready: max chi {int(max(m.bond_dims()))}, "
+        f"{sum(1 for d in m.bond_dims() if d == chi)} bonds at {chi} "
+        f"({time.perf_counter() - t0:.1f} s)")
+    rng = np.random.default_rng(2024)
+    u = torch.as_tensor(rng.random((S, n)), device=m.device)
+    for _ in range(args.warmup):
+        m.sample(u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        bits, logp = m.sample(u)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    b = bits.cpu().numpy()
+    lp = logp.cpu().numpy()
+    nrm = m.norm2()
+    err = max(abs(lp[i] - math.log(abs(m.amplitude(b[i])) ** 2 / nrm)) for i in range(8))
+    return {"metric": "shots/s, perfect sampling of all 100 qubits at chi=1024",
+            "value": S / dt, "unit": "shots/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": 1e3 * dt, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"benchmark circuit state after {args.prep_layers} layers "
+                                   f"({args.precision}, {args.storage}), {S} shots per call"},
+            "distinct_strings": int(len({tuple(r) for r in b})),
+            "max_abs_logp_err_vs_amplitude": err}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -404,7 +450,7 @@ def main():
         sys.exit(2)
     if args.workload != "chi1024":
         fn = {"wide": bench_wide, "ansatz": bench_ansatz, "batch": bench_batch,
-              "nonlocal": bench_nonlocal}[args.workload]
+              "nonlocal": bench_nonlocal, "sample": bench_sample}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return
     import torch

@@ -11,6 +11,7 @@
 //
 //   W[:, 2j+s] = A_q^s v_j                      (two GEMMs, s = 0, 1)
 //   Y          = E_q W                          (one GEMM; E_q = left-block Gram)
+// (the GEMMs, and those that build E_q, run on the matrix cores: k_zgemm.hip)
 //   p[c]       = Re W[:, c]^H Y[:, c]           (weight of node j with bit s)
 //   per shot:  bit = u < p[2j] / (p[2j] + p[2j+1]) ? 0 : 1, key = 2j + bit
 //   the used keys are numbered in order (scan) and become the next nodes,
@@ -23,63 +24,6 @@
 #include "tn_complex.h"
 
 namespace tn {
-
-constexpr int ST = 64, SK = 16;
-
-// C[:, c] = A B[:, c] for c < min(bound, mult * *mcount): A is M x K with row
-// stride lda (unit stride along K), B is K x cols with column stride ldb
-// (unit stride along K), C is M x cols with column stride ldc.
-template <class SA>
-__global__ __launch_bounds__(256) void k_smp_gemm(int M, int K, int bound, const int *mcount,
-                                                  int mult, const SA *A, long long lda,
-                                                  const double2 *B, int ldb, double2 *C,
-                                                  int ldc) {
-  const int ncols = min(bound, mult * *mcount);
-  const int j0 = blockIdx.x * ST, i0 = blockIdx.y * ST;
-  if (j0 >= ncols) return;
-  __shared__ double2 As[SK * ST], Bs[SK * ST];
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  double2 acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; i++)
-#pragma unroll
-    for (int j = 0; j < 4; j++) acc[i][j] = make_double2(0.0, 0.0);
-  const int r = tid >> 2, kq = (tid & 3) * 4;
-  for (int k0 = 0; k0 < K; k0 += SK) {
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-      const int gk = k0 + kq + q;
-      const int gi = i0 + r, gj = j0 + r;
-      As[(kq + q) * ST + r] = (gi < M && gk < K) ? cload(A + gi * lda + gk) : make_double2(0, 0);
-      Bs[(kq + q) * ST + r] =
-          (gj < ncols && gk < K) ? B[(size_t)gj * ldb + gk] : make_double2(0, 0);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < SK; kk++) {
-      double2 a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; i++) a[i] = As[kk * ST + tx + 16 * i];
-#pragma unroll
-      for (int j = 0; j < 4; j++) b[j] = Bs[kk * ST + ty + 16 * j];
-#pragma unroll
-      for (int i = 0; i < 4; i++)
-#pragma unroll
-        for (int j = 0; j < 4; j++) cfma(acc[i][j], a[i], b[j]);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int j = 0; j < 4; j++) {
-    const int gj = j0 + ty + 16 * j;
-    if (gj >= ncols) continue;
-#pragma unroll
-    for (int i = 0; i < 4; i++) {
-      const int gi = i0 + tx + 16 * i;
-      if (gi < M) C[(size_t)gj * ldc + gi] = acc[i][j];
-    }
-  }
-}
 
 // p[c] = Re sum_a conj(W[a, c]) Y[a, c], one wave per column.
 __global__ __launch_bounds__(256) void k_smp_prob(const double2 *W, const double2 *Y, int M,
@@ -200,19 +144,6 @@ void launch_smp_init(hipStream_t st, int shots, int *node, double *logp, int *fl
   const int total = std::max(shots, nflag);
   hipLaunchKernelGGL(k_smp_init, dim3((total + 255) / 256), dim3(256), 0, st, shots, nflag, node,
                      logp, flag, V, E0, ctr);
-}
-
-void launch_smp_gemm(hipStream_t st, int M, int K, int bound, const int *mcount, int mult,
-                     const void *A, int a_storage, long long lda, const double2 *B, int ldb,
-                     double2 *C, int ldc) {
-  if (bound <= 0 || M <= 0) return;
-  dim3 grid((bound + ST - 1) / ST, (M + ST - 1) / ST);
-  if (a_storage == 0)
-    hipLaunchKernelGGL(k_smp_gemm<double2>, grid, dim3(256), 0, st, M, K, bound, mcount, mult,
-                       (const double2 *)A, lda, B, ldb, C, ldc);
-  else
-    hipLaunchKernelGGL(k_smp_gemm<float2>, grid, dim3(256), 0, st, M, K, bound, mcount, mult,
-                       (const float2 *)A, lda, B, ldb, C, ldc);
 }
 
 void launch_smp_prob(hipStream_t st, const double2 *W, const double2 *Y, int M, int bound,

@@ -1804,8 +1804,8 @@ tnsim_status tnsim_amplitude(tnsim_mps h, const uint8_t *bits, tnsim_c128 *out) 
 // and the node tables of one step (see k_sample.hip).
 struct SampleLayout {
   std::vector<size_t> env;  // E_q, dimcap[q]^2 complex128
-  size_t F = 0, V0 = 0, V1 = 0, W = 0, Y = 0, p = 0, flag = 0, idx = 0, node = 0, key = 0,
-         logp = 0, ctr = 0, total = 0;
+  size_t F = 0, P = 0, V0 = 0, V1 = 0, W = 0, Y = 0, p = 0, flag = 0, idx = 0, node = 0,
+         key = 0, logp = 0, ctr = 0, total = 0;
 };
 
 static SampleLayout sample_layout(const Layout &L, int max_shots) {
@@ -1822,6 +1822,8 @@ static SampleLayout sample_layout(const Layout &L, int max_shots) {
   }
   S.F = off;
   off = align_up(off + sizeof(double2) * (size_t)dmax * 2 * dmax);
+  S.P = off;  // split-K partial products of the environment GEMMs
+  off = align_up(off + sizeof(double2) * ZGEMM_PART_ELEMS);
   S.V0 = off;
   off = align_up(off + sizeof(double2) * ms * dmax);
   S.V1 = off;
@@ -1875,10 +1877,17 @@ tnsim_status tnsim_sample(tnsim_mps h, void *dev_ws, size_t ws_bytes, int32_t sh
       *key = (int *)(ws + S.key), *ctr = (int *)(ws + S.ctr);
   launch_smp_init(st, shots, node, logp, flag, V, E(0), ctr);
   // E_{q+1} = sum_s A_q^{s H} E_q A_q^s, as F = E_q A_q, then A_q^H F
+  double2 *Pb = (double2 *)(ws + S.P);
   for (int q = 0; q + 1 < n; q++) {
     const int la = h->dims[q], rb = h->dims[q + 1];
-    launch_gemm_nn(st, la, 2 * rb, la, E(q), la, h->site(q), 2 * rb, sto, F, 2 * rb);
-    launch_gemm_cn(st, rb, rb, 2 * la, h->site(q), rb, sto, F, rb, E(q + 1), rb);
+    ZgemmArgs f{la, 2 * rb, la, E(q), la, h->site(q), 2 * rb, F, 2 * rb, nullptr, 0};
+    f.ksplit = zgemm_ksplit(la, 2 * rb, la);
+    f.part = Pb;
+    launch_zgemm(st, ZGEMM_NN_ROW, f, 0, sto);
+    ZgemmArgs e{rb, rb, 2 * la, h->site(q), rb, F, rb, E(q + 1), rb, nullptr, 0};
+    e.ksplit = zgemm_ksplit(rb, rb, 2 * la);
+    e.part = Pb;
+    launch_zgemm(st, ZGEMM_CN_ROW, e, sto, 0);
   }
   LAUNCHCHK(h, "sample environments");
   long long mb = 1;  // bound on the node count before the step
@@ -1886,10 +1895,13 @@ tnsim_status tnsim_sample(tnsim_mps h, void *dev_ws, size_t ws_bytes, int32_t sh
     const int la = h->dims[q], rb = h->dims[q + 1];
     const int b1 = (int)std::min<long long>(mb, shots);
     const char *A = (const char *)h->site(q);
-    for (int sb = 0; sb < 2; sb++)
-      launch_smp_gemm(st, la, rb, b1, ctr, 1, A + (size_t)sb * rb * L.elem, sto, 2LL * rb, V, rb,
-                      Wb + (size_t)sb * la, 2 * la);
-    launch_smp_gemm(st, la, la, 2 * b1, ctr, 2, E(q), 0, la, Wb, la, Yb, la);
+    ZgemmArgs w{la, b1, rb, A, 2LL * rb, V, rb, Wb, 2LL * la, ctr, 1};
+    w.batch = 2;  // s = 0, 1: rows s of the site, columns 2j+s of W
+    w.za = rb;
+    w.zc = la;
+    launch_zgemm(st, ZGEMM_NN_COL, w, sto, 0);
+    launch_zgemm(st, ZGEMM_NN_COL,
+                 ZgemmArgs{la, 2 * b1, la, E(q), la, Wb, la, Yb, la, ctr, 2}, 0, 0);
     launch_smp_prob(st, Wb, Yb, la, 2 * b1, ctr, p);
     launch_smp_decide(st, shots, n, q, dev_u, p, node, key, flag, dev_bits, logp, ctr + 1);
     launch_smp_scan(st, flag, idx, ctr);

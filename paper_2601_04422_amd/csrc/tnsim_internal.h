@@ -173,12 +173,40 @@ void launch_gemm_cn(hipStream_t st, int M, int N, int K, const void *A, int lda,
                     const double2 *B, int ldb, double2 *C, int ldc);
 void launch_pauli_phys(hipStream_t st, const double2 *F, double2 *F2, int chiA, int chiB,
                        double2 p00, double2 p01, double2 p10, double2 p11);
+// complex float64 GEMM on the matrix cores (k_zgemm.hip): C (M x N) = op(A) B
+// with op(A) M x K.  N is capped at mult * *mcount when mcount is not null
+// (a count that earlier kernels left on the device; the grid covers N).
+struct ZgemmArgs {
+  int M, N, K;
+  const void *A;
+  long long sa;
+  const void *B;
+  long long sb;
+  double2 *C;
+  long long sc;
+  const int *mcount;
+  int mult;
+  int batch = 1;              // independent products, operands offset by z * (za, zb, zc)
+  long long za = 0, zb = 0, zc = 0;
+  int ksplit = 1;             // K split over workgroups (batch 1 only); the partial products
+  double2 *part = nullptr;    // go to part (ksplit x M x N) and are added in order into C
+  int kchunk = 0;             // K per split (set by the launcher)
+};
+// ksplit that gives a product of this shape about 1024 workgroups (1 if none
+// needed); ksplit * M * N never exceeds ZGEMM_PART_ELEMS when it is above 1
+int zgemm_ksplit(int M, int N, int K);
+constexpr size_t ZGEMM_PART_ELEMS = (size_t)1024 * 64 * 64;
+enum ZgemmKind {
+  ZGEMM_NN_ROW,  // A(i,k) = A[i*sa + k]; B(k,j) = B[k*sb + j]; C(i,j) = C[i*sc + j]
+  ZGEMM_CN_ROW,  // op(A)(i,k) = conj(A[k*sa + i]); B, C as above
+  ZGEMM_NN_COL,  // A(i,k) = A[i*sa + k]; B(k,j) = B[j*sb + k]; C(i,j) = C[j*sc + i]
+};
+void launch_zgemm(hipStream_t st, ZgemmKind kind, const ZgemmArgs &g, int a_storage,
+                  int b_storage);
+
 // perfect sampling (k_sample.hip)
 void launch_smp_init(hipStream_t st, int shots, int *node, double *logp, int *flag, double2 *V,
                      double2 *E0, int *ctr);
-void launch_smp_gemm(hipStream_t st, int M, int K, int bound, const int *mcount, int mult,
-                     const void *A, int a_storage, long long lda, const double2 *B, int ldb,
-                     double2 *C, int ldc);
 void launch_smp_prob(hipStream_t st, const double2 *W, const double2 *Y, int M, int bound,
                      const int *mcount, double *p);
 void launch_smp_decide(hipStream_t st, int shots, int n, int q, const double *u, const double *p,

@@ -109,3 +109,29 @@ def test_gate_beyond_qr_rows_vs_oracle(T):
     pg = _block(m.site(i), m.site(i + 1))
     po = _block(o.site(i), o.site(i + 1))
     assert np.linalg.norm(pg - po) / np.linalg.norm(po) < tol
+
+
+def test_sampling_full_size_vs_oracle_amplitudes(T):
+    """Perfect sampling at chi = 1024 (n = 24, the middle bonds at 1024,
+    complex128 sites) with 1000 shots (a ragged last column tile): every drawn
+    string's log-probability equals log |<x|psi>|^2 from the oracle's
+    amplitude contraction of the same state (norm 1 to rounding: the sites
+    are float64 isometries), and the strings are those of the same draw split
+    over two calls."""
+    import math
+
+    dims, sites, lams = _state(1024, 2031)
+    m = T.MPS(N_SITES, 1024)
+    m.import_state(sites, lams)
+    o = O.OracleMPS(N_SITES, 1024)
+    o.set_state([m.site(q) for q in range(N_SITES)], [m.lam(b) for b in range(N_SITES - 1)])
+    u = np.random.default_rng(2032).random((1000, N_SITES))
+    bits, logp = m.sample(u)
+    bits, logp = bits.cpu().numpy(), logp.cpu().numpy()
+    assert len({tuple(b) for b in bits}) == 1000
+    for i in range(0, 1000, 37):
+        ref = math.log(abs(o.amplitude(bits[i])) ** 2)
+        assert abs(logp[i] - ref) < 1e-9, (i, logp[i], ref)
+    b2, l2 = m.sample(u[500:])
+    assert np.array_equal(b2.cpu().numpy(), bits[500:])
+    assert np.max(np.abs(l2.cpu().numpy() - logp[500:])) < 1e-12
