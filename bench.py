@@ -432,6 +432,16 @@ def bench_sample(args):
     lp = logp.cpu().numpy()
     nrm = m.norm2()
     err = max(abs(lp[i] - math.log(abs(m.amplitude(b[i])) ** 2 / nrm)) for i in range(8))
+    # algorithmic float64 work of one call (8 flops per complex multiply-add):
+    # environments 4 chi^3 per site, node products 4 chi_L chi_R m_q and
+    # 4 chi_L^2 m_q per site with m_q the distinct suffixes drawn so far
+    d = [1] + [int(x) for x in m.bond_dims()] + [1]
+    env = sum(8.0 * (d[q] ** 2 * 2 * d[q + 1] + 2 * d[q] * d[q + 1] ** 2) for q in range(n - 1))
+    nw = ny = 0.0
+    for q in range(n - 1, -1, -1):
+        mq = len({r.tobytes() for r in b[:, q + 1:]}) if q + 1 < n else 1
+        nw += 8.0 * 2 * d[q] * d[q + 1] * mq
+        ny += 8.0 * d[q] ** 2 * 2 * mq
     return {"metric": "shots/s, perfect sampling of all 100 qubits at chi=1024",
             "value": S / dt, "unit": "shots/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": 1e3 * dt, "higher_is_better": True,
@@ -439,6 +449,8 @@ def bench_sample(args):
             "config": {"workload": f"benchmark circuit state after {args.prep_layers} layers "
                                    f"({args.precision}, {args.storage}), {S} shots per call"},
             "distinct_strings": int(len({tuple(r) for r in b})),
+            "flops_per_call": {"environments": env, "node_products": nw, "node_weights": ny},
+            "tflops_per_s": (env + nw + ny) / dt / 1e12,
             "max_abs_logp_err_vs_amplitude": err}
 
 
