@@ -142,7 +142,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=16)
     ap.add_argument("--workload", default="chi1024",
-                    choices=["chi1024", "wide", "ansatz", "batch", "nonlocal", "sample"],
+                    choices=["chi1024", "wide", "ansatz", "batch", "nonlocal", "sample", "qasm"],
                     help="chi1024: the headline metric; the others measure the secondary "
                          "workloads (one JSON line each)")
     return ap.parse_args()
@@ -454,6 +454,51 @@ def bench_sample(args):
             "max_abs_logp_err_vs_amplitude": err}
 
 
+def bench_qasm(args):
+    """A circuit read from OpenQASM: 20 Trotter steps of a Heisenberg chain
+    on 64 qubits (rxx, ryy, rzz on every bond, then rz fields), chi_max=256,
+    cutoff 1e-10, through the dependency scheduler, as parsed and after gate
+    fusion (three two-qubit gates per bond and step become one)."""
+    import torch
+
+    from paper_2601_04422_amd import tnsim as T
+    from paper_2601_04422_amd import workloads as W
+
+    n, chi = 64, 256
+    text = W.heisenberg_qasm(n, 20)
+    t0 = time.perf_counter()
+    nq, gates = T.parse_qasm(text)
+    t_parse = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    fused = T.fuse(gates, nq)
+    t_fuse = time.perf_counter() - t0
+    res = {}
+    for name, circ in (("parsed", gates), ("fused", fused)):
+        m = T.MPS(n, chi, 1e-10, precision=args.precision, storage=args.storage)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m.run_circuit(circ)
+        torch.cuda.synchronize()
+        res[name] = (m, time.perf_counter() - t0, sum(1 for g in circ if g[1] >= 0))
+        log(f"{name}: {res[name][2]} two-qubit gates, {res[name][1]:.2f} s, "
+            f"max chi {int(max(m.bond_dims()))}")
+    a, b = res["parsed"][0], res["fused"][0]
+    fid = abs(a.overlap(b)) ** 2 / (a.norm2() * b.norm2())
+    n2q = res["parsed"][2]
+    return {"metric": "circuit 2q gates/s, 64-qubit Heisenberg Trotter circuit from OpenQASM, fused",
+            "value": n2q / res["fused"][1], "unit": "2q gates/s (of the parsed circuit)",
+            "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": 1e3 * res["fused"][1],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": f"{args.precision} contraction, f64 svd", "data": "synthetic",
+            "config": {"workload": f"heisenberg n={n}, 20 steps, dt=0.1, chi_max={chi}, "
+                                   f"cutoff 1e-10, {args.storage}"},
+            "parse_ms": 1e3 * t_parse, "fuse_ms": 1e3 * t_fuse,
+            "two_qubit_gates": {"parsed": n2q, "fused": res["fused"][2]},
+            "seconds": {"parsed": res["parsed"][1], "fused": res["fused"][1]},
+            "fused_vs_parsed_1_minus_F": 1 - fid,
+            "max_bond": int(max(b.bond_dims()))}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -462,7 +507,8 @@ def main():
         sys.exit(2)
     if args.workload != "chi1024":
         fn = {"wide": bench_wide, "ansatz": bench_ansatz, "batch": bench_batch,
-              "nonlocal": bench_nonlocal, "sample": bench_sample}[args.workload]
+              "nonlocal": bench_nonlocal, "sample": bench_sample,
+              "qasm": bench_qasm}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return
     import torch

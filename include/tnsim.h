@@ -301,6 +301,38 @@ tnsim_status tnsim_profile_read(tnsim_mps mps, tnsim_kernel_stat *out);
 #define TNSIM_TUNE_BUCKETS 4
 tnsim_status tnsim_autotune(tnsim_mps mps, int32_t *table_out);
 
+/* ---- circuit front end (host only; no device work) ----
+   OpenQASM 2.0 text -> one- and two-qubit gates (Sec. III: the simulator's
+   input is OpenQASM).  Read: OPENQASM 2.x; include (the standard gate
+   library is built in); qreg/creg (qubits numbered in declaration order);
+   gate definitions with parameters; parameter expressions (+ - * / ^, pi,
+   sin cos tan exp ln sqrt); whole-register arguments broadcast; barrier and
+   measure are skipped (all qubits are sampled after the circuit); opaque,
+   reset and if are rejected.  Built-in gates: id x y z h s sdg t tdg sx sxdg
+   rx ry rz p u1 u2 u3 u U, cx CX cy cz ch csx crx cry crz cp cu1 cu3 cu swap
+   rxx ryy rzz, and ccx cswap as six-CNOT decompositions.  Matrices: U(t,p,l)
+   = [[cos t/2, -e^{il} sin t/2], [e^{ip} sin t/2, e^{i(p+l)} cos t/2]],
+   R_P(t) = exp(-i t P/2), p(l) = diag(1, e^{il}), controlled gates control
+   on their first qubit; a two-qubit matrix has row 2*s_q0 + s_q1.
+   gates: host array of cap entries; *n_gates receives the count (also when
+   it exceeds cap: then TNSIM_E_CAPACITY and nothing is written).
+   *n_qubits: total qubits of all qregs.  Syntax or semantic errors give
+   TNSIM_E_ARG with a message (line number first) in err (err_len bytes,
+   may be NULL). */
+tnsim_status tnsim_qasm_parse(const char *text, tnsim_gate *gates, int32_t cap, int32_t *n_gates,
+                              int32_t *n_qubits, char *err, int32_t err_len);
+/* Gate fusion (Sec. IV.A: sequential gates that share qubits are compressed
+   so that fewer contractions are needed), in one pass over the circuit:
+   a one-qubit gate is multiplied into the last two-qubit gate on its qubit
+   (if there is one) or held until the next two-qubit gate on its qubit,
+   which takes it; a two-qubit gate whose two qubits were last touched by
+   one earlier two-qubit gate on the same pair is multiplied into that gate;
+   one-qubit gates never followed by a two-qubit gate are emitted at the end,
+   one per qubit.  The fused circuit is the same unitary.  out needs room for
+   n_in gates (the result never has more); qubits must be < n_qubits. */
+tnsim_status tnsim_fuse(const tnsim_gate *in, int32_t n_in, int32_t n_qubits, tnsim_gate *out,
+                        int32_t *n_out);
+
 const char *tnsim_status_string(tnsim_status st);
 const char *tnsim_last_error(tnsim_mps mps);
 

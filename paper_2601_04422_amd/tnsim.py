@@ -79,6 +79,9 @@ _SIGS = {
     "tnsim_profile": (C.c_int, [_P, C.c_int32]),
     "tnsim_profile_read": (C.c_int, [_P, _P]),
     "tnsim_autotune": (C.c_int, [_P, _P]),
+    "tnsim_qasm_parse": (C.c_int, [C.c_char_p, _P, C.c_int32, C.POINTER(C.c_int32),
+                                   C.POINTER(C.c_int32), C.c_char_p, C.c_int32]),
+    "tnsim_fuse": (C.c_int, [_P, C.c_int32, C.c_int32, _P, C.POINTER(C.c_int32)]),
     "tnsim_status_string": (C.c_char_p, [C.c_int]),
     "tnsim_last_error": (C.c_char_p, [_P]),
 }
@@ -124,6 +127,42 @@ def pack_gates(gates: Sequence) -> np.ndarray:
         arr[k]["q1"] = q1
         arr[k]["m"] = _c128_array(m, 16)
     return arr
+
+
+def unpack_gates(arr: np.ndarray) -> List:
+    """array of tnsim_gate -> [(q0, q1, matrix), ...] (2x2 or 4x4 complex)."""
+    out = []
+    for g in arr:
+        m = np.array(g["m"], dtype=np.complex128)
+        q0, q1 = int(g["q0"]), int(g["q1"])
+        out.append((q0, q1, m[:4].reshape(2, 2).copy() if q1 < 0 else m.reshape(4, 4).copy()))
+    return out
+
+
+def parse_qasm(text: str):
+    """OpenQASM 2.0 text -> (n_qubits, [(q0, q1, matrix), ...]) (tnsim_qasm_parse)."""
+    b = text.encode()
+    n, nq = C.c_int32(), C.c_int32()
+    err = C.create_string_buffer(512)
+    st = lib().tnsim_qasm_parse(b, None, 0, C.byref(n), C.byref(nq), err, 512)
+    if st not in (OK, E_CAPACITY):
+        raise TnsimError(st, "qasm_parse", err.value.decode())
+    arr = np.zeros(max(n.value, 1), dtype=GATE_DTYPE)
+    st = lib().tnsim_qasm_parse(b, arr.ctypes.data, arr.size, C.byref(n), C.byref(nq), err, 512)
+    if st != OK:
+        raise TnsimError(st, "qasm_parse", err.value.decode())
+    return nq.value, unpack_gates(arr[: n.value])
+
+
+def fuse(gates: Sequence, n_qubits: int) -> List:
+    """Gate fusion (tnsim_fuse): the same unitary in fewer gates."""
+    arr = pack_gates(gates)
+    out = np.zeros(max(len(gates), 1), dtype=GATE_DTYPE)
+    n = C.c_int32()
+    st = lib().tnsim_fuse(arr.ctypes.data, len(gates), n_qubits, out.ctypes.data, C.byref(n))
+    if st != OK:
+        raise TnsimError(st, "fuse")
+    return unpack_gates(out[: n.value])
 
 
 def apply_layer_multi(mpss: Sequence["MPS"], layers: Sequence[Sequence]) -> int:

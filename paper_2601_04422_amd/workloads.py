@@ -271,3 +271,25 @@ def random_canonical_mps(n: int, dims: Sequence[int], seed: int,
 def saturated_dims(n: int, chi_max: int) -> List[int]:
     """Largest left-canonical bond dimensions: min(chi_max, 2^q, 2^(n-q))."""
     return [min(chi_max, 2 ** min(q, n - q)) for q in range(n + 1)]
+
+
+# ---------------------------------------------------------------- circuits as OpenQASM text
+
+def heisenberg_qasm(n: int, steps: int, dt: float = 0.1, seed: int = 1007) -> str:
+    """First-order Trotter steps of a Heisenberg chain with random fields:
+    per step rxx, ryy, rzz(2 dt) on every bond (even bonds, then odd) and
+    rz(2 dt h_q) on every qubit, h_q uniform in [-1, 1]; starts from the Neel
+    state (x on odd qubits).  Three two-qubit gates per bond and step, which
+    fusion merges into one."""
+    rng = np.random.default_rng(seed)
+    h = rng.uniform(-1.0, 1.0, n)
+    out = ['OPENQASM 2.0;', 'include "qelib1.inc";', f"qreg q[{n}];", f"creg c[{n}];"]
+    out += [f"x q[{q}];" for q in range(1, n, 2)]
+    for _ in range(steps):
+        for start in (0, 1):
+            for j in range(start, n - 1, 2):
+                for g in ("rxx", "ryy", "rzz"):
+                    out.append(f"{g}({2 * dt!r}) q[{j}], q[{j + 1}];")
+        out += [f"rz({float(2 * dt * h[q])!r}) q[{q}];" for q in range(n)]
+    out.append("measure q -> c;")
+    return "\n".join(out) + "\n"
