@@ -170,7 +170,8 @@ int zgemm_ksplit(int M, int N, int K) {
 
 template <bool AK, bool AC, bool BK, bool CM>
 static void zgemm_dispatch(hipStream_t st, ZgemmArgs g, int a_storage, int b_storage) {
-  if (g.mcount) g.ksplit = 1;  // the partial sums cover the whole bound
+  // the partial sums cover the whole bound, and must fit the caller's buffer
+  if (g.mcount || !g.part || (size_t)g.ksplit * g.M * g.N > ZGEMM_PART_ELEMS) g.ksplit = 1;
   if (g.ksplit > 1) {
     g.batch = 1;
     g.kchunk = ((g.K + g.ksplit - 1) / g.ksplit + ZK - 1) / ZK * ZK;

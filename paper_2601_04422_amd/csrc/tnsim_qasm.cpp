@@ -191,7 +191,15 @@ struct Parser {
     }
     return b;
   }
+  int nest = 0;  // expression nesting, bounded so that a hostile text cannot exhaust the stack
   double unary(const std::map<std::string, double> &env) {
+    struct Guard {
+      int &n;
+      Guard(int &x, int line) : n(x) {
+        if (++n > 256) fail_at(line, "expression nested too deeply");
+      }
+      ~Guard() { n--; }
+    } guard(nest, peek().line);
     if (is_sym("-")) {
       i++;
       return -unary(env);

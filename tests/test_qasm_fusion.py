@@ -182,6 +182,10 @@ def test_definitions_exact_phases():
     ("qreg q[2];\nqreg r[3];\ncx q, r;", "different sizes"),
     ("qreg q[2];\nrx(theta) q[0];", "unknown parameter"),
     ("qreg q[2];\nh q[0]; @", "unexpected character"),
+    ("qreg q[1];\nrx(" + "(" * 400 + "1" + ")" * 400 + ") q[0];", "nested too deeply"),
+    ("qreg q[1];\ngate g a { g a; }\ng q[0];", "nested too deeply"),
+    ("qreg q[1];\nopaque g a;", "not supported"),
+    ("OPENQASM 3.0;\nqreg q[1];", "OpenQASM 2"),
 ])
 def test_errors(text, msg):
     with pytest.raises(T.TnsimError) as e:
