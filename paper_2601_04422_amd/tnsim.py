@@ -408,6 +408,16 @@ class MPS:
                   "sample")
         return bits, logp
 
+    def sample_counts(self, u) -> dict:
+        """The drawn strings as a histogram {bit string: count}, the string
+        written qubit 0 first (the form in which the paper reports shots)."""
+        bits, _ = self.sample(u)
+        b = bits.cpu().numpy()
+        if b.shape[0] == 0:
+            return {}
+        rows, counts = np.unique(b, axis=0, return_counts=True)
+        return {"".join("01"[int(x)] for x in r): int(c) for r, c in zip(rows, counts)}
+
     def sweep_stats(self) -> dict:
         g, sm = C.c_int64(), C.c_int64()
         mx = C.c_int32()

@@ -173,3 +173,15 @@ def test_sampling_errors(T):
     # the handle still works after the errors
     bits, _ = m.sample(np.random.default_rng(3).random((5, n)))
     assert bits.shape == (5, n)
+
+
+def test_sample_counts_histogram(T):
+    """GHZ on 8 qubits: 3000 shots give only the two strings, in proportions
+    within sampling noise of 1/2, and the counts add up to the shots."""
+    n = 8
+    m = T.MPS(n, 4)
+    m.run_gates(W.ghz(n))
+    counts = m.sample_counts(np.random.default_rng(11).random((3000, n)))
+    assert set(counts) == {"0" * n, "1" * n}
+    assert sum(counts.values()) == 3000
+    assert abs(counts["0" * n] / 3000 - 0.5) < 0.04
