@@ -433,15 +433,16 @@ def bench_sample(args):
     nrm = m.norm2()
     err = max(abs(lp[i] - math.log(abs(m.amplitude(b[i])) ** 2 / nrm)) for i in range(8))
     # algorithmic float64 work of one call (8 flops per complex multiply-add):
-    # environments 4 chi^3 per site, node products 4 chi_L chi_R m_q and
-    # 4 chi_L^2 m_q per site with m_q the distinct suffixes drawn so far
+    # per-site weights M_q^s = A_q^{sH} E_q A_q^s (4 chi^3), node weights
+    # [M^0; M^1] V (2 chi_R^2 m_q) and next nodes A^s v (chi_L chi_R m'_q), with
+    # m_q the distinct suffixes before drawing qubit q and m'_q after
     d = [1] + [int(x) for x in m.bond_dims()] + [1]
-    env = sum(8.0 * (d[q] ** 2 * 2 * d[q + 1] + 2 * d[q] * d[q + 1] ** 2) for q in range(n - 1))
+    env = sum(8.0 * (d[q] ** 2 * 2 * d[q + 1] + 2 * d[q] * d[q + 1] ** 2) for q in range(n))
+    distinct = [len({r.tobytes() for r in b[:, q:]}) for q in range(n)] + [1]
     nw = ny = 0.0
     for q in range(n - 1, -1, -1):
-        mq = len({r.tobytes() for r in b[:, q + 1:]}) if q + 1 < n else 1
-        nw += 8.0 * 2 * d[q] * d[q + 1] * mq
-        ny += 8.0 * d[q] ** 2 * 2 * mq
+        ny += 8.0 * 2 * d[q + 1] ** 2 * distinct[q + 1]
+        nw += 8.0 * d[q] * d[q + 1] * distinct[q]
     return {"metric": "shots/s, perfect sampling of all 100 qubits at chi=1024",
             "value": S / dt, "unit": "shots/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": 1e3 * dt, "higher_is_better": True,

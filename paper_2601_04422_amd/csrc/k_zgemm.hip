@@ -27,11 +27,30 @@ constexpr int ZT = 64, ZK = 16;
 // BK: B(k,j) = B[j*sb + k], else B[k*sb + j].
 // CM: C(i,j) = C[j*sc + i], else C[i*sc + j].
 // blockIdx.z: batch index, or K split (partial products to g.part).
-template <class TA, class TB, bool AK, bool AC, bool BK, bool CM>
-__global__ __launch_bounds__(256) void k_zgemm(ZgemmArgs g) {
-  int N = g.N;
-  if (g.mcount) N = min(N, g.mult * *g.mcount);
-  const int j0 = blockIdx.x * ZT, i0 = blockIdx.y * ZT;
+// GA (gathered columns): output columns *g.clo .. *g.chi - 1 (device
+// values; the grid covers at most N of them), column j reads column
+// g.bmap[j] of B and is scaled by g.cscale[j]; tiles from column *g.asplit
+// on read A + g.za.
+template <class TA, class TB, bool AK, bool AC, bool BK, bool CM, bool GA>
+__global__ __launch_bounds__(256, AK ? 4 : 3) void k_zgemm(ZgemmArgs g) {
+  // XCD-aware tile order: workgroups are dealt to the 8 XCDs in turn, so
+  // workgroup L runs on XCD L % 8.  Each XCD gets a contiguous run of tiles
+  // in row-tile-major order, so the A rows of its tiles stay in its own L2.
+  const int nx = gridDim.x, ntile = gridDim.x * gridDim.y;
+  const int L = blockIdx.x + nx * blockIdx.y, xcd = L & 7, slot = L >> 3;
+  const int per = ntile >> 3, extra = ntile & 7;
+  const int t_lin = xcd * per + min(xcd, extra) + slot;
+  const int tx = t_lin % nx, ty = t_lin / nx;
+  int N = g.N, j0 = tx * ZT, A_off_tile = 0;
+  if (GA) {
+    const int lo = *g.clo;
+    N = *g.chi;
+    j0 += lo;
+    if (g.asplit && j0 >= *g.asplit) A_off_tile = 1;
+  } else if (g.mcount) {
+    N = min(N, g.mult * *g.mcount);
+  }
+  const int i0 = ty * ZT;
   if (j0 >= N) return;
   const int M = g.M, z = blockIdx.z;
   const TA *A = (const TA *)g.A;
@@ -42,7 +61,7 @@ __global__ __launch_bounds__(256) void k_zgemm(ZgemmArgs g) {
     kb = z * g.kchunk;
     K = min(g.K, kb + g.kchunk);
   } else {
-    A += z * g.za;
+    A += (z + A_off_tile) * g.za;
     B += z * g.zb;
     C += z * g.zc;
   }
@@ -74,8 +93,9 @@ __global__ __launch_bounds__(256) void k_zgemm(ZgemmArgs g) {
         gj = j0 + bc + q;
         gk = k0 + br;
       }
+      const long long bj = GA ? (long long)(gj < N ? g.bmap[gj] : 0) : gj;
       rb[q] = (gj < N && gk < K)
-                  ? cload(B + (BK ? (long long)gj * g.sb + gk : (long long)gk * g.sb + gj))
+                  ? cload(B + (BK ? bj * g.sb + gk : (long long)gk * g.sb + bj))
                   : make_double2(0.0, 0.0);
     }
   };
@@ -134,11 +154,12 @@ __global__ __launch_bounds__(256) void k_zgemm(ZgemmArgs g) {
     for (int y = 0; y < 2; y++) {
       const int j = j0 + wn + 16 * y + l16;
       if (j >= N) continue;
+      const double sc = GA ? g.cscale[j] : 1.0;
 #pragma unroll
       for (int v = 0; v < 4; v++) {
         const int i = i0 + wm + 16 * x + lg + 4 * v;
         if (i >= M) continue;
-        const double2 c = make_double2(cr[x][y][v], ci[x][y][v]);
+        const double2 c = make_double2(sc * cr[x][y][v], sc * ci[x][y][v]);
         if (g.ksplit > 1)
           g.part[((size_t)z * M + i) * g.N + j] = c;
         else
@@ -168,10 +189,10 @@ int zgemm_ksplit(int M, int N, int K) {
   return ks;
 }
 
-template <bool AK, bool AC, bool BK, bool CM>
+template <bool AK, bool AC, bool BK, bool CM, bool GA = false>
 static void zgemm_dispatch(hipStream_t st, ZgemmArgs g, int a_storage, int b_storage) {
   // the partial sums cover the whole bound, and must fit the caller's buffer
-  if (g.mcount || !g.part || (size_t)g.ksplit * g.M * g.N > ZGEMM_PART_ELEMS) g.ksplit = 1;
+  if (GA || g.mcount || !g.part || (size_t)g.ksplit * g.M * g.N > ZGEMM_PART_ELEMS) g.ksplit = 1;
   if (g.ksplit > 1) {
     g.batch = 1;
     g.kchunk = ((g.K + g.ksplit - 1) / g.ksplit + ZK - 1) / ZK * ZK;
@@ -179,13 +200,13 @@ static void zgemm_dispatch(hipStream_t st, ZgemmArgs g, int a_storage, int b_sto
   }
   dim3 grid((g.N + ZT - 1) / ZT, (g.M + ZT - 1) / ZT, g.ksplit > 1 ? g.ksplit : g.batch);
   if (a_storage == 0 && b_storage == 0)
-    hipLaunchKernelGGL((k_zgemm<double2, double2, AK, AC, BK, CM>), grid, dim3(256), 0, st, g);
+    hipLaunchKernelGGL((k_zgemm<double2, double2, AK, AC, BK, CM, GA>), grid, dim3(256), 0, st, g);
   else if (a_storage == 0)
-    hipLaunchKernelGGL((k_zgemm<double2, float2, AK, AC, BK, CM>), grid, dim3(256), 0, st, g);
+    hipLaunchKernelGGL((k_zgemm<double2, float2, AK, AC, BK, CM, GA>), grid, dim3(256), 0, st, g);
   else if (b_storage == 0)
-    hipLaunchKernelGGL((k_zgemm<float2, double2, AK, AC, BK, CM>), grid, dim3(256), 0, st, g);
+    hipLaunchKernelGGL((k_zgemm<float2, double2, AK, AC, BK, CM, GA>), grid, dim3(256), 0, st, g);
   else
-    hipLaunchKernelGGL((k_zgemm<float2, float2, AK, AC, BK, CM>), grid, dim3(256), 0, st, g);
+    hipLaunchKernelGGL((k_zgemm<float2, float2, AK, AC, BK, CM, GA>), grid, dim3(256), 0, st, g);
   if (g.ksplit > 1) {
     const size_t MN = (size_t)g.M * g.N;
     hipLaunchKernelGGL(k_zgemm_sum<CM>, dim3((unsigned)((MN + 255) / 256)), dim3(256), 0, st, g);
@@ -204,6 +225,10 @@ void launch_zgemm(hipStream_t st, ZgemmKind kind, const ZgemmArgs &g, int a_stor
       break;
     case ZGEMM_NN_COL:  // C = A B, A k-contiguous, B and C column-major
       zgemm_dispatch<true, false, true, true>(st, g, a_storage, b_storage);
+      break;
+    case ZGEMM_NN_COL_GATHER:  // the same on gathered, scaled columns
+      if (g.clo && g.chi && g.bmap && g.cscale)
+        zgemm_dispatch<true, false, true, true, true>(st, g, a_storage, b_storage);
       break;
   }
 }

@@ -1800,12 +1800,13 @@ tnsim_status tnsim_amplitude(tnsim_mps h, const uint8_t *bits, tnsim_c128 *out) 
   return TNSIM_OK;
 }
 
-// Workspace of tnsim_sample: the left-block Gram matrices E_q of every site
-// and the node tables of one step (see k_sample.hip).
+// Workspace of tnsim_sample: per site the stacked weights [M_q^0; M_q^1]
+// (M_q^s = A_q^{sH} E_q A_q^s), and the node tables of one step (see
+// k_sample.hip).
 struct SampleLayout {
-  std::vector<size_t> env;  // E_q, dimcap[q]^2 complex128
-  size_t F = 0, P = 0, V0 = 0, V1 = 0, W = 0, Y = 0, p = 0, flag = 0, idx = 0, node = 0,
-         key = 0, logp = 0, ctr = 0, total = 0;
+  std::vector<size_t> msite;  // 2 x dimcap[q+1]^2 complex128 per site
+  size_t E0 = 0, E1 = 0, F = 0, P = 0, V0 = 0, V1 = 0, Y = 0, p = 0, flag = 0, idx = 0,
+         node = 0, key = 0, parent = 0, scale = 0, logp = 0, ctr = 0, total = 0;
 };
 
 static SampleLayout sample_layout(const Layout &L, int max_shots) {
@@ -1813,39 +1814,34 @@ static SampleLayout sample_layout(const Layout &L, int max_shots) {
   const int n = L.n;
   int dmax = 1;
   for (int q = 0; q <= n; q++) dmax = std::max(dmax, L.dimcap[q]);
-  const size_t ms = (size_t)std::max(max_shots, 1);
+  // node tables: at most one node per distinct drawn suffix (<= shots) plus
+  // fewer than 64 zero nodes that align the bit-1 nodes to a column tile
+  const size_t ms = (size_t)std::max(max_shots, 1) + 64, d2 = (size_t)dmax * dmax;
   size_t off = 0;
-  S.env.resize(n);
-  for (int q = 0; q < n; q++) {
-    S.env[q] = off;
-    off = align_up(off + sizeof(double2) * (size_t)L.dimcap[q] * L.dimcap[q]);
-  }
-  S.F = off;
-  off = align_up(off + sizeof(double2) * (size_t)dmax * 2 * dmax);
-  S.P = off;  // split-K partial products of the environment GEMMs
-  off = align_up(off + sizeof(double2) * ZGEMM_PART_ELEMS);
-  S.V0 = off;
-  off = align_up(off + sizeof(double2) * ms * dmax);
-  S.V1 = off;
-  off = align_up(off + sizeof(double2) * ms * dmax);
-  S.W = off;
-  off = align_up(off + sizeof(double2) * 2 * ms * dmax);
-  S.Y = off;
-  off = align_up(off + sizeof(double2) * 2 * ms * dmax);
-  S.p = off;
-  off = align_up(off + sizeof(double) * 2 * ms);
-  S.flag = off;
-  off = align_up(off + sizeof(int) * (2 * ms + 1));
-  S.idx = off;
-  off = align_up(off + sizeof(int) * (2 * ms + 1));
-  S.node = off;
-  off = align_up(off + sizeof(int) * ms);
-  S.key = off;
-  off = align_up(off + sizeof(int) * ms);
-  S.logp = off;
-  off = align_up(off + sizeof(double) * ms);
-  S.ctr = off;
-  off = align_up(off + sizeof(int) * 4);
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  S.msite.resize(n);
+  for (int q = 0; q < n; q++)
+    S.msite[q] = take(sizeof(double2) * 2 * (size_t)L.dimcap[q + 1] * L.dimcap[q + 1]);
+  S.E0 = take(sizeof(double2) * d2);  // E_q, E_{q+1} in turn
+  S.E1 = take(sizeof(double2) * d2);
+  S.F = take(sizeof(double2) * 2 * d2);
+  S.P = take(sizeof(double2) * ZGEMM_PART_ELEMS);  // split-K partial products
+  S.V0 = take(sizeof(double2) * ms * dmax);
+  S.V1 = take(sizeof(double2) * ms * dmax);
+  S.Y = take(sizeof(double2) * 2 * ms * dmax);
+  S.p = take(sizeof(double) * 2 * ms);
+  S.flag = take(sizeof(int) * (2 * ms + 1));
+  S.idx = take(sizeof(int) * (2 * ms + 1));
+  S.node = take(sizeof(int) * (ms - 64));
+  S.key = take(sizeof(int) * (ms - 64));
+  S.parent = take(sizeof(int) * ms);
+  S.scale = take(sizeof(double) * ms);
+  S.logp = take(sizeof(double) * (ms - 64));
+  S.ctr = take(sizeof(int) * 8);
   S.total = off;
   return S;
 }
@@ -1869,47 +1865,64 @@ tnsim_status tnsim_sample(tnsim_mps h, void *dev_ws, size_t ws_bytes, int32_t sh
   const int n = L.n, sto = L.storage;
   hipStream_t st = h->stream;
   char *ws = (char *)dev_ws;
-  auto E = [&](int q) { return (double2 *)(ws + S.env[q]); };
-  double2 *F = (double2 *)(ws + S.F), *V = (double2 *)(ws + S.V0), *Vn = (double2 *)(ws + S.V1);
-  double2 *Wb = (double2 *)(ws + S.W), *Yb = (double2 *)(ws + S.Y);
+  auto Ms = [&](int q) { return (double2 *)(ws + S.msite[q]); };
+  double2 *E = (double2 *)(ws + S.E0), *En = (double2 *)(ws + S.E1);
+  double2 *F = (double2 *)(ws + S.F), *Pb = (double2 *)(ws + S.P);
+  double2 *V = (double2 *)(ws + S.V0), *Vn = (double2 *)(ws + S.V1), *Yb = (double2 *)(ws + S.Y);
   double *p = (double *)(ws + S.p), *logp = (double *)(ws + S.logp);
+  double *scale = (double *)(ws + S.scale);
   int *flag = (int *)(ws + S.flag), *idx = (int *)(ws + S.idx), *node = (int *)(ws + S.node),
-      *key = (int *)(ws + S.key), *ctr = (int *)(ws + S.ctr);
-  launch_smp_init(st, shots, node, logp, flag, V, E(0), ctr);
-  // E_{q+1} = sum_s A_q^{s H} E_q A_q^s, as F = E_q A_q, then A_q^H F
-  double2 *Pb = (double2 *)(ws + S.P);
-  for (int q = 0; q + 1 < n; q++) {
+      *key = (int *)(ws + S.key), *parent = (int *)(ws + S.parent), *ctr = (int *)(ws + S.ctr);
+  const int cap = shots + 64;  // node-table columns (see sample_layout)
+  launch_smp_init(st, shots, cap, node, logp, flag, V, E, ctr);
+  // M_q^s = A_q^{sH} (E_q A_q^s): F = E_q A_q (rows (a, s)), then one product
+  // per s over the rows of that s; E_{q+1} = M_q^0 + M_q^1
+  for (int q = 0; q < n; q++) {
     const int la = h->dims[q], rb = h->dims[q + 1];
-    ZgemmArgs f{la, 2 * rb, la, E(q), la, h->site(q), 2 * rb, F, 2 * rb, nullptr, 0};
+    ZgemmArgs f{la, 2 * rb, la, E, la, h->site(q), 2 * rb, F, 2 * rb, nullptr, 0};
     f.ksplit = zgemm_ksplit(la, 2 * rb, la);
     f.part = Pb;
     launch_zgemm(st, ZGEMM_NN_ROW, f, 0, sto);
-    ZgemmArgs e{rb, rb, 2 * la, h->site(q), rb, F, rb, E(q + 1), rb, nullptr, 0};
-    e.ksplit = zgemm_ksplit(rb, rb, 2 * la);
-    e.part = Pb;
-    launch_zgemm(st, ZGEMM_CN_ROW, e, sto, 0);
+    for (int sb = 0; sb < 2; sb++) {
+      const char *A = (const char *)h->site(q) + (size_t)sb * rb * L.elem;
+      ZgemmArgs e{rb, rb, la, A, 2LL * rb, F + (size_t)sb * rb, 2LL * rb,
+                  Ms(q) + (size_t)sb * rb * rb, rb, nullptr, 0};
+      e.ksplit = zgemm_ksplit(rb, rb, la);
+      e.part = Pb;
+      launch_zgemm(st, ZGEMM_CN_ROW, e, sto, 0);
+    }
+    if (q + 1 < n) {
+      launch_smp_add(st, Ms(q), (size_t)rb * rb, En);
+      std::swap(E, En);
+    }
   }
-  LAUNCHCHK(h, "sample environments");
+  LAUNCHCHK(h, "sample weights");
   long long mb = 1;  // bound on the node count before the step
   for (int q = n - 1; q >= 0; q--) {
     const int la = h->dims[q], rb = h->dims[q + 1];
-    const int b1 = (int)std::min<long long>(mb, shots);
-    const char *A = (const char *)h->site(q);
-    ZgemmArgs w{la, b1, rb, A, 2LL * rb, V, rb, Wb, 2LL * la, ctr, 1};
-    w.batch = 2;  // s = 0, 1: rows s of the site, columns 2j+s of W
-    w.za = rb;
-    w.zc = la;
-    launch_zgemm(st, ZGEMM_NN_COL, w, sto, 0);
-    launch_zgemm(st, ZGEMM_NN_COL,
-                 ZgemmArgs{la, 2 * b1, la, E(q), la, Wb, la, Yb, la, ctr, 2}, 0, 0);
-    launch_smp_prob(st, Wb, Yb, la, 2 * b1, ctr, p);
-    launch_smp_decide(st, shots, n, q, dev_u, p, node, key, flag, dev_bits, logp, ctr + 1);
+    const int b1 = (int)std::min<long long>(mb, cap);
+    const int b2 = (int)std::min<long long>(2LL * b1 + 64, cap);  // after the step
+    // Y = [M^0; M^1] V, then the weights of both bits of every node
+    launch_zgemm(st, ZGEMM_NN_COL, ZgemmArgs{2 * rb, b1, rb, Ms(q), rb, V, rb, Yb, 2LL * rb, ctr, 1},
+                 0, 0);
+    launch_smp_prob(st, V, Yb, rb, 2 * b1, ctr, p);
+    launch_smp_decide(st, shots, n, q, dev_u, p, node, key, flag, dev_bits, logp, ctr);
     launch_smp_scan(st, flag, idx, ctr);
-    launch_smp_gather(st, Wb, p, idx, ctr, 2 * b1, la, Vn);
+    launch_smp_parent(st, flag, idx, p, ctr, 2 * b1, parent, scale);
+    // next nodes: columns [0, ctr[4]) from bit 0, [ctr[4], ctr[0]) from bit 1
+    // (ctr[4] is a multiple of 64, so each column tile reads one row set of A)
+    ZgemmArgs w{la, b2, rb, h->site(q), 2LL * rb, V, rb, Vn, la, nullptr, 0};
+    w.za = rb;
+    w.clo = ctr + 5;
+    w.chi = ctr + 0;
+    w.asplit = ctr + 4;
+    w.bmap = parent;
+    w.cscale = scale;
+    launch_zgemm(st, ZGEMM_NN_COL_GATHER, w, sto, 0);
     launch_smp_relabel(st, shots, key, idx, node);
     LAUNCHCHK(h, "sample step");
     std::swap(V, Vn);
-    mb = std::min<long long>(2 * mb, shots);
+    mb = b2;
   }
   if (dev_logp)
     HIPCHK(h, hipMemcpyAsync(dev_logp, logp, sizeof(double) * shots, hipMemcpyDeviceToDevice, st));

@@ -191,6 +191,11 @@ struct ZgemmArgs {
   int ksplit = 1;             // K split over workgroups (batch 1 only); the partial products
   double2 *part = nullptr;    // go to part (ksplit x M x N) and are added in order into C
   int kchunk = 0;             // K per split (set by the launcher)
+  // ZGEMM_NN_COL_GATHER only: output columns [*clo, *chi) (device values, at
+  // most N of them); column j reads column bmap[j] of B, scaled by cscale[j];
+  // tiles of 64 columns from *asplit on (a multiple of 64) use A + za
+  const int *clo = nullptr, *chi = nullptr, *bmap = nullptr, *asplit = nullptr;
+  const double *cscale = nullptr;
 };
 // ksplit that gives a product of this shape about 1024 workgroups (1 if none
 // needed); ksplit * M * N never exceeds ZGEMM_PART_ELEMS when it is above 1
@@ -200,22 +205,24 @@ enum ZgemmKind {
   ZGEMM_NN_ROW,  // A(i,k) = A[i*sa + k]; B(k,j) = B[k*sb + j]; C(i,j) = C[i*sc + j]
   ZGEMM_CN_ROW,  // op(A)(i,k) = conj(A[k*sa + i]); B, C as above
   ZGEMM_NN_COL,  // A(i,k) = A[i*sa + k]; B(k,j) = B[j*sb + k]; C(i,j) = C[j*sc + i]
+  ZGEMM_NN_COL_GATHER,  // as NN_COL on gathered, scaled columns (see ZgemmArgs)
 };
 void launch_zgemm(hipStream_t st, ZgemmKind kind, const ZgemmArgs &g, int a_storage,
                   int b_storage);
 
 // perfect sampling (k_sample.hip)
-void launch_smp_init(hipStream_t st, int shots, int *node, double *logp, int *flag, double2 *V,
-                     double2 *E0, int *ctr);
-void launch_smp_prob(hipStream_t st, const double2 *W, const double2 *Y, int M, int bound,
-                     const int *mcount, double *p);
+void launch_smp_init(hipStream_t st, int shots, int node_cap, int *node, double *logp, int *flag,
+                     double2 *V, double2 *E0, int *ctr);
+void launch_smp_prob(hipStream_t st, const double2 *V, const double2 *Y, int M, int bound,
+                     const int *ctr, double *p);
 void launch_smp_decide(hipStream_t st, int shots, int n, int q, const double *u, const double *p,
                        const int *node, int *key, int *flag, uint8_t *bits, double *logp,
-                       int *err);
-void launch_smp_scan(hipStream_t st, int *flag, int *idx, int *ctr);
-void launch_smp_gather(hipStream_t st, const double2 *W, const double *p, const int *idx,
-                       const int *ctr, int bound, int M, double2 *Vn);
+                       int *ctr);
+void launch_smp_scan(hipStream_t st, const int *flag, int *idx, int *ctr);
+void launch_smp_parent(hipStream_t st, int *flag, const int *idx, const double *p, const int *ctr,
+                       int bound, int *parent, double *scale);
 void launch_smp_relabel(hipStream_t st, int shots, const int *key, const int *idx, int *node);
+void launch_smp_add(hipStream_t st, const double2 *M01, size_t n, double2 *E);
 void launch_amp_step(hipStream_t st, const double2 *v, double2 *w, const void *A, int storage,
                      int chiL, int chiR, int bit);
 
