@@ -67,3 +67,39 @@ def test_fused_heisenberg_vs_unfused_oracle(T, precision, storage, tol):
     o = O.run_gates(n, 64, 0.0, gates)
     f = mps_fidelity_gpu_vs_oracle(m, o, lambda k: O.OracleMPS(k, 4096))
     assert 1 - f < tol
+
+
+def test_parsed_fused_circuit_sampled_vs_oracle(T):
+    """The whole chain on one circuit: OpenQASM text (distant CNOTs and
+    controlled phases, Toffolis, rotations) parsed and fused, run through the
+    scheduler with truncation at chi = 16, then sampled; the draws equal the
+    oracle's on the same final state."""
+    n = 12
+    rng = np.random.default_rng(21)
+    lines = ['OPENQASM 2.0;', 'include "qelib1.inc";', f"qreg q[{n}];", f"creg c[{n}];"]
+    for _ in range(120):
+        kind = rng.integers(0, 5)
+        a, b, c = (int(x) for x in rng.choice(n, 3, replace=False))
+        if kind == 0:
+            lines.append(f"u3({rng.uniform(0, 3):.6f}, {rng.uniform(0, 6):.6f}, {rng.uniform(0, 6):.6f}) q[{a}];")
+        elif kind == 1:
+            lines.append(f"cp({rng.uniform(0, 6):.6f}) q[{a}], q[{b}];")
+        elif kind == 2:
+            lines.append(f"ccx q[{a}], q[{b}], q[{c}];")
+        elif kind == 3:
+            lines.append(f"cx q[{a}], q[{b}];")
+        else:
+            lines.append(f"rzz({rng.uniform(0, 6):.6f}) q[{a}], q[{b}];")
+    lines.append("measure q -> c;")
+    nq, gates = T.parse_qasm("\n".join(lines) + "\n")
+    fused = T.fuse(gates, nq)
+    m = T.MPS(n, 16, 1e-10)
+    m.run_circuit(fused)
+    assert max(m.bond_dims()) == 16  # truncated
+    o = O.OracleMPS(n, 4096)
+    o.set_state([m.site(q) for q in range(n)], [m.lam(b) for b in range(n - 1)])
+    u = rng.random((1500, n))
+    bits, logp = m.sample(u)
+    rbits, rlogp = o.sample(u)
+    assert np.array_equal(bits.cpu().numpy(), rbits)
+    assert np.max(np.abs(logp.cpu().numpy() - rlogp)) < 1e-10

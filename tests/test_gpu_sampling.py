@@ -47,7 +47,8 @@ def _compare(bits, logp, rbits, rlogp, tol=1e-10):
     assert np.max(np.abs(logp - rlogp)) < tol
 
 
-@pytest.mark.parametrize("precision,storage", [("fp64", "c128"), ("bf16x6", "c64")])
+@pytest.mark.parametrize("precision,storage", [("fp64", "c128"), ("bf16x6", "c64"),
+                                               ("bf16x3", "c64"), ("f32acc", "c64")])
 def test_sampling_vs_oracle(T, precision, storage):
     """A truncated random brickwork state (n=12, chi_max=32): 2000 shots."""
     n = 12
