@@ -407,18 +407,29 @@ __global__ __launch_bounds__(256) void k_qrg_s(const GateDesc *descs, int stage,
   const int l16 = lane & 15, lg = lane >> 4;
   const int tp = (wave >> 1) * 16, tc = (wave & 1) * 16;  // this wave's 16x16 tile of S
   qd4_t accR = {0.0, 0.0, 0.0, 0.0}, accI = {0.0, 0.0, 0.0, 0.0};
-  for (int r0 = rbeg; r0 < rend; r0 += 32) {
-    for (int e = tid; e < 32 * QG; e += 256) {
-      const int r = e % 32, p = e / 32;
-      Vs[r][p] = (r0 + r < rend) ? qr_vget(q, j0, w, r0 + r, p) : make_double2(0.0, 0.0);
+  // the next 32 rows of V and B are loaded into registers while the current
+  // ones are multiplied
+  static_assert(32 * QG == 4 * 256 && 32 * QGT == 4 * 256, "four elements per thread");
+  double2 vr[4], br[4];
+  auto load = [&](int r0) {
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const int e = tid + 256 * k, r = e % 32, p = e / 32;
+      vr[k] = (r0 + r < rend) ? qr_vget(q, j0, w, r0 + r, p) : make_double2(0.0, 0.0);
+      br[k] = (r0 + r < rend && c0 + p < t.ncols) ? t.B[(size_t)(c0 + p) * t.ldb + r0 + r]
+                                                  : make_double2(0.0, 0.0);
     }
-    for (int e = tid; e < 32 * QGT; e += 256) {
-      const int r = e % 32, cc = e / 32;
-      Bs[r][cc] = (r0 + r < rend && c0 + cc < t.ncols)
-                      ? t.B[(size_t)(c0 + cc) * t.ldb + r0 + r]
-                      : make_double2(0.0, 0.0);
+  };
+  load(rbeg);
+  for (int r0 = rbeg; r0 < rend; r0 += 32) {
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const int e = tid + 256 * k, r = e % 32, p = e / 32;
+      Vs[r][p] = vr[k];
+      Bs[r][p] = br[k];
     }
     __syncthreads();
+    if (r0 + 32 < rend) load(r0 + 32);
 #pragma unroll
     for (int kk = 0; kk < 32; kk += 4) {
       const double2 a = Vs[kk + lg][tp + l16];  // S = conj(V)^T B
@@ -503,13 +514,30 @@ __global__ __launch_bounds__(256) void k_qrg_b(const GateDesc *descs, int stage,
   __syncthreads();
   // (V Y)^T = Y^T V^T: tiles of 16 target columns x 16 rows; the wave's tiles
   // are column tile (wave & 1) and every other row tile of the chunk
+  // the next tile's V and B entries are loaded while the current tile is
+  // multiplied (row tiles of one wave never overlap those of another)
   const int tc = (wave & 1) * 16;
-  for (int rt = rbeg + (wave >> 1) * 16; rt < rend; rt += 32) {
+  double2 vc[QG / 4], bc[4];
+  auto load = [&](int rt, double2 *vv, double2 *bb) {
+#pragma unroll
+    for (int k = 0; k < QG / 4; k++) vv[k] = qr_vget(q, j0, w, rt + l16, 4 * k + lg);  // V^T[k][row]
+    const int r = rt + l16;
+#pragma unroll
+    for (int v = 0; v < 4; v++) {
+      const int c = c0 + tc + lg + 4 * v;
+      bb[v] = (r < rend && c < t.ncols) ? t.B[(size_t)c * t.ldb + r] : make_double2(0.0, 0.0);
+    }
+  };
+  int rt = rbeg + (wave >> 1) * 16;
+  if (rt < rend) load(rt, vc, bc);
+  for (; rt < rend; rt += 32) {
+    double2 vn[QG / 4], bn[4];
+    if (rt + 32 < rend) load(rt + 32, vn, bn);
     qd4_t accR = {0.0, 0.0, 0.0, 0.0}, accI = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int k0 = 0; k0 < QG; k0 += 4) {
-      const double2 a = Ys[k0 + lg][tc + l16];               // Y^T[col][k]
-      const double2 b = qr_vget(q, j0, w, rt + l16, k0 + lg);  // V^T[k][row]
+    for (int k = 0; k < QG / 4; k++) {
+      const double2 a = Ys[4 * k + lg][tc + l16];  // Y^T[col][k]
+      const double2 b = vc[k];
       accR = qmfma(a.x, b.x, accR);
       accR = qmfma(-a.y, b.y, accR);
       accI = qmfma(a.x, b.y, accI);
@@ -520,11 +548,15 @@ __global__ __launch_bounds__(256) void k_qrg_b(const GateDesc *descs, int stage,
 #pragma unroll
       for (int v = 0; v < 4; v++) {
         const int c = c0 + tc + lg + 4 * v;
-        if (c < t.ncols) {
-          double2 *bp = t.B + (size_t)c * t.ldb + r;
-          *bp = make_double2(bp->x - accR[v], bp->y - accI[v]);
-        }
+        if (c < t.ncols)
+          t.B[(size_t)c * t.ldb + r] = make_double2(bc[v].x - accR[v], bc[v].y - accI[v]);
       }
+    }
+    if (rt + 32 < rend) {
+#pragma unroll
+      for (int k = 0; k < QG / 4; k++) vc[k] = vn[k];
+#pragma unroll
+      for (int v = 0; v < 4; v++) bc[v] = bn[v];
     }
   }
 }
