@@ -88,3 +88,23 @@ def test_status_strings():
     lib = T.lib()
     for code in range(7):
         assert lib.tnsim_status_string(code)
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """No CPU fallback: without the built library the binding raises."""
+    monkeypatch.setattr(T, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "libtnsim.so"))
+    monkeypatch.setattr(T, "_lib", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        T.lib()
+
+
+def test_sample_workspace_bytes():
+    cfg = T.Config(100, 1024, 1e-12, 0, 1, 0, 0.0, 0, 1)
+    small = T.lib().tnsim_sample_workspace_bytes(C.byref(cfg), 16)
+    big = T.lib().tnsim_sample_workspace_bytes(C.byref(cfg), 4096)
+    assert 0 < small < big
+    # per-site weights (two chi x chi blocks per site) dominate at few shots
+    assert small > 2 * 16 * 1024 * 1024 * 70
+    assert T.lib().tnsim_sample_workspace_bytes(C.byref(cfg), 0) == 0
+    bad = T.Config(1, 1024, 1e-12, 0, 1, 0, 0.0, 0, 1)
+    assert T.lib().tnsim_sample_workspace_bytes(C.byref(bad), 16) == 0
