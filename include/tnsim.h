@@ -106,7 +106,8 @@ typedef struct {
 
 typedef struct {
   int32_t q0, q1;     /* q1 = -1 marks a one-qubit gate */
-  tnsim_c128 m[16];   /* 2x2 in m[0..3] (row-major) or 4x4 row-major */
+  tnsim_c128 m[16];   /* 2x2 in m[0..3] (row-major) or 4x4 row-major; every entry point
+                         that takes gate matrices rejects a non-finite entry (TNSIM_E_ARG) */
 } tnsim_gate;
 
 /* Bytes of device memory a handle with this configuration needs; 0 if the

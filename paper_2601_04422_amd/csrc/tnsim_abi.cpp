@@ -887,6 +887,14 @@ void expand_gate(const tnsim_gate &g, std::vector<tnsim_gate> &out) {
   }
 }
 
+// Gate matrices must be finite: a NaN or infinity would reach the SVD.
+bool finite_gate(const tnsim_c128 *m, int count) {
+  for (int k = 0; k < count; k++)
+    if (!std::isfinite(m[k].re) || !std::isfinite(m[k].im)) return false;
+  return true;
+}
+bool finite_gate(const tnsim_gate &g) { return finite_gate(g.m, g.q1 < 0 ? 4 : 16); }
+
 // Validate a layer; fills 1q and 2q lists.
 tnsim_status validate_layer(tnsim_mps h, const tnsim_gate *gates, int ng,
                             std::vector<std::pair<int, const tnsim_c128 *>> &g1,
@@ -896,7 +904,7 @@ tnsim_status validate_layer(tnsim_mps h, const tnsim_gate *gates, int ng,
   std::vector<char> used(n, 0);
   for (int k = 0; k < ng; k++) {
     int a = gates[k].q0, b = gates[k].q1;
-    if (a < 0 || a >= n || b < -1 || b >= n || a == b) return TNSIM_E_ARG;
+    if (a < 0 || a >= n || b < -1 || b >= n || a == b || !finite_gate(gates[k])) return TNSIM_E_ARG;
     if (b >= 0 && std::abs(a - b) != 1) return TNSIM_E_NONLOCAL;
     if (used[a] || (b >= 0 && used[b])) return TNSIM_E_OVERLAP;
     used[a] = 1;
@@ -1594,14 +1602,15 @@ tnsim_status tnsim_mps_reset(tnsim_mps h) {
 tnsim_status tnsim_apply_1q(tnsim_mps h, int32_t q, const tnsim_c128 u[4]) {
   tnsim_status s = check_handle(h);
   if (s != TNSIM_OK) return s;
-  if (!u || q < 0 || q >= h->L.n) return TNSIM_E_ARG;
+  if (!u || q < 0 || q >= h->L.n || !finite_gate(u, 4)) return TNSIM_E_ARG;
   return run_1q(h, {{q, u}});
 }
 
 tnsim_status tnsim_apply_2q(tnsim_mps h, int32_t q0, int32_t q1, const tnsim_c128 g[16]) {
   tnsim_status s = check_handle(h);
   if (s != TNSIM_OK) return s;
-  if (!g || q0 < 0 || q1 < 0 || q0 >= h->L.n || q1 >= h->L.n || q0 == q1) return TNSIM_E_ARG;
+  if (!g || q0 < 0 || q1 < 0 || q0 >= h->L.n || q1 >= h->L.n || q0 == q1 || !finite_gate(g, 16))
+    return TNSIM_E_ARG;
   h->last_sweeps = 0;
   h->last_batch.clear();
   if (std::abs(q0 - q1) != 1) {  // a SWAP chain, one local gate after the other
@@ -1640,7 +1649,7 @@ tnsim_status tnsim_apply_circuit(tnsim_mps h, const tnsim_gate *gates, int32_t n
   std::vector<tnsim_gate> local;
   for (int k = 0; k < n_gates; k++) {
     const int a = gates[k].q0, b = gates[k].q1;
-    if (a < 0 || a >= n || b < -1 || b >= n || a == b) return TNSIM_E_ARG;
+    if (a < 0 || a >= n || b < -1 || b >= n || a == b || !finite_gate(gates[k])) return TNSIM_E_ARG;
     expand_gate(gates[k], local);
   }
   h->last_sweeps = 0;
@@ -2108,6 +2117,8 @@ tnsim_status tnsim_forward_checkpointed(tnsim_mps h, void *dev_ws, size_t ws_byt
   if (h->cfg.precision != TNSIM_FP64) return TNSIM_E_ARG;  // the adjoint records float64
   if (reinterpret_cast<uintptr_t>(dev_ws) % ALIGN) return TNSIM_E_ARG;
   if (segment_start[0] != 0) return TNSIM_E_ARG;
+  for (int p = 0; p < n_params; p++)
+    if (!std::isfinite(angles[p])) return TNSIM_E_ARG;
   int max_seg = 0;
   for (int sg = 0; sg < n_segments; sg++) {
     int a = segment_start[sg], b = sg + 1 < n_segments ? segment_start[sg + 1] : n_gates;
@@ -2120,6 +2131,7 @@ tnsim_status tnsim_forward_checkpointed(tnsim_mps h, void *dev_ws, size_t ws_byt
     if (b >= 0 && std::abs(a - b) != 1) return TNSIM_E_NONLOCAL;
     if (p >= n_params || (p >= 0 && (b >= 0 || rot_axis[p] < 0 || rot_axis[p] > 2)))
       return TNSIM_E_ARG;
+    if (p < 0 && !finite_gate(circuit[g])) return TNSIM_E_ARG;
   }
   std::vector<std::vector<double2>> tabs(n_terms);
   std::vector<std::vector<char>> isIs(n_terms);

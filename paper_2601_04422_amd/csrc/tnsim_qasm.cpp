@@ -450,6 +450,7 @@ struct Parser {
       i++;
       while (!is_sym(")")) {
         params.push_back(expr(penv ? *penv : none));
+        if (!std::isfinite(params.back())) fail_at(line, "a gate parameter is not finite");
         if (is_sym(",")) i++;
         else if (!is_sym(")")) fail_at(line, "expected ',' or ')'");
       }

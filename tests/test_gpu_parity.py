@@ -177,7 +177,16 @@ def test_errors_leave_state_unchanged(T):
     assert m.apply_layer([(0, 2, g)]) == T.E_NONLOCAL
     assert m.apply_layer([(5, 6, g)]) == T.E_ARG
     assert m.apply_2q(0, 6, g) == T.E_ARG
+    bad = np.array(g, dtype=np.complex128)
+    bad[1, 1] = np.nan
+    assert m.apply_2q(0, 1, bad) == T.E_ARG
+    assert m.apply_2q(0, 3, bad) == T.E_ARG
+    assert m.apply_layer([(2, 3, bad)]) == T.E_ARG
+    assert m.apply_circuit([(1, 4, bad)]) == T.E_ARG
+    with pytest.raises(T.TnsimError):
+        m.apply_1q(0, np.array([[1, 0], [0, np.inf]]))
     assert list(m.bond_dims()) == [1] * (n - 1)
+    assert abs(m.amplitude([0] * n) - 1) < 1e-15
     nc = T.MPS(n, 8, jacobi_max_sweeps=1)
     rng = np.random.default_rng(2)
     assert nc.apply_2q(2, 3, W.haar_u4(rng)) == T.E_NOCONV

@@ -186,6 +186,8 @@ def test_definitions_exact_phases():
     ("qreg q[1];\ngate g a { g a; }\ng q[0];", "nested too deeply"),
     ("qreg q[1];\nopaque g a;", "not supported"),
     ("OPENQASM 3.0;\nqreg q[1];", "OpenQASM 2"),
+    ("qreg q[1];\nrx(1/0) q[0];", "not finite"),
+    ("qreg q[1];\nrz(1e999) q[0];", "not finite"),
 ])
 def test_errors(text, msg):
     with pytest.raises(T.TnsimError) as e:
