@@ -34,7 +34,7 @@ struct Layout {
   size_t x_off = 0, j_off = 0, t_off = 0, v_off = 0, pf_off = 0, ver_off = 0, seen_off = 0,
          sig_off = 0, perm_off = 0, sc_off = 0, u_off = 0, tq_off = 0;  // within a slot
   size_t gp_off = 0;  // pooled pair-Gram partials
-  size_t desc_off = 0, d1_off = 0, ctr_off = 0, scg_off = 0;
+  size_t desc_off = 0, desc2_off = 0, d1_off = 0, ctr_off = 0, scg_off = 0;
   size_t e0_off = 0, e1_off = 0, f_off = 0, f2_off = 0, va_off = 0, vb_off = 0;
   size_t total = 0;
 };
@@ -140,6 +140,8 @@ Layout make_layout(const tnsim_config &c) {
   off = align_up(off + sizeof(double2) * (size_t)L.gp_blocks * PW * PW);
   L.desc_off = off;
   off = align_up(off + sizeof(GateDesc) * L.desc_cap);
+  L.desc2_off = off;  // descriptors of gates prepared on the second stream
+  off = align_up(off + sizeof(GateDesc) * L.desc_cap);
   L.scg_off = off;
   off = align_up(off + sizeof(SlotScalars) * L.desc_cap);
   L.d1_off = off;
@@ -224,6 +226,12 @@ struct tnsim_mps_s {
   std::string err;
   char *pin = nullptr;
   size_t pin_bytes = 0;
+  // second stream of the circuit scheduler: gates admitted into the sweeps
+  // are prepared there (own descriptor region and pinned staging buffer)
+  // while the gates in flight keep sweeping on `stream`
+  hipStream_t stream2 = nullptr;
+  char *pin2 = nullptr;
+  hipEvent_t ev_main = nullptr, ev_prep = nullptr;
   // profiling
   struct Rec {
     int cls;
@@ -232,6 +240,7 @@ struct tnsim_mps_s {
   };
   bool prof = false;
   int inner_sweeps = 1;  // one inner sweep per pair solve (outer sweeps finish the job)
+  bool overlap_prepare = true;  // TNSIM_OVERLAP_PREPARE=0: scheduler prepares in line
   std::vector<int32_t> last_batch;  // 6 ints per two-qubit gate of the last apply call
   GradState grad;
   // captured Jacobi sweep (reused while the batch shape is unchanged)
@@ -244,7 +253,7 @@ struct tnsim_mps_s {
   int64_t sw_gates = 0, sw_sum = 0;
   int sw_max = 0;
   std::vector<hipEvent_t> evpool;
-  std::vector<Rec> pending;
+  std::vector<Rec> pending, pending2;  // profiling events on stream, stream2
   tnsim_kernel_stat kstat[TNSIM_K_COUNT] = {};
 
   template <class T>
@@ -307,26 +316,30 @@ struct ProfScope {
   tnsim_mps h;
   int cls;
   double flops, bytes;
+  hipStream_t st;
+  std::vector<tnsim_mps_s::Rec> *pend;
   hipEvent_t a = nullptr;
-  ProfScope(tnsim_mps h_, int cls_, double fl = 0.0, double by = 0.0)
-      : h(h_), cls(cls_), flops(fl), bytes(by) {
+  ProfScope(tnsim_mps h_, int cls_, double fl = 0.0, double by = 0.0, bool second = false)
+      : h(h_), cls(cls_), flops(fl), bytes(by), st(second ? h_->stream2 : h_->stream),
+        pend(second ? &h_->pending2 : &h_->pending) {
     if (h->prof) {
       a = ev_get(h);
-      if (a) hipEventRecord(a, h->stream);
+      if (a) hipEventRecord(a, st);
     }
   }
   ~ProfScope() {
     if (!h->prof || !a) return;
     hipEvent_t b = ev_get(h);
     if (!b) return;
-    hipEventRecord(b, h->stream);
-    h->pending.push_back({cls, a, b, flops, bytes});
+    hipEventRecord(b, st);
+    pend->push_back({cls, a, b, flops, bytes});
   }
 };
 
 // After a stream synchronisation: fold finished event pairs into the totals.
-void prof_drain(tnsim_mps h) {
-  for (auto &r : h->pending) {
+void prof_drain(tnsim_mps h, bool second = false) {
+  auto &pend = second ? h->pending2 : h->pending;
+  for (auto &r : pend) {
     float ms = 0.0f;
     if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) h->kstat[r.cls].ms += ms;
     h->kstat[r.cls].launches += 1;
@@ -335,7 +348,7 @@ void prof_drain(tnsim_mps h) {
     h->evpool.push_back(r.a);
     h->evpool.push_back(r.b);
   }
-  h->pending.clear();
+  pend.clear();
 }
 
 tnsim_status init_state(tnsim_mps h) {
@@ -439,19 +452,23 @@ GateDesc make_desc(tnsim_mps o, const BatchItem &it, bool force_trans) {
 }
 
 // Copy descriptors into the owner's descriptor array.  Waits for the stream
-// first: the pinned staging buffer may still feed an earlier copy.
-tnsim_status put_descs(tnsim_mps o, const GateDesc *D, int n) {
-  HIPCHK(o, hipStreamSynchronize(o->stream));
-  prof_drain(o);
-  memcpy(o->pin, D, sizeof(GateDesc) * n);
-  HIPCHK(o, hipMemcpyAsync(o->at<GateDesc>(o->L.desc_off), o->pin, sizeof(GateDesc) * n,
-                           hipMemcpyHostToDevice, o->stream));
+// first: the pinned staging buffer may still feed an earlier copy.  With
+// `second`, the second stream, its staging buffer and descriptor region.
+tnsim_status put_descs(tnsim_mps o, const GateDesc *D, int n, bool second = false) {
+  hipStream_t st = second ? o->stream2 : o->stream;
+  char *pin = second ? o->pin2 : o->pin;
+  HIPCHK(o, hipStreamSynchronize(st));
+  prof_drain(o, second);
+  memcpy(pin, D, sizeof(GateDesc) * n);
+  HIPCHK(o, hipMemcpyAsync(o->at<GateDesc>(second ? o->L.desc2_off : o->L.desc_off), pin,
+                           sizeof(GateDesc) * n, hipMemcpyHostToDevice, st));
   return TNSIM_OK;
 }
 
 // Everything before the Jacobi sweeps: merge, gate and weight, QR
-// preconditioning, column norms, the per-gate scalars.
-tnsim_status gates_prepare(tnsim_mps o, const GateDesc *D, int ng) {
+// preconditioning, column norms, the per-gate scalars.  With `second`, on
+// the second stream (the caller orders it after the work it depends on).
+tnsim_status gates_prepare(tnsim_mps o, const GateDesc *D, int ng, bool second = false) {
   tnsim_mps h = o;
   int maxM = 0, maxColsPad = 0, maxChiR = 0, qrN = 0, qrMr = 0;
   double theta_flop = 0.0, theta_byte = 0.0, colnorm_byte = 0.0, qr_flop = 0.0;
@@ -471,16 +488,16 @@ tnsim_status gates_prepare(tnsim_mps o, const GateDesc *D, int ng) {
       qr_flop += 8.0 * (mm * nn * nn - nn * nn * nn / 3.0) + 16.0 * nn * nn * nn / 3.0;
     }
   }
-  tnsim_status s = put_descs(o, D, ng);
+  tnsim_status s = put_descs(o, D, ng, second);
   if (s != TNSIM_OK) return s;
-  GateDesc *ddev = o->at<GateDesc>(o->L.desc_off);
-  hipStream_t st = o->stream;
+  GateDesc *ddev = o->at<GateDesc>(second ? o->L.desc2_off : o->L.desc_off);
+  hipStream_t st = second ? o->stream2 : o->stream;
   {
-    ProfScope p(h, TNSIM_K_OTHER);
+    ProfScope p(h, TNSIM_K_OTHER, 0.0, 0.0, second);
     launch_setup_slots(st, ddev, ng, maxColsPad, 0);
   }
   {
-    ProfScope p(h, TNSIM_K_THETA, theta_flop, theta_byte);
+    ProfScope p(h, TNSIM_K_THETA, theta_flop, theta_byte, second);
     launch_theta(st, ddev, ng, o->cfg.precision, maxM, maxChiR);
   }
   // QR preconditioning of the gates that take it: M = Q1 R1 (stage 0),
@@ -490,7 +507,7 @@ tnsim_status gates_prepare(tnsim_mps o, const GateDesc *D, int ng) {
   // of the matrix in one pass.
   const int qrGroups = (qrN + QG - 1) / QG;
   if (qrN > 0) {
-    ProfScope p(h, TNSIM_K_QR, qr_flop, 0.0);
+    ProfScope p(h, TNSIM_K_QR, qr_flop, 0.0, second);
     for (int stage = 0; stage < 2; stage++) {
       for (int grp = 0; grp < qrGroups; grp++) {
         const int gend = (grp + 1) * QG;
@@ -506,11 +523,11 @@ tnsim_status gates_prepare(tnsim_mps o, const GateDesc *D, int ng) {
     launch_qr_r2h(st, ddev, ng, qrN);
   }
   {
-    ProfScope p(h, TNSIM_K_COLNORM, 0.0, colnorm_byte);
+    ProfScope p(h, TNSIM_K_COLNORM, 0.0, colnorm_byte, second);
     launch_colnorm(st, ddev, ng, maxColsPad);
   }
   {
-    ProfScope p(h, TNSIM_K_OTHER);
+    ProfScope p(h, TNSIM_K_OTHER, 0.0, 0.0, second);
     launch_gate_init(st, ddev, ng);
   }
   LAUNCHCHK(h, "theta");
@@ -934,7 +951,29 @@ tnsim_status validate_layer(tnsim_mps h, const tnsim_gate *gates, int ng,
 // which the last gates of a layer converge.
 constexpr int kAdmitGroup = 16;
 
+// The second stream of the scheduler, its events and staging buffer, made on
+// first use (default priority, like every stream here).
+tnsim_status ensure_stream2(tnsim_mps h) {
+  if (h->stream2) return TNSIM_OK;
+  HIPCHK(h, hipHostMalloc((void **)&h->pin2, h->pin_bytes, hipHostMallocDefault));
+  HIPCHK(h, hipEventCreateWithFlags(&h->ev_main, hipEventDisableTiming));
+  HIPCHK(h, hipEventCreateWithFlags(&h->ev_prep, hipEventDisableTiming));
+  HIPCHK(h, hipStreamCreateWithFlags(&h->stream2, hipStreamNonBlocking));
+  return TNSIM_OK;
+}
+
+tnsim_status run_circuit_impl(tnsim_mps h, const tnsim_gate *gates, int ng);
+
 tnsim_status run_circuit(tnsim_mps h, const tnsim_gate *gates, int ng) {
+  tnsim_status s = run_circuit_impl(h, gates, ng);
+  // no preparation may outlive the call, whatever its outcome
+  if (h->stream2 && hipStreamSynchronize(h->stream2) != hipSuccess && s == TNSIM_OK)
+    s = fail(h, hipErrorUnknown, "second stream");
+  prof_drain(h, true);
+  return s;
+}
+
+tnsim_status run_circuit_impl(tnsim_mps h, const tnsim_gate *gates, int ng) {
   struct Op {
     int kind = 0;  // 1 or 2 qubits
     int q = 0;     // site (1q)
@@ -995,6 +1034,20 @@ tnsim_status run_circuit(tnsim_mps h, const tnsim_gate *gates, int ng) {
   SweepRunner sw{h};
   bool dirty = true;
   std::vector<char> rot;
+  // gates admitted while others sweep are prepared on the second stream and
+  // join the sweeps once their preparation has finished
+  if (h->overlap_prepare) {
+    tnsim_status s = ensure_stream2(h);
+    if (s != TNSIM_OK) return s;
+  }
+  std::vector<Flight> prep;
+  auto join = [&]() -> tnsim_status {
+    HIPCHK(h, hipStreamWaitEvent(h->stream, h->ev_prep, 0));
+    for (const Flight &f : prep) fl.push_back(f);
+    prep.clear();
+    dirty = true;
+    return TNSIM_OK;
+  };
   for (;;) {
     // one-qubit gates: all ready ones at once (they are on distinct sites)
     while (!ready1.empty()) {
@@ -1010,24 +1063,40 @@ tnsim_status run_circuit(tnsim_mps h, const tnsim_gate *gates, int ng) {
     // QR) costs about the same latency for one gate as for many, so ready
     // gates wait until there are enough of them or the GPU runs short of work
     std::vector<GateDesc> nd;
-    std::vector<BatchItem> ni;
+    std::vector<Flight> nf;
     size_t taken = 0;
-    const bool admit = (int)ready2.size() >= kAdmitGroup || (int)fl.size() < kAdmitGroup;
+    const bool admit = prep.empty() &&
+                       ((int)ready2.size() >= kAdmitGroup || (int)fl.size() < kAdmitGroup);
     for (; admit && taken < ready2.size() && !free_slots.empty(); taken++) {
       const int k = ready2[taken];
       BatchItem it{h, free_slots.back(), &ops[k].p};
       free_slots.pop_back();
-      ni.push_back(it);
       nd.push_back(make_desc(h, it, false));
-      fl.push_back(Flight{it, nd.back(), k, 0});
+      nf.push_back(Flight{it, nd.back(), k, 0});
     }
     ready2.erase(ready2.begin(), ready2.begin() + taken);
     if (!nd.empty()) {
-      tnsim_status s = gates_prepare(h, nd.data(), (int)nd.size());
-      if (s != TNSIM_OK) return s;
-      dirty = true;
+      if (h->overlap_prepare && !fl.empty()) {
+        // after everything issued so far (the predecessors' write-backs)
+        HIPCHK(h, hipEventRecord(h->ev_main, h->stream));
+        HIPCHK(h, hipStreamWaitEvent(h->stream2, h->ev_main, 0));
+        tnsim_status s = gates_prepare(h, nd.data(), (int)nd.size(), true);
+        if (s != TNSIM_OK) return s;
+        HIPCHK(h, hipEventRecord(h->ev_prep, h->stream2));
+        prep = nf;
+      } else {
+        tnsim_status s = gates_prepare(h, nd.data(), (int)nd.size());
+        if (s != TNSIM_OK) return s;
+        for (const Flight &f : nf) fl.push_back(f);
+        dirty = true;
+      }
     }
     if (fl.empty()) {
+      if (!prep.empty()) {  // nothing to sweep meanwhile
+        tnsim_status s = join();
+        if (s != TNSIM_OK) return s;
+        continue;
+      }
       if (ready1.empty() && ready2.empty()) break;
       continue;
     }
@@ -1074,6 +1143,15 @@ tnsim_status run_circuit(tnsim_mps h, const tnsim_gate *gates, int ng) {
       }
       fl.swap(keep);
       dirty = true;
+    }
+    if (!prep.empty()) {
+      const hipError_t q = hipEventQuery(h->ev_prep);
+      if (q == hipSuccess) {
+        s = join();
+        if (s != TNSIM_OK) return s;
+      } else if (q != hipErrorNotReady) {
+        return fail(h, q, "hipEventQuery");
+      }
     }
   }
   return TNSIM_OK;
@@ -1551,6 +1629,7 @@ tnsim_status tnsim_mps_create(const tnsim_config *cfg, void *dev_arena, size_t a
     int v = atoi(e);
     if (v >= 1 && v <= 1 << 20) h->gram_wg_target = v;
   }
+  if (const char *e = getenv("TNSIM_OVERLAP_PREPARE")) h->overlap_prepare = atoi(e) != 0;
   if (const char *e = getenv("TNSIM_INNER_SWEEPS")) {
     int v = atoi(e);
     if (v >= 1 && v <= 60) h->inner_sweeps = v;
@@ -1585,6 +1664,14 @@ tnsim_status tnsim_mps_create(const tnsim_config *cfg, void *dev_arena, size_t a
 tnsim_status tnsim_mps_destroy(tnsim_mps h) {
   if (!h) return TNSIM_E_ARG;
   if (!h->poisoned) hipStreamSynchronize(h->stream);
+  if (h->stream2) {
+    hipStreamSynchronize(h->stream2);
+    prof_drain(h, true);
+    hipStreamDestroy(h->stream2);
+  }
+  if (h->ev_main) hipEventDestroy(h->ev_main);
+  if (h->ev_prep) hipEventDestroy(h->ev_prep);
+  if (h->pin2) hipHostFree(h->pin2);
   prof_drain(h);
   if (h->sweep_exec) hipGraphExecDestroy(h->sweep_exec);
   for (hipEvent_t e : h->evpool) hipEventDestroy(e);
