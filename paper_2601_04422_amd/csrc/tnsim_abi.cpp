@@ -241,6 +241,7 @@ struct tnsim_mps_s {
   bool prof = false;
   int inner_sweeps = 1;  // one inner sweep per pair solve (outer sweeps finish the job)
   bool overlap_prepare = true;  // TNSIM_OVERLAP_PREPARE=0: scheduler prepares in line
+  int admit_group = 16;         // scheduler: ready gates admitted together (TNSIM_ADMIT_GROUP)
   std::vector<int32_t> last_batch;  // 6 ints per two-qubit gate of the last apply call
   GradState grad;
   // captured Jacobi sweep (reused while the batch shape is unchanged)
@@ -948,8 +949,9 @@ tnsim_status validate_layer(tnsim_mps h, const tnsim_gate *gates, int ng,
 // gates in flight share each Jacobi sweep; a gate that converges is truncated
 // and written back at once, which releases its successors.  Gates of
 // consecutive layers thus overlap: the next layer's gates fill the sweeps in
-// which the last gates of a layer converge.
-constexpr int kAdmitGroup = 16;
+// which the last gates of a layer converge.  Ready gates are admitted in
+// groups (admit_group, or fewer when little is in flight), and a group
+// admitted while others sweep is prepared on the second stream.
 
 // The second stream of the scheduler, its events and staging buffer, made on
 // first use (default priority, like every stream here).
@@ -1066,7 +1068,7 @@ tnsim_status run_circuit_impl(tnsim_mps h, const tnsim_gate *gates, int ng) {
     std::vector<Flight> nf;
     size_t taken = 0;
     const bool admit = prep.empty() &&
-                       ((int)ready2.size() >= kAdmitGroup || (int)fl.size() < kAdmitGroup);
+                       ((int)ready2.size() >= h->admit_group || (int)fl.size() < h->admit_group);
     for (; admit && taken < ready2.size() && !free_slots.empty(); taken++) {
       const int k = ready2[taken];
       BatchItem it{h, free_slots.back(), &ops[k].p};
@@ -1630,6 +1632,10 @@ tnsim_status tnsim_mps_create(const tnsim_config *cfg, void *dev_arena, size_t a
     if (v >= 1 && v <= 1 << 20) h->gram_wg_target = v;
   }
   if (const char *e = getenv("TNSIM_OVERLAP_PREPARE")) h->overlap_prepare = atoi(e) != 0;
+  if (const char *e = getenv("TNSIM_ADMIT_GROUP")) {
+    const int v = atoi(e);
+    if (v >= 1 && v <= 4096) h->admit_group = v;
+  }
   if (const char *e = getenv("TNSIM_INNER_SWEEPS")) {
     int v = atoi(e);
     if (v >= 1 && v <= 60) h->inner_sweeps = v;
