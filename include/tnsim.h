@@ -231,6 +231,18 @@ tnsim_status tnsim_import_state(tnsim_mps mps, const tnsim_c128 *const *sites,
 size_t tnsim_sample_workspace_bytes(const tnsim_config *cfg, int32_t max_shots);
 tnsim_status tnsim_sample(tnsim_mps mps, void *dev_ws, size_t ws_bytes, int32_t shots,
                           const double *dev_u, uint8_t *dev_bits, double *dev_logp);
+/* The same in two parts, for many draws from one state: tnsim_sample_prepare
+   builds the per-site weights M_q^s = A_q^{sH} E_q A_q^s (the part of
+   tnsim_sample that does not depend on the shots) in a workspace sized for
+   max_shots; each tnsim_sample_draw then draws up to max_shots strings from
+   them, exactly as tnsim_sample would.  A draw needs the same workspace
+   (pointer and size) as the last prepare and an unchanged state: after any
+   call that may change the state (gates, reset, import, copy into it,
+   gradients) it returns TNSIM_E_ARG until prepared again.  Shots above
+   max_shots: TNSIM_E_CAPACITY. */
+tnsim_status tnsim_sample_prepare(tnsim_mps mps, void *dev_ws, size_t ws_bytes, int32_t max_shots);
+tnsim_status tnsim_sample_draw(tnsim_mps mps, void *dev_ws, size_t ws_bytes, int32_t shots,
+                               const double *dev_u, uint8_t *dev_bits, double *dev_logp);
 
 /* ---- gradients of a Pauli-sum loss with respect to rotation angles ----
    Loss L = sum_t coeffs[t] <psi|P_t|psi>/<psi|psi>, psi = circuit |0...0>.

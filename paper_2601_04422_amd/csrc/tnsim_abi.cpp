@@ -242,6 +242,12 @@ struct tnsim_mps_s {
   int inner_sweeps = 1;  // one inner sweep per pair solve (outer sweeps finish the job)
   bool overlap_prepare = true;  // TNSIM_OVERLAP_PREPARE=0: scheduler prepares in line
   int admit_group = 16;         // scheduler: ready gates admitted together (TNSIM_ADMIT_GROUP)
+  // sampling weights prepared for draws: valid while the state is unchanged
+  uint64_t state_version = 0;   // bumped by every call that may change the state
+  void *smp_ws = nullptr;
+  size_t smp_bytes = 0;
+  int smp_cap = 0;
+  uint64_t smp_version = 0;
   std::vector<int32_t> last_batch;  // 6 ints per two-qubit gate of the last apply call
   GradState grad;
   // captured Jacobi sweep (reused while the batch shape is unchanged)
@@ -1689,12 +1695,14 @@ tnsim_status tnsim_mps_destroy(tnsim_mps h) {
 tnsim_status tnsim_mps_reset(tnsim_mps h) {
   tnsim_status s = check_handle(h);
   if (s != TNSIM_OK) return s;
+  h->state_version++;
   return init_state(h);
 }
 
 tnsim_status tnsim_apply_1q(tnsim_mps h, int32_t q, const tnsim_c128 u[4]) {
   tnsim_status s = check_handle(h);
   if (s != TNSIM_OK) return s;
+  h->state_version++;
   if (!u || q < 0 || q >= h->L.n || !finite_gate(u, 4)) return TNSIM_E_ARG;
   return run_1q(h, {{q, u}});
 }
@@ -1702,6 +1710,7 @@ tnsim_status tnsim_apply_1q(tnsim_mps h, int32_t q, const tnsim_c128 u[4]) {
 tnsim_status tnsim_apply_2q(tnsim_mps h, int32_t q0, int32_t q1, const tnsim_c128 g[16]) {
   tnsim_status s = check_handle(h);
   if (s != TNSIM_OK) return s;
+  h->state_version++;
   if (!g || q0 < 0 || q1 < 0 || q0 >= h->L.n || q1 >= h->L.n || q0 == q1 || !finite_gate(g, 16))
     return TNSIM_E_ARG;
   h->last_sweeps = 0;
@@ -1723,6 +1732,7 @@ tnsim_status tnsim_apply_2q(tnsim_mps h, int32_t q0, int32_t q1, const tnsim_c12
 tnsim_status tnsim_apply_layer(tnsim_mps h, const tnsim_gate *gates, int32_t n_gates) {
   tnsim_status s = check_handle(h);
   if (s != TNSIM_OK) return s;
+  h->state_version++;
   std::vector<std::pair<int, const tnsim_c128 *>> g1;
   std::vector<Pending> g2;
   s = validate_layer(h, gates, n_gates, g1, g2);
@@ -1737,6 +1747,7 @@ tnsim_status tnsim_apply_layer(tnsim_mps h, const tnsim_gate *gates, int32_t n_g
 tnsim_status tnsim_apply_circuit(tnsim_mps h, const tnsim_gate *gates, int32_t n_gates) {
   tnsim_status s = check_handle(h);
   if (s != TNSIM_OK) return s;
+  h->state_version++;
   const int n = h->L.n;
   if (n_gates < 0 || (n_gates > 0 && !gates)) return TNSIM_E_ARG;
   std::vector<tnsim_gate> local;
@@ -1763,6 +1774,7 @@ tnsim_status tnsim_apply_layer_multi(tnsim_mps const *mps, const tnsim_gate *con
     for (int j = 0; j < k; j++)
       if (mps[j] == mps[k]) return TNSIM_E_ARG;
   }
+  for (int k = 0; k < n_mps; k++) mps[k]->state_version++;
   std::vector<std::vector<std::pair<int, const tnsim_c128 *>>> g1(n_mps);
   std::vector<std::vector<Pending>> g2(n_mps);
   for (int k = 0; k < n_mps; k++) {
@@ -1953,32 +1965,19 @@ size_t tnsim_sample_workspace_bytes(const tnsim_config *cfg, int32_t max_shots) 
   return sample_layout(make_layout(*cfg), max_shots).total;
 }
 
-tnsim_status tnsim_sample(tnsim_mps h, void *dev_ws, size_t ws_bytes, int32_t shots,
-                          const double *dev_u, uint8_t *dev_bits, double *dev_logp) {
-  tnsim_status s = check_handle(h);
-  if (s != TNSIM_OK) return s;
-  if (shots < 0 || shots > (1 << 28)) return TNSIM_E_ARG;
-  if (shots == 0) return TNSIM_OK;
-  if (!dev_ws || !dev_u || !dev_bits) return TNSIM_E_ARG;
-  if (reinterpret_cast<uintptr_t>(dev_ws) % ALIGN) return TNSIM_E_ARG;
+// Per-site bit weights M_q^s = A_q^{sH} (E_q A_q^s) into the workspace: F =
+// E_q A_q (rows (a, s)), then one product per s over the rows of that s;
+// E_{q+1} = M_q^0 + M_q^1.
+static tnsim_status sample_weights(tnsim_mps h, char *ws, const SampleLayout &S) {
   const Layout &L = h->L;
-  const SampleLayout S = sample_layout(L, shots);
-  if (ws_bytes < S.total) return TNSIM_E_CAPACITY;
   const int n = L.n, sto = L.storage;
   hipStream_t st = h->stream;
-  char *ws = (char *)dev_ws;
   auto Ms = [&](int q) { return (double2 *)(ws + S.msite[q]); };
   double2 *E = (double2 *)(ws + S.E0), *En = (double2 *)(ws + S.E1);
   double2 *F = (double2 *)(ws + S.F), *Pb = (double2 *)(ws + S.P);
-  double2 *V = (double2 *)(ws + S.V0), *Vn = (double2 *)(ws + S.V1), *Yb = (double2 *)(ws + S.Y);
-  double *p = (double *)(ws + S.p), *logp = (double *)(ws + S.logp);
-  double *scale = (double *)(ws + S.scale);
-  int *flag = (int *)(ws + S.flag), *idx = (int *)(ws + S.idx), *node = (int *)(ws + S.node),
-      *key = (int *)(ws + S.key), *parent = (int *)(ws + S.parent), *ctr = (int *)(ws + S.ctr);
-  const int cap = shots + 64;  // node-table columns (see sample_layout)
-  launch_smp_init(st, shots, cap, node, logp, flag, V, E, ctr);
-  // M_q^s = A_q^{sH} (E_q A_q^s): F = E_q A_q (rows (a, s)), then one product
-  // per s over the rows of that s; E_{q+1} = M_q^0 + M_q^1
+  // E_0 = 1 (and the node tables of a one-shot draw, unused here)
+  launch_smp_init(st, 0, 64, (int *)(ws + S.node), (double *)(ws + S.logp), (int *)(ws + S.flag),
+                  (double2 *)(ws + S.V0), E, (int *)(ws + S.ctr));
   for (int q = 0; q < n; q++) {
     const int la = h->dims[q], rb = h->dims[q + 1];
     ZgemmArgs f{la, 2 * rb, la, E, la, h->site(q), 2 * rb, F, 2 * rb, nullptr, 0};
@@ -1999,6 +1998,24 @@ tnsim_status tnsim_sample(tnsim_mps h, void *dev_ws, size_t ws_bytes, int32_t sh
     }
   }
   LAUNCHCHK(h, "sample weights");
+  return TNSIM_OK;
+}
+
+// The draws, from weights already in the workspace (layout S, shots within
+// its capacity).
+static tnsim_status sample_draw(tnsim_mps h, char *ws, const SampleLayout &S, int shots,
+                                const double *dev_u, uint8_t *dev_bits, double *dev_logp) {
+  const Layout &L = h->L;
+  const int n = L.n, sto = L.storage;
+  hipStream_t st = h->stream;
+  auto Ms = [&](int q) { return (double2 *)(ws + S.msite[q]); };
+  double2 *V = (double2 *)(ws + S.V0), *Vn = (double2 *)(ws + S.V1), *Yb = (double2 *)(ws + S.Y);
+  double *p = (double *)(ws + S.p), *logp = (double *)(ws + S.logp);
+  double *scale = (double *)(ws + S.scale);
+  int *flag = (int *)(ws + S.flag), *idx = (int *)(ws + S.idx), *node = (int *)(ws + S.node),
+      *key = (int *)(ws + S.key), *parent = (int *)(ws + S.parent), *ctr = (int *)(ws + S.ctr);
+  const int cap = shots + 64;  // node-table columns (see sample_layout)
+  launch_smp_init(st, shots, cap, node, logp, flag, V, (double2 *)(ws + S.E0), ctr);
   long long mb = 1;  // bound on the node count before the step
   for (int q = n - 1; q >= 0; q--) {
     const int la = h->dims[q], rb = h->dims[q + 1];
@@ -2039,12 +2056,69 @@ tnsim_status tnsim_sample(tnsim_mps h, void *dev_ws, size_t ws_bytes, int32_t sh
   return TNSIM_OK;
 }
 
+static tnsim_status sample_check_ws(tnsim_mps h, void *dev_ws, size_t ws_bytes, int cap,
+                                    SampleLayout &S) {
+  if (!dev_ws || reinterpret_cast<uintptr_t>(dev_ws) % ALIGN) return TNSIM_E_ARG;
+  S = sample_layout(h->L, cap);
+  return ws_bytes < S.total ? TNSIM_E_CAPACITY : TNSIM_OK;
+}
+
+tnsim_status tnsim_sample(tnsim_mps h, void *dev_ws, size_t ws_bytes, int32_t shots,
+                          const double *dev_u, uint8_t *dev_bits, double *dev_logp) {
+  tnsim_status s = check_handle(h);
+  if (s != TNSIM_OK) return s;
+  if (shots < 0 || shots > (1 << 28)) return TNSIM_E_ARG;
+  if (shots == 0) return TNSIM_OK;
+  if (!dev_u || !dev_bits) return TNSIM_E_ARG;
+  SampleLayout S;
+  s = sample_check_ws(h, dev_ws, ws_bytes, shots, S);
+  if (s != TNSIM_OK) return s;
+  s = sample_weights(h, (char *)dev_ws, S);
+  if (s != TNSIM_OK) return s;
+  return sample_draw(h, (char *)dev_ws, S, shots, dev_u, dev_bits, dev_logp);
+}
+
+tnsim_status tnsim_sample_prepare(tnsim_mps h, void *dev_ws, size_t ws_bytes, int32_t max_shots) {
+  tnsim_status s = check_handle(h);
+  if (s != TNSIM_OK) return s;
+  if (max_shots < 1 || max_shots > (1 << 28)) return TNSIM_E_ARG;
+  SampleLayout S;
+  s = sample_check_ws(h, dev_ws, ws_bytes, max_shots, S);
+  if (s != TNSIM_OK) return s;
+  h->smp_ws = nullptr;  // invalid until the weights are in
+  s = sample_weights(h, (char *)dev_ws, S);
+  if (s != TNSIM_OK) return s;
+  h->smp_ws = dev_ws;
+  h->smp_bytes = ws_bytes;
+  h->smp_cap = max_shots;
+  h->smp_version = h->state_version;
+  return TNSIM_OK;
+}
+
+tnsim_status tnsim_sample_draw(tnsim_mps h, void *dev_ws, size_t ws_bytes, int32_t shots,
+                               const double *dev_u, uint8_t *dev_bits, double *dev_logp) {
+  tnsim_status s = check_handle(h);
+  if (s != TNSIM_OK) return s;
+  if (shots < 0 || shots > (1 << 28)) return TNSIM_E_ARG;
+  if (dev_ws == nullptr || dev_ws != h->smp_ws || ws_bytes != h->smp_bytes ||
+      h->smp_version != h->state_version) {
+    h->err = "sample_draw: no current weights in this workspace (call tnsim_sample_prepare)";
+    return TNSIM_E_ARG;
+  }
+  if (shots > h->smp_cap) return TNSIM_E_CAPACITY;
+  if (shots == 0) return TNSIM_OK;
+  if (!dev_u || !dev_bits) return TNSIM_E_ARG;
+  const SampleLayout S = sample_layout(h->L, h->smp_cap);
+  return sample_draw(h, (char *)dev_ws, S, shots, dev_u, dev_bits, dev_logp);
+}
+
 tnsim_status tnsim_mps_copy(tnsim_mps dst, tnsim_mps src) {
   tnsim_status s = check_handle(dst);
   if (s != TNSIM_OK) return s;
   s = check_handle(src);
   if (s != TNSIM_OK) return s;
   if (dst->L.n != src->L.n) return TNSIM_E_ARG;
+  dst->state_version++;
   const int n = dst->L.n;
   for (int q = 1; q < n; q++)
     if (src->dims[q] > dst->L.dimcap[q]) return TNSIM_E_CAPACITY;
@@ -2155,6 +2229,7 @@ tnsim_status tnsim_import_state(tnsim_mps h, const tnsim_c128 *const *sites,
                                 const double *const *lambdas, const int32_t *chis) {
   tnsim_status s = check_handle(h);
   if (s != TNSIM_OK) return s;
+  h->state_version++;
   const int n = h->L.n;
   if (!sites || !chis || (n > 1 && !lambdas)) return TNSIM_E_ARG;
   if (chis[0] != 1 || chis[n] != 1) return TNSIM_E_ARG;
@@ -2202,6 +2277,7 @@ tnsim_status tnsim_forward_checkpointed(tnsim_mps h, void *dev_ws, size_t ws_byt
                                         int32_t n_terms, double *loss) {
   tnsim_status s = check_handle(h);
   if (s != TNSIM_OK) return s;
+  h->state_version++;
   const int n = h->L.n;
   if (!dev_ws || !loss || n_gates < 0 || (n_gates > 0 && (!circuit || !param_of_gate)) ||
       n_params < 0 || (n_params > 0 && (!angles || !rot_axis)) || n_segments < 1 ||
@@ -2280,6 +2356,7 @@ tnsim_status tnsim_forward_checkpointed(tnsim_mps h, void *dev_ws, size_t ws_byt
 tnsim_status tnsim_backward(tnsim_mps h, double dloss, double *grad_angles) {
   tnsim_status s = check_handle(h);
   if (s != TNSIM_OK) return s;
+  h->state_version++;
   GradState &G = h->grad;
   if (!G.ready || (G.n_params > 0 && !grad_angles)) return TNSIM_E_ARG;
   const int n = h->L.n;

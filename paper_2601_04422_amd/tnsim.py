@@ -76,6 +76,8 @@ _SIGS = {
     "tnsim_backward": (C.c_int, [_P, C.c_double, _P]),
     "tnsim_sample_workspace_bytes": (C.c_size_t, [C.POINTER(Config), C.c_int32]),
     "tnsim_sample": (C.c_int, [_P, _P, C.c_size_t, C.c_int32, _P, _P, _P]),
+    "tnsim_sample_prepare": (C.c_int, [_P, _P, C.c_size_t, C.c_int32]),
+    "tnsim_sample_draw": (C.c_int, [_P, _P, C.c_size_t, C.c_int32, _P, _P, _P]),
     "tnsim_profile": (C.c_int, [_P, C.c_int32]),
     "tnsim_profile_read": (C.c_int, [_P, _P]),
     "tnsim_autotune": (C.c_int, [_P, _P]),
@@ -406,6 +408,38 @@ class MPS:
                                      self._smp_ws.numel(), shots, C.c_void_p(ut.data_ptr()),
                                      C.c_void_p(bits.data_ptr()), C.c_void_p(logp.data_ptr())),
                   "sample")
+        return bits, logp
+
+    def sample_prepare(self, max_shots: int) -> None:
+        """Build the per-site weights once (tnsim_sample_prepare) for later
+        sample_draw calls of up to max_shots shots each."""
+        import torch
+
+        ws = lib().tnsim_sample_workspace_bytes(C.byref(self.cfg), int(max_shots))
+        if ws == 0:
+            raise TnsimError(E_ARG, "sample_workspace_bytes")
+        self._draw_ws = torch.empty(ws, dtype=torch.uint8, device=self.device)
+        self._chk(lib().tnsim_sample_prepare(self._h, C.c_void_p(self._draw_ws.data_ptr()),
+                                             self._draw_ws.numel(), int(max_shots)),
+                  "sample_prepare")
+
+    def sample_draw(self, u):
+        """Draws from the prepared weights; same result as sample(u)."""
+        import torch
+
+        ws = getattr(self, "_draw_ws", None)
+        if ws is None:
+            raise TnsimError(E_ARG, "sample_draw", "call sample_prepare first")
+        ut = torch.as_tensor(u, dtype=torch.float64).to(self.device).contiguous()
+        if ut.dim() != 2 or ut.shape[1] != self.n:
+            raise ValueError("u must be shots x n")
+        shots = ut.shape[0]
+        bits = torch.empty((shots, self.n), dtype=torch.uint8, device=self.device)
+        logp = torch.empty(shots, dtype=torch.float64, device=self.device)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        self._chk(lib().tnsim_sample_draw(self._h, C.c_void_p(ws.data_ptr()), ws.numel(), shots,
+                                          C.c_void_p(ut.data_ptr()), C.c_void_p(bits.data_ptr()),
+                                          C.c_void_p(logp.data_ptr())), "sample_draw")
         return bits, logp
 
     def sample_counts(self, u) -> dict:

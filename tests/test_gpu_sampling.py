@@ -186,3 +186,31 @@ def test_sample_counts_histogram(T):
     assert set(counts) == {"0" * n, "1" * n}
     assert sum(counts.values()) == 3000
     assert abs(counts["0" * n] / 3000 - 0.5) < 0.04
+
+
+def test_prepare_once_draw_many(T):
+    """Weights built once serve several draws, each equal to a full sample;
+    any change of the state makes a draw fail until prepared again."""
+    n = 12
+    m = T.MPS(n, 32, 1e-10)
+    m.run_layers(W.brickwork_haar(n, 6, 77))
+    m.sample_prepare(500)
+    rng = np.random.default_rng(31)
+    for shots in (500, 137, 1):
+        u = rng.random((shots, n))
+        b1, l1 = m.sample_draw(u)
+        b2, l2 = m.sample(u)
+        assert np.array_equal(b1.cpu().numpy(), b2.cpu().numpy())
+        assert np.array_equal(l1.cpu().numpy(), l2.cpu().numpy())
+    with pytest.raises(T.TnsimError) as e:
+        m.sample_draw(rng.random((501, n)))
+    assert e.value.code == T.E_CAPACITY
+    m.apply_1q(3, W.rx(0.4))
+    with pytest.raises(T.TnsimError) as e:
+        m.sample_draw(rng.random((10, n)))
+    assert e.value.code == T.E_ARG
+    m.sample_prepare(10)
+    u = rng.random((10, n))
+    b1, _ = m.sample_draw(u)
+    b2, _ = m.sample(u)
+    assert np.array_equal(b1.cpu().numpy(), b2.cpu().numpy())
