@@ -149,25 +149,42 @@ void launch_pauli_phys(hipStream_t st, const double2 *F, double2 *F2, int chiA, 
                      chiA, chiB, p00, p01, p10, p11);
 }
 
-// w[b] = sum_a v[a] A[a, bit, b]
+// w[b] = sum_a v[a] A[a, bit, b].  The rows a are split over blockIdx.y
+// (chunks of AMP_ROWS) so that a wide bond still fills the GPU; the partial
+// sums go to `part` (splits x chiR) and are added in split order.
+constexpr int AMP_ROWS = 64;
+
 template <class S>
-__global__ void k_amp_step(const double2 *v, double2 *w, const S *A, int chiL, int chiR, int bit) {
-  int b = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_amp_part(const double2 *v, double2 *part, const S *A,
+                                                  int chiL, int chiR, int bit) {
+  const int b = blockIdx.x * 256 + threadIdx.x;
   if (b >= chiR) return;
+  const int a0 = blockIdx.y * AMP_ROWS, a1 = min(chiL, a0 + AMP_ROWS);
   double2 acc = make_double2(0.0, 0.0);
-  for (int a = 0; a < chiL; a++) cfma(acc, v[a], cload(A + ((size_t)a * 2 + bit) * chiR + b));
+  for (int a = a0; a < a1; a++) cfma(acc, v[a], cload(A + ((size_t)a * 2 + bit) * chiR + b));
+  part[(size_t)blockIdx.y * chiR + b] = acc;
+}
+
+__global__ void k_amp_sum(const double2 *part, int splits, int chiR, double2 *w) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= chiR) return;
+  double2 acc = part[b];
+  for (int k = 1; k < splits; k++) acc = cadd(acc, part[(size_t)k * chiR + b]);
   w[b] = acc;
 }
 
-void launch_amp_step(hipStream_t st, const double2 *v, double2 *w, const void *A, int storage,
-                     int chiL, int chiR, int bit) {
-  dim3 grid((chiR + 255) / 256);
+// part needs ceil(chiL / 64) * chiR entries.
+void launch_amp_step(hipStream_t st, const double2 *v, double2 *w, double2 *part, const void *A,
+                     int storage, int chiL, int chiR, int bit) {
+  const int splits = (chiL + AMP_ROWS - 1) / AMP_ROWS;
+  dim3 grid((chiR + 255) / 256, splits);
   if (storage == 0)
-    hipLaunchKernelGGL(k_amp_step<double2>, grid, dim3(256), 0, st, v, w, (const double2 *)A, chiL,
-                       chiR, bit);
+    hipLaunchKernelGGL(k_amp_part<double2>, grid, dim3(256), 0, st, v, part, (const double2 *)A,
+                       chiL, chiR, bit);
   else
-    hipLaunchKernelGGL(k_amp_step<float2>, grid, dim3(256), 0, st, v, w, (const float2 *)A, chiL,
-                       chiR, bit);
+    hipLaunchKernelGGL(k_amp_part<float2>, grid, dim3(256), 0, st, v, part, (const float2 *)A,
+                       chiL, chiR, bit);
+  hipLaunchKernelGGL(k_amp_sum, dim3((chiR + 255) / 256), dim3(256), 0, st, part, splits, chiR, w);
 }
 
 }  // namespace tn

@@ -1901,7 +1901,8 @@ tnsim_status tnsim_amplitude(tnsim_mps h, const uint8_t *bits, tnsim_c128 *out) 
   memcpy(h->pin, &one, sizeof one);
   HIPCHK(h, hipMemcpyAsync(v, h->pin, sizeof one, hipMemcpyHostToDevice, st));
   for (int q = 0; q < n; q++) {
-    launch_amp_step(st, v, w, h->site(q), h->L.storage, h->dims[q], h->dims[q + 1], bits[q]);
+    launch_amp_step(st, v, w, h->at<double2>(h->L.f_off), h->site(q), h->L.storage, h->dims[q],
+                    h->dims[q + 1], bits[q]);
     LAUNCHCHK(h, "amplitude");
     std::swap(v, w);
   }

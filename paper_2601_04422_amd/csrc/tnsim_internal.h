@@ -223,7 +223,7 @@ void launch_smp_parent(hipStream_t st, int *flag, const int *idx, const double *
                        int bound, int *parent, double *scale);
 void launch_smp_relabel(hipStream_t st, int shots, const int *key, const int *idx, int *node);
 void launch_smp_add(hipStream_t st, const double2 *M01, size_t n, double2 *E);
-void launch_amp_step(hipStream_t st, const double2 *v, double2 *w, const void *A, int storage,
-                     int chiL, int chiR, int bit);
+void launch_amp_step(hipStream_t st, const double2 *v, double2 *w, double2 *part, const void *A,
+                     int storage, int chiL, int chiR, int bit);
 
 }  // namespace tn
