@@ -28,9 +28,13 @@
  *     bytes (any device allocator; 256-byte alignment) and passes it with a
  *     hipStream_t to tnsim_mps_create.  Buffer and stream must outlive the
  *     handle; the handle owns host metadata and a small pinned staging
- *     buffer only.
+ *     buffer, plus, once tnsim_apply_circuit (or a distant tnsim_apply_2q)
+ *     has run, a second stream with its own staging buffer on which the
+ *     scheduler prepares gates; tnsim_mps_destroy frees them.
  *   - Host arrays passed in (gates, bits, Pauli strings) are copied before the
- *     call returns.  Output pointers are host memory.
+ *     call returns.  Output pointers are host memory, except the sampling
+ *     buffers (device memory, see tnsim_sample).
+ *   - A handle is not thread-safe: calls on one handle must not overlap.
  *   - tnsim_apply_* enqueue on the handle's stream.  The Jacobi sweep loop
  *     synchronises the stream to test convergence, so they return after the
  *     gate work is done.  Readouts synchronise.
@@ -148,8 +152,8 @@ tnsim_status tnsim_apply_layer(tnsim_mps mps, const tnsim_gate *gates, int32_t n
    in parallel): a gate starts once the gates before it on its qubits are
    done, and two-qubit gates in flight, from any layer, share the launches of
    every Jacobi sweep.  gates: host array of n_gates entries, read during the
-   call only.  Errors: TNSIM_E_ARG (qubit out of range, q0 == q1; validated
-   before any work, state unchanged);
+   call only.  Errors: TNSIM_E_ARG (qubit out of range, q0 == q1, a
+   non-finite matrix entry; validated before any work, state unchanged);
    TNSIM_E_NOCONV (a Jacobi ran out of sweeps: the gates completed by then
    stay applied, each one whole and in an order consistent with the circuit,
    the others are not; the MPS stays valid); TNSIM_E_DEVICE. */
