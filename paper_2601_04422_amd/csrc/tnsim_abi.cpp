@@ -1181,15 +1181,19 @@ tnsim_status transfer(tnsim_mps h, tnsim_mps bra, tnsim_mps ket, const double2 *
   for (int q = 0; q < n; q++) {
     int lb = bra->dims[q], rb = bra->dims[q + 1];
     int lk = ket->dims[q], rk = ket->dims[q + 1];
-    // F = E (lb x lk) * K (lk x 2rk)
-    launch_gemm_nn(st, lb, 2 * rk, lk, E, lk, ket->site(q), 2 * rk, ket->L.storage, F, 2 * rk);
+    // F = E (lb x lk) * K (lk x 2rk), on the matrix cores
+    launch_zgemm(st, ZGEMM_NN_ROW,
+                 ZgemmArgs{lb, 2 * rk, lk, E, lk, ket->site(q), 2 * rk, F, 2 * rk, nullptr, 0}, 0,
+                 ket->L.storage);
     const double2 *Fp = F;
     if (P && !isI[q]) {
       launch_pauli_phys(st, F, F2, lb, rk, P[4 * q], P[4 * q + 1], P[4 * q + 2], P[4 * q + 3]);
       Fp = F2;
     }
     // E' = B^H (rb x 2lb) * F (2lb x rk)
-    launch_gemm_cn(st, rb, rk, 2 * lb, bra->site(q), rb, bra->L.storage, Fp, rk, E2, rk);
+    launch_zgemm(st, ZGEMM_CN_ROW,
+                 ZgemmArgs{rb, rk, 2 * lb, bra->site(q), rb, Fp, rk, E2, rk, nullptr, 0},
+                 bra->L.storage, 0);
     LAUNCHCHK(h, "transfer");
     std::swap(E, E2);
   }
