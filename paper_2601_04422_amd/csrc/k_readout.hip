@@ -3,133 +3,12 @@
 //   E_q[b,b'] = sum conj(B_q[a,s,b]) P[s,s'] E_{q-1}[a,a'] K_q[a',s',b']
 //
 // is done per site as F = E K (GEMM), F2 = P on the physical index, and
-// E' = B^H F2 (GEMM with the bra conjugate-transposed), all in float64.
+// E' = B^H F2 (GEMM with the bra conjugate-transposed), all in float64; the
+// two GEMMs are k_zgemm's (k_zgemm.hip), the Pauli step is here.
 #include "tnsim_internal.h"
 #include "tn_complex.h"
 
 namespace tn {
-
-constexpr int RT = 64, RK = 16;
-
-// C (M x N) = A (M x K, complex128 row-major) * B (K x N, site storage, row-major)
-template <class SB>
-__global__ __launch_bounds__(256) void k_gemm_nn(int M, int N, int K, const double2 *A, int lda,
-                                                 const SB *B, int ldb, double2 *C, int ldc) {
-  __shared__ double2 As[RK * RT], Bs[RK * RT];
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  const int i0 = blockIdx.x * RT, j0 = blockIdx.y * RT;
-  double2 acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; i++)
-#pragma unroll
-    for (int j = 0; j < 4; j++) acc[i][j] = make_double2(0.0, 0.0);
-  for (int k0 = 0; k0 < K; k0 += RK) {
-    {
-      int r = tid >> 2, kq = (tid & 3) * 4;
-#pragma unroll
-      for (int q = 0; q < 4; q++) {
-        int gi = i0 + r, gk = k0 + kq + q;
-        As[(kq + q) * RT + r] = (gi < M && gk < K) ? A[(size_t)gi * lda + gk] : make_double2(0, 0);
-      }
-      int kk = tid >> 4, jq = (tid & 15) * 4;
-#pragma unroll
-      for (int q = 0; q < 4; q++) {
-        int gk = k0 + kk, gj = j0 + jq + q;
-        Bs[kk * RT + jq + q] = (gk < K && gj < N) ? cload(B + (size_t)gk * ldb + gj) : make_double2(0, 0);
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < RK; kk++) {
-      double2 a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; i++) a[i] = As[kk * RT + ty + 16 * i];
-#pragma unroll
-      for (int j = 0; j < 4; j++) b[j] = Bs[kk * RT + tx + 16 * j];
-#pragma unroll
-      for (int i = 0; i < 4; i++)
-#pragma unroll
-        for (int j = 0; j < 4; j++) cfma(acc[i][j], a[i], b[j]);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int i = 0; i < 4; i++)
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-      int gi = i0 + ty + 16 * i, gj = j0 + tx + 16 * j;
-      if (gi < M && gj < N) C[(size_t)gi * ldc + gj] = acc[i][j];
-    }
-}
-
-// C (M x N) = A^H B, A stored K x M (site storage, row-major), B K x N complex128
-template <class SA>
-__global__ __launch_bounds__(256) void k_gemm_cn(int M, int N, int K, const SA *A, int lda,
-                                                 const double2 *B, int ldb, double2 *C, int ldc) {
-  __shared__ double2 As[RK * RT], Bs[RK * RT];
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  const int i0 = blockIdx.x * RT, j0 = blockIdx.y * RT;
-  double2 acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; i++)
-#pragma unroll
-    for (int j = 0; j < 4; j++) acc[i][j] = make_double2(0.0, 0.0);
-  for (int k0 = 0; k0 < K; k0 += RK) {
-    {
-      int kk = tid >> 4, iq = (tid & 15) * 4;
-#pragma unroll
-      for (int q = 0; q < 4; q++) {
-        int gk = k0 + kk, gi = i0 + iq + q;
-        As[kk * RT + iq + q] = (gk < K && gi < M) ? cconj(cload(A + (size_t)gk * lda + gi)) : make_double2(0, 0);
-        int gj = j0 + iq + q;
-        Bs[kk * RT + iq + q] = (gk < K && gj < N) ? B[(size_t)gk * ldb + gj] : make_double2(0, 0);
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < RK; kk++) {
-      double2 a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; i++) a[i] = As[kk * RT + ty + 16 * i];
-#pragma unroll
-      for (int j = 0; j < 4; j++) b[j] = Bs[kk * RT + tx + 16 * j];
-#pragma unroll
-      for (int i = 0; i < 4; i++)
-#pragma unroll
-        for (int j = 0; j < 4; j++) cfma(acc[i][j], a[i], b[j]);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int i = 0; i < 4; i++)
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-      int gi = i0 + ty + 16 * i, gj = j0 + tx + 16 * j;
-      if (gi < M && gj < N) C[(size_t)gi * ldc + gj] = acc[i][j];
-    }
-}
-
-void launch_gemm_nn(hipStream_t st, int M, int N, int K, const double2 *A, int lda, const void *B,
-                    int ldb, int b_storage, double2 *C, int ldc) {
-  dim3 grid((M + RT - 1) / RT, (N + RT - 1) / RT);
-  if (b_storage == 0)
-    hipLaunchKernelGGL(k_gemm_nn<double2>, grid, dim3(256), 0, st, M, N, K, A, lda,
-                       (const double2 *)B, ldb, C, ldc);
-  else
-    hipLaunchKernelGGL(k_gemm_nn<float2>, grid, dim3(256), 0, st, M, N, K, A, lda,
-                       (const float2 *)B, ldb, C, ldc);
-}
-
-void launch_gemm_cn(hipStream_t st, int M, int N, int K, const void *A, int lda, int a_storage,
-                    const double2 *B, int ldb, double2 *C, int ldc) {
-  dim3 grid((M + RT - 1) / RT, (N + RT - 1) / RT);
-  if (a_storage == 0)
-    hipLaunchKernelGGL(k_gemm_cn<double2>, grid, dim3(256), 0, st, M, N, K, (const double2 *)A,
-                       lda, B, ldb, C, ldc);
-  else
-    hipLaunchKernelGGL(k_gemm_cn<float2>, grid, dim3(256), 0, st, M, N, K, (const float2 *)A, lda,
-                       B, ldb, C, ldc);
-}
 
 // F2[a,s,b] = sum_s' P[s,s'] F[a,s',b]; F is chiA x 2 x chiB
 __global__ void k_pauli_phys(const double2 *F, double2 *F2, int chiA, int chiB, double2 p00,

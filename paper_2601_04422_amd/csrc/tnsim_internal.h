@@ -167,10 +167,6 @@ void launch_angle_grad(hipStream_t st, const double *ubar, const Mat4 &u, int ax
                        double *grad);
 
 // Readouts
-void launch_gemm_nn(hipStream_t st, int M, int N, int K, const double2 *A, int lda,
-                    const void *B, int ldb, int b_storage, double2 *C, int ldc);
-void launch_gemm_cn(hipStream_t st, int M, int N, int K, const void *A, int lda, int a_storage,
-                    const double2 *B, int ldb, double2 *C, int ldc);
 void launch_pauli_phys(hipStream_t st, const double2 *F, double2 *F2, int chiA, int chiB,
                        double2 p00, double2 p01, double2 p10, double2 p11);
 // complex float64 GEMM on the matrix cores (k_zgemm.hip): C (M x N) = op(A) B
