@@ -347,6 +347,27 @@ def bench_batch(args):
             "max_fidelity_err_vs_oracle": max(fids) if fids else None}
 
 
+def oracle_rate(gates, n, chi, cutoff, threads, budget_s=20.0):
+    """The CPU oracle on the first gates of a circuit until budget_s has
+    passed: two-qubit gates per second (the early gates meet smaller bonds,
+    so this flatters the CPU)."""
+    from oracle import oracle as O
+
+    O.set_threads(threads)
+    o = O.OracleMPS(n, chi, cutoff)
+    t0 = time.perf_counter()
+    k = done = 0
+    for g in gates:
+        o.apply(g)
+        k += 1
+        done += g[1] >= 0
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "2q gates/s", "cores": O.threads(), "kind": "oracle",
+            "sample": f"first {k} of {len(gates)} gates ({done} two-qubit), {dt:.1f} s"}
+
+
 def bench_nonlocal(args):
     """Gates on distant qubits (SWAP chains): n=48, 400 gates, 60% two-qubit
     gates (Haar U(4)) on random pairs up to 8 apart, chi_max=128, cutoff 1e-10.
@@ -386,6 +407,7 @@ def bench_nonlocal(args):
     torch.cuda.synchronize()
     dt_ref = time.perf_counter() - t1
     fid = abs(m.overlap(ref)) ** 2 / (m.norm2() * ref.norm2())
+    cpu = None if args.no_cpu else oracle_rate(gates, n, chi, 1e-10, args.cpu_threads)
     return {"metric": "non-local 2q gates/s, n=48 random pairs up to 8 apart, chi_max=128",
             "value": n2q / dt, "unit": "2q gates/s", "n_gpus": 1, "steps": 1, "warmup": 0,
             "ms_per_step": 1e3 * dt, "higher_is_better": True, "scaling": "weak",
@@ -394,7 +416,7 @@ def bench_nonlocal(args):
             "config": {"workload": f"{count} gates, {n2q} two-qubit ({swaps} SWAPs added), "
                                    f"cutoff 1e-10, {args.storage}"},
             "fp64_per_gate_gates_per_s": n2q / dt_ref, "fidelity_err_vs_fp64": 1 - fid,
-            "max_bond": int(max(m.bond_dims()))}
+            "max_bond": int(max(m.bond_dims())), "cpu_baseline": cpu}
 
 
 def bench_sample(args):
@@ -496,6 +518,11 @@ def bench_qasm(args):
     a, b = res["parsed"][0], res["fused"][0]
     fid = abs(a.overlap(b)) ** 2 / (a.norm2() * b.norm2())
     n2q = res["parsed"][2]
+    cpu = None
+    if not args.no_cpu:  # the oracle on the fused circuit, rate in gates of the parsed one
+        cpu = oracle_rate(fused, n, chi, 1e-10, args.cpu_threads)
+        cpu["value"] *= n2q / max(1, res["fused"][2])
+        cpu["unit"] = "2q gates/s (of the parsed circuit)"
     return {"metric": "circuit 2q gates/s, 64-qubit Heisenberg Trotter circuit from OpenQASM, fused",
             "value": n2q / res["fused"][1], "unit": "2q gates/s (of the parsed circuit)",
             "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": 1e3 * res["fused"][1],
@@ -507,7 +534,7 @@ def bench_qasm(args):
             "two_qubit_gates": {"parsed": n2q, "fused": res["fused"][2]},
             "seconds": {"parsed": res["parsed"][1], "fused": res["fused"][1]},
             "fused_vs_parsed_1_minus_F": 1 - fid,
-            "max_bond": int(max(b.bond_dims()))}
+            "max_bond": int(max(b.bond_dims())), "cpu_baseline": cpu}
 
 
 def main():
