@@ -6,16 +6,15 @@
 // blocks of 32.  A sweep runs the round-robin tournament over the blocks; in
 // one round every block is paired with one other block, and for every pair:
 //
-//   k_gram : G = X_IJ^H X_IJ (64x64 Hermitian), split over row chunks;
-//   k_eig  : G = V D V^H by cyclic two-sided Jacobi in LDS; a pair whose
-//            columns are already orthogonal to tolerance is left alone;
-//   k_rot  : X_IJ <- X_IJ V (and J_IJ <- J_IJ V).
+//   k_gram_mfma2 : G = X_IJ^H X_IJ (64x64 Hermitian), split over row chunks;
+//   k_eig        : G = V D V^H by cyclic two-sided Jacobi in LDS; a pair whose
+//                  columns are already orthogonal to tolerance is left alone;
+//   k_rot_mfma3  : X_IJ <- X_IJ V (and J_IJ <- J_IJ V).
 //
 // All pairs of all gates of a batch run in the same launches.  The sweep
 // ends the rounds; a gate converges after a sweep in which no pair rotated.
 // Then k_colnorm gives sigma_j^2 = ||x_j||^2 and k_trunc sorts them and
 // applies the truncation rule.
-#include <cstdlib>
 
 #include "tnsim_internal.h"
 #include "tn_complex.h"
@@ -138,62 +137,6 @@ void launch_begin_sweep(hipStream_t st, const GateDesc *d, int ng) {
 
 // ---------------------------------------------------------------- Gram of a column pair
 
-constexpr int GK = 32;  // rows per LDS tile
-
-__global__ __launch_bounds__(256) void k_gram(const GateDesc *descs, int round, int ksplit) {
-  const GateDesc &d = descs[blockIdx.y];
-  const int pairIdx = blockIdx.x / ksplit, kc = blockIdx.x % ksplit;
-  if (!d.sc->active || round >= d.nblk - 1 || pairIdx >= d.nblk / 2) return;
-  int I, J;
-  rr_pair(round, pairIdx, d.nblk, I, J);
-  if (pair_known_orthogonal(d, I, J)) return;
-  int chunk = (d.rows + ksplit - 1) / ksplit;
-  chunk = (chunk + GK - 1) / GK * GK;
-  const int rbeg = kc * chunk;
-  const int rend = min(d.rows, rbeg + chunk);
-
-  __shared__ double2 Xs[GK][PW + 1];
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  double2 acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; i++)
-#pragma unroll
-    for (int j = 0; j < 4; j++) acc[i][j] = make_double2(0.0, 0.0);
-
-  const int lcol = tid >> 2, lr = (tid & 3) * 8;
-  const double2 *xcol = d.X + (size_t)pair_col(I, J, lcol) * d.ldx;
-  for (int r0 = rbeg; r0 < rend; r0 += GK) {
-#pragma unroll
-    for (int j = 0; j < 8; j++) {
-      int r = r0 + lr + j;
-      Xs[lr + j][lcol] = r < rend ? xcol[r] : make_double2(0.0, 0.0);
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int k = 0; k < GK; k++) {
-      double2 a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; i++) a[i] = Xs[k][ty + 16 * i];
-#pragma unroll
-      for (int j = 0; j < 4; j++) b[j] = Xs[k][tx + 16 * j];
-#pragma unroll
-      for (int i = 0; i < 4; i++)
-#pragma unroll
-        for (int j = 0; j < 4; j++) cfmac(acc[i][j], a[i], b[j]);
-    }
-    __syncthreads();
-  }
-  if (tid == 0 && d.ctr && rend > rbeg) {
-    atomicAdd(&d.ctr[CTR_GRAM_FLOP], 8ull * (rend - rbeg) * (PW * (PW + 1) / 2));
-    atomicAdd(&d.ctr[CTR_GRAM_BYTE], 16ull * (rend - rbeg) * PW + 16ull * PW * PW);
-  }
-  double2 *G = d.Gp + ((size_t)kc * d.gpStride + pairIdx) * (PW * PW);
-#pragma unroll
-  for (int i = 0; i < 4; i++)
-#pragma unroll
-    for (int j = 0; j < 4; j++) G[(ty + 16 * i) * PW + tx + 16 * j] = acc[i][j];
-}
-
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
 // v_mfma_f64_16x16x4f64 operand layout (lane l = 0..63): A[l%16][l/16],
@@ -204,99 +147,9 @@ __device__ __forceinline__ d4_t mfma64(double a, double b, d4_t c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// Same pair Gram on float64 matrix cores (v_mfma_f64_16x16x4).  G is
-// Hermitian, so only the 10 upper 16x16 tiles (TI <= TJ) are computed; the
-// pair solve mirrors the lower triangle.  Five wavefronts take two tiles each;
-// the first four load the rows.
-constexpr int GRAM_WAVES = 5;
-constexpr int GKM = 32;  // rows per LDS tile
-__constant__ int kGramTiles[GRAM_WAVES][2][2] = {{{0, 0}, {0, 1}}, {{0, 2}, {0, 3}},
-                                                 {{1, 1}, {1, 2}}, {{1, 3}, {2, 2}},
-                                                 {{2, 3}, {3, 3}}};
-
-__global__ __launch_bounds__(64 * GRAM_WAVES) void k_gram_mfma(const GateDesc *descs, int round,
-                                                               int ksplit) {
-  const GateDesc &d = descs[blockIdx.y];
-  const int pairIdx = blockIdx.x / ksplit, kc = blockIdx.x % ksplit;
-  if (!d.sc->active || round >= d.nblk - 1 || pairIdx >= d.nblk / 2) return;
-  int I, J;
-  rr_pair(round, pairIdx, d.nblk, I, J);
-  if (pair_known_orthogonal(d, I, J)) return;
-  int chunk = (d.rows + ksplit - 1) / ksplit;
-  chunk = (chunk + GKM - 1) / GKM * GKM;
-  const int rbeg = kc * chunk;
-  const int rend = min(d.rows, rbeg + chunk);
-
-  __shared__ double2 Xs[GKM][PW + 1];
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int l16 = lane & 15, lg = lane >> 4;
-  const bool loader = tid < 256;  // 64 columns x 4 groups of 8 rows
-  int tI[2], tJ[2];
-#pragma unroll
-  for (int t = 0; t < 2; t++) {
-    tI[t] = kGramTiles[wave][t][0];
-    tJ[t] = kGramTiles[wave][t][1];
-  }
-  d4_t accR[2], accI[2];
-#pragma unroll
-  for (int t = 0; t < 2; t++) {
-    accR[t] = d4_t{0.0, 0.0, 0.0, 0.0};
-    accI[t] = d4_t{0.0, 0.0, 0.0, 0.0};
-  }
-  const int lcol = (tid >> 2) & (PW - 1), lr = (tid & 3) * (GKM / 4);
-  const double2 *xcol = d.X + (size_t)pair_col(I, J, lcol) * d.ldx;
-  double2 pre[GKM / 4];  // next row tile, loaded while the current one is multiplied
-  if (loader) {
-#pragma unroll
-    for (int j = 0; j < GKM / 4; j++) {
-      int r = rbeg + lr + j;
-      pre[j] = r < rend ? xcol[r] : make_double2(0.0, 0.0);
-    }
-  }
-  for (int r0 = rbeg; r0 < rend; r0 += GKM) {
-    if (loader) {
-#pragma unroll
-      for (int j = 0; j < GKM / 4; j++) Xs[lr + j][lcol] = pre[j];
-    }
-    __syncthreads();
-    if (loader && r0 + GKM < rend) {
-#pragma unroll
-      for (int j = 0; j < GKM / 4; j++) {
-        int r = r0 + GKM + lr + j;
-        pre[j] = r < rend ? xcol[r] : make_double2(0.0, 0.0);
-      }
-    }
-#pragma unroll
-    for (int kk = 0; kk < GKM; kk += 4) {
-      const int row = kk + lg;
-      // G_pq = sum_r conj(x_rp) x_rq
-#pragma unroll
-      for (int t = 0; t < 2; t++) {
-        const double2 xa = Xs[row][tI[t] * 16 + l16];
-        const double2 xb = Xs[row][tJ[t] * 16 + l16];
-        accR[t] = mfma64(xa.x, xb.x, accR[t]);
-        accR[t] = mfma64(xa.y, xb.y, accR[t]);
-        accI[t] = mfma64(xa.x, xb.y, accI[t]);
-        accI[t] = mfma64(-xa.y, xb.x, accI[t]);
-      }
-    }
-    __syncthreads();
-  }
-  if (tid == 0 && d.ctr && rend > rbeg) {
-    atomicAdd(&d.ctr[CTR_GRAM_FLOP], 8ull * (rend - rbeg) * (PW * (PW + 1) / 2));
-    atomicAdd(&d.ctr[CTR_GRAM_BYTE], 16ull * (rend - rbeg) * PW + 16ull * PW * PW);
-  }
-  double2 *G = d.Gp + ((size_t)kc * d.gpStride + pairIdx) * (PW * PW);
-#pragma unroll
-  for (int t = 0; t < 2; t++)
-#pragma unroll
-    for (int e = 0; e < 4; e++) {
-      int p = tI[t] * 16 + lg + 4 * e, q = tJ[t] * 16 + l16;
-      G[p * PW + q] = make_double2(accR[t][e], accI[t][e]);
-    }
-}
-
-// Pair Gram, variant 2: no LDS staging.  In one k-step (4 rows) lane l reads
+// Pair Gram on float64 matrix cores (v_mfma_f64_16x16x4), without LDS
+// staging.  G is Hermitian, so only its 10 upper 16x16 tiles are computed (the
+// pair solve mirrors the lower triangle).  In one k-step (4 rows) lane l reads
 // row 4 s + l/16 of the pair's columns 16 t + l%16 (t = 0..3): that is both
 // the A operand (conjugated) and the B operand of v_mfma_f64_16x16x4 for
 // every tile, so four loads feed all 10 upper tiles (40 MFMAs).  Each
@@ -604,265 +457,7 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(const GateDesc *descs, int 
 
 // ---------------------------------------------------------------- apply a pair rotation
 
-constexpr int RR = 64;  // rows per workgroup
-
-__global__ __launch_bounds__(256) void k_rot(const GateDesc *descs, int round) {
-  const GateDesc &d = descs[blockIdx.y];
-  if (!d.sc->active || round >= d.nblk - 1) return;
-  const int npairs = d.nblk / 2;
-  const int xchunks = (d.rows + RR - 1) / RR;
-  const int jchunks = d.trans ? (d.m + RR - 1) / RR : 0;
-  const int per = xchunks + jchunks;
-  const int pairIdx = blockIdx.x / per, chunk = blockIdx.x % per;
-  if (pairIdx >= npairs) return;
-  if (!d.pairFlag[pairIdx]) return;
-  int I, J;
-  rr_pair(round, pairIdx, d.nblk, I, J);
-  double2 *base;
-  int ld, nrows, r0;
-  if (chunk < xchunks) {
-    base = d.X;
-    ld = d.ldx;
-    nrows = d.rows;
-    r0 = chunk * RR;
-  } else {
-    base = d.J;
-    ld = d.ldj;
-    nrows = d.m;
-    r0 = (chunk - xchunks) * RR;
-  }
-  __shared__ double2 Xs[RR * LDG];  // [row][col]
-  __shared__ double2 Vs[PW * LDG];  // [k][col]
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  const double2 *V = d.V + (size_t)pairIdx * (PW * PW);
-  for (int e = tid; e < PW * PW; e += 256) Vs[(e / PW) * LDG + e % PW] = V[e];
-  {
-    // column-major source: thread reads consecutive rows of one column
-    for (int e = tid; e < RR * PW; e += 256) {
-      int r = e % RR, c = e / RR;
-      int gr = r0 + r;
-      Xs[r * LDG + c] =
-          gr < nrows ? base[(size_t)pair_col(I, J, c) * ld + gr] : make_double2(0.0, 0.0);
-    }
-  }
-  if (tid == 0 && d.ctr) {
-    unsigned long long nr = (unsigned long long)min(RR, nrows - r0);
-    atomicAdd(&d.ctr[CTR_ROT_FLOP], 8ull * nr * PW * PW);
-    atomicAdd(&d.ctr[CTR_ROT_BYTE], 32ull * nr * PW + 16ull * PW * PW);
-  }
-  __syncthreads();
-  double2 acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; i++)
-#pragma unroll
-    for (int j = 0; j < 4; j++) acc[i][j] = make_double2(0.0, 0.0);
-#pragma unroll 4
-  for (int k = 0; k < PW; k++) {
-    double2 a[4], b[4];
-#pragma unroll
-    for (int i = 0; i < 4; i++) a[i] = Xs[(ty + 16 * i) * LDG + k];
-#pragma unroll
-    for (int j = 0; j < 4; j++) b[j] = Vs[k * LDG + tx + 16 * j];
-#pragma unroll
-    for (int i = 0; i < 4; i++)
-#pragma unroll
-      for (int j = 0; j < 4; j++) cfma(acc[i][j], a[i], b[j]);
-  }
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < 4; i++)
-#pragma unroll
-    for (int j = 0; j < 4; j++) Xs[(ty + 16 * i) * LDG + tx + 16 * j] = acc[i][j];
-  __syncthreads();
-  for (int e = tid; e < RR * PW; e += 256) {
-    int r = e % RR, c = e / RR;
-    int gr = r0 + r;
-    if (gr < nrows) base[(size_t)pair_col(I, J, c) * ld + gr] = Xs[r * LDG + c];
-  }
-}
-
-// Same pair rotation on float64 matrix cores.
-__global__ __launch_bounds__(256) void k_rot_mfma(const GateDesc *descs, int round) {
-  const GateDesc &d = descs[blockIdx.y];
-  if (!d.sc->active || round >= d.nblk - 1) return;
-  const int npairs = d.nblk / 2;
-  const int xchunks = (d.rows + RR - 1) / RR;
-  const int jchunks = d.trans ? (d.m + RR - 1) / RR : 0;
-  const int per = xchunks + jchunks;
-  const int pairIdx = blockIdx.x / per, chunk = blockIdx.x % per;
-  if (pairIdx >= npairs) return;
-  if (!d.pairFlag[pairIdx]) return;
-  int I, J;
-  rr_pair(round, pairIdx, d.nblk, I, J);
-  double2 *base;
-  int ld, nrows, r0;
-  if (chunk < xchunks) {
-    base = d.X;
-    ld = d.ldx;
-    nrows = d.rows;
-    r0 = chunk * RR;
-  } else {
-    base = d.J;
-    ld = d.ldj;
-    nrows = d.m;
-    r0 = (chunk - xchunks) * RR;
-  }
-  __shared__ double2 Xs[RR * LDG];  // [row][col]
-  __shared__ double2 Vs[PW * LDG];  // [k][col]
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32, l16 = lane & 15, lg = lane >> 4;
-  const double2 *V = d.V + (size_t)pairIdx * (PW * PW);
-  for (int e = tid; e < PW * PW; e += 256) Vs[(e / PW) * LDG + e % PW] = V[e];
-  for (int e = tid; e < RR * PW; e += 256) {
-    int r = e % RR, c = e / RR;
-    int gr = r0 + r;
-    Xs[r * LDG + c] =
-        gr < nrows ? base[(size_t)pair_col(I, J, c) * ld + gr] : make_double2(0.0, 0.0);
-  }
-  if (tid == 0 && d.ctr) {
-    unsigned long long nr = (unsigned long long)min(RR, nrows - r0);
-    atomicAdd(&d.ctr[CTR_ROT_FLOP], 8ull * nr * PW * PW);
-    atomicAdd(&d.ctr[CTR_ROT_BYTE], 32ull * nr * PW + 16ull * PW * PW);
-  }
-  __syncthreads();
-  d4_t accR[2][2], accI[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; i++)
-#pragma unroll
-    for (int j = 0; j < 2; j++) {
-      accR[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
-      accI[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
-    }
-#pragma unroll 4
-  for (int k0 = 0; k0 < PW; k0 += 4) {
-    const int k = k0 + lg;
-    double2 xa[2], vb[2];
-#pragma unroll
-    for (int t = 0; t < 2; t++) {
-      xa[t] = Xs[(wr + t * 16 + l16) * LDG + k];
-      vb[t] = Vs[k * LDG + wc + t * 16 + l16];
-    }
-#pragma unroll
-    for (int ti = 0; ti < 2; ti++)
-#pragma unroll
-      for (int tj = 0; tj < 2; tj++) {
-        accR[ti][tj] = mfma64(xa[ti].x, vb[tj].x, accR[ti][tj]);
-        accR[ti][tj] = mfma64(-xa[ti].y, vb[tj].y, accR[ti][tj]);
-        accI[ti][tj] = mfma64(xa[ti].x, vb[tj].y, accI[ti][tj]);
-        accI[ti][tj] = mfma64(xa[ti].y, vb[tj].x, accI[ti][tj]);
-      }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int ti = 0; ti < 2; ti++)
-#pragma unroll
-    for (int tj = 0; tj < 2; tj++)
-#pragma unroll
-      for (int e = 0; e < 4; e++) {
-        int r = wr + ti * 16 + lg + 4 * e, c = wc + tj * 16 + l16;
-        Xs[r * LDG + c] = make_double2(accR[ti][tj][e], accI[ti][tj][e]);
-      }
-  __syncthreads();
-  for (int e = tid; e < RR * PW; e += 256) {
-    int r = e % RR, c = e / RR;
-    int gr = r0 + r;
-    if (gr < nrows) base[(size_t)pair_col(I, J, c) * ld + gr] = Xs[r * LDG + c];
-  }
-}
-
-// Pair rotation, variant 2: X operands go straight from global memory into the
-// matrix cores (lanes of a 16-group read 16 consecutive rows of one column, a
-// coalesced segment); only V is staged in LDS, so two workgroups fit per CU.
-// Each workgroup handles d.rotRows rows (V is staged once for all of them:
-// 256 when the batch fills the GPU, fewer when only a few pairs are left);
-// results stay in registers until every wavefront has read its inputs, then
-// overwrite X in place.
-
-__global__ __launch_bounds__(256) void k_rot_mfma2(const GateDesc *descs, int round) {
-  const GateDesc &d = descs[blockIdx.y];
-  if (!d.sc->active || round >= d.nblk - 1) return;
-  const int npairs = d.nblk / 2;
-  const int RR2 = d.rotRows;
-  const int xchunks = (d.rows + RR2 - 1) / RR2;
-  const int jchunks = d.trans ? (d.m + RR2 - 1) / RR2 : 0;
-  const int per = xchunks + jchunks;
-  const int pairIdx = blockIdx.x / per, chunk = blockIdx.x % per;
-  if (pairIdx >= npairs) return;
-  if (!d.pairFlag[pairIdx]) return;
-  int I, J;
-  rr_pair(round, pairIdx, d.nblk, I, J);
-  double2 *base;
-  int ld, nrows, r0;
-  if (chunk < xchunks) {
-    base = d.X;
-    ld = d.ldx;
-    nrows = d.rows;
-    r0 = chunk * RR2;
-  } else {
-    base = d.J;
-    ld = d.ldj;
-    nrows = d.m;
-    r0 = (chunk - xchunks) * RR2;
-  }
-  __shared__ double2 Vs[PW * LDG];  // [k][col]
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32, l16 = lane & 15, lg = lane >> 4;
-  const double2 *V = d.V + (size_t)pairIdx * (PW * PW);
-  for (int e = tid; e < PW * PW; e += 256) Vs[(e / PW) * LDG + e % PW] = V[e];
-  if (tid == 0 && d.ctr) {
-    unsigned long long nr = (unsigned long long)min(RR2, nrows - r0);  // all row blocks
-    atomicAdd(&d.ctr[CTR_ROT_FLOP], 8ull * nr * PW * PW);
-    atomicAdd(&d.ctr[CTR_ROT_BYTE], 32ull * nr * PW + 16ull * PW * PW);
-  }
-  __syncthreads();
-  for (int rb = r0; rb < min(nrows, r0 + RR2); rb += 64) {
-    d4_t accR[2][2], accI[2][2];
-#pragma unroll
-    for (int i = 0; i < 2; i++)
-#pragma unroll
-      for (int j = 0; j < 2; j++) {
-        accR[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
-        accI[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
-      }
-    int grow[2];
-#pragma unroll
-    for (int t = 0; t < 2; t++) grow[t] = rb + wr + t * 16 + l16;
-#pragma unroll 4
-    for (int k0 = 0; k0 < PW; k0 += 4) {
-      const int k = k0 + lg;
-      const double2 *xc = base + (size_t)pair_col(I, J, k) * ld;
-      double2 xa[2], vb[2];
-#pragma unroll
-      for (int t = 0; t < 2; t++) {
-        xa[t] = grow[t] < nrows ? xc[grow[t]] : make_double2(0.0, 0.0);
-        vb[t] = Vs[k * LDG + wc + t * 16 + l16];
-      }
-#pragma unroll
-      for (int ti = 0; ti < 2; ti++)
-#pragma unroll
-        for (int tj = 0; tj < 2; tj++) {
-          accR[ti][tj] = mfma64(xa[ti].x, vb[tj].x, accR[ti][tj]);
-          accR[ti][tj] = mfma64(-xa[ti].y, vb[tj].y, accR[ti][tj]);
-          accI[ti][tj] = mfma64(xa[ti].x, vb[tj].y, accI[ti][tj]);
-          accI[ti][tj] = mfma64(xa[ti].y, vb[tj].x, accI[ti][tj]);
-        }
-    }
-    __syncthreads();  // every wavefront has read this block's rows of X
-#pragma unroll
-    for (int ti = 0; ti < 2; ti++)
-#pragma unroll
-      for (int tj = 0; tj < 2; tj++)
-#pragma unroll
-        for (int e = 0; e < 4; e++) {
-          int r = rb + wr + ti * 16 + lg + 4 * e, c = wc + tj * 16 + l16;
-          if (r < nrows)
-            base[(size_t)pair_col(I, J, c) * ld + r] =
-                make_double2(accR[ti][tj][e], accI[ti][tj][e]);
-        }
-  }
-}
-
-// Pair rotation, variant 3: the transposed product (X V)^T = V^T X^T, so that
+// Pair rotation on float64 matrix cores, as the transposed product (X V)^T = V^T X^T, so that
 // the X operand of v_mfma_f64_16x16x4 (B: 16 lanes = 16 consecutive rows of
 // one column) and the result (16 lanes = 16 consecutive rows of one column)
 // are both contiguous 256-byte segments.  A wavefront owns whole 16-row tiles
@@ -960,42 +555,11 @@ __global__ __launch_bounds__(256, 2) void k_rot_mfma3(const GateDesc *descs, int
   }
 }
 
-int g_rot_variant = -1;  // -1: read TNSIM_ROT_KERNEL once
-
-static int rot_variant() {
-  if (g_rot_variant < 0) {
-    const char *e = getenv("TNSIM_ROT_KERNEL");  // "1", "2": earlier variants
-    g_rot_variant = (e && (e[0] == '1' || e[0] == '2')) ? e[0] - '0' : 3;
-  }
-  return g_rot_variant;
-}
-
-int g_jacobi_mfma = -1;  // -1: read TNSIM_JACOBI_KERNELS once
-
-static bool use_mfma() {
-  if (g_jacobi_mfma < 0) {
-    const char *e = getenv("TNSIM_JACOBI_KERNELS");
-    g_jacobi_mfma = (e && e[0] == 'v') ? 0 : 1;  // "valu" selects the vector-ALU kernels
-  }
-  return g_jacobi_mfma != 0;
-}
-
 void launch_gram(hipStream_t st, const GateDesc *d, int ng, int round, int max_pairs,
                  int ksplit) {
   if (ng <= 0) return;
-  static int variant = -1;  // TNSIM_GRAM_KERNEL=1 selects the LDS-staged kernel
-  if (variant < 0) {
-    const char *e = getenv("TNSIM_GRAM_KERNEL");
-    variant = (e && e[0] == '1') ? 1 : 2;
-  }
-  if (use_mfma() && variant == 2)
-    hipLaunchKernelGGL(k_gram_mfma2, dim3(max_pairs * ksplit, ng), dim3(256), 0, st, d, round,
-                       ksplit);
-  else if (use_mfma())
-    hipLaunchKernelGGL(k_gram_mfma, dim3(max_pairs * ksplit, ng), dim3(64 * GRAM_WAVES), 0, st, d,
-                       round, ksplit);
-  else
-    hipLaunchKernelGGL(k_gram, dim3(max_pairs * ksplit, ng), dim3(256), 0, st, d, round, ksplit);
+  hipLaunchKernelGGL(k_gram_mfma2, dim3(max_pairs * ksplit, ng), dim3(256), 0, st, d, round,
+                     ksplit);
 }
 
 void launch_eig(hipStream_t st, const GateDesc *d, int ng, int round, int max_pairs, int ksplit) {
@@ -1017,17 +581,8 @@ void launch_gather_sc(hipStream_t st, const GateDesc *d, int ng, SlotScalars *ou
 void launch_rot(hipStream_t st, const GateDesc *d, int ng, int round, int max_pairs,
                 int max_rows, int max_m, int rot_rows) {
   if (ng <= 0) return;
-  int per = (max_rows + RR - 1) / RR + (max_m + RR - 1) / RR;
-  if (use_mfma() && rot_variant() >= 2) {
-    int per2 = (max_rows + rot_rows - 1) / rot_rows + (max_m + rot_rows - 1) / rot_rows;
-    if (rot_variant() == 3)
-      hipLaunchKernelGGL(k_rot_mfma3, dim3(max_pairs * per2, ng), dim3(256), 0, st, d, round);
-    else
-      hipLaunchKernelGGL(k_rot_mfma2, dim3(max_pairs * per2, ng), dim3(256), 0, st, d, round);
-  } else if (use_mfma())
-    hipLaunchKernelGGL(k_rot_mfma, dim3(max_pairs * per, ng), dim3(256), 0, st, d, round);
-  else
-    hipLaunchKernelGGL(k_rot, dim3(max_pairs * per, ng), dim3(256), 0, st, d, round);
+  const int per = (max_rows + rot_rows - 1) / rot_rows + (max_m + rot_rows - 1) / rot_rows;
+  hipLaunchKernelGGL(k_rot_mfma3, dim3(max_pairs * per, ng), dim3(256), 0, st, d, round);
 }
 
 // ---------------------------------------------------------------- sort + truncate

@@ -372,9 +372,18 @@ class MPS:
             seg.ctypes.data, seg.size, pp, cf.ctypes.data, cf.size, C.byref(out)),
             "forward_checkpointed")
         self._n_params = ang.size
+        # the handle keeps the checkpoints of this forward only: a later
+        # forward replaces them, so each forward gets a new id
+        self._fwd_id = getattr(self, "_fwd_id", 0) + 1
         return out.value
 
+    @property
+    def forward_id(self) -> int:
+        """Id of the last forward_checkpointed call (0 before the first)."""
+        return getattr(self, "_fwd_id", 0)
+
     def backward(self, dloss: float = 1.0) -> np.ndarray:
+        """Gradient of the loss of the last forward_checkpointed call."""
         g = np.zeros(max(self._n_params, 1), dtype=np.float64)
         self._chk(lib().tnsim_backward(self._h, dloss, g.ctypes.data), "backward")
         return g[: self._n_params]
@@ -518,11 +527,18 @@ def _autograd_function():
             a = angles.detach().to("cpu", torch.float64).numpy()
             loss = mps.forward_checkpointed(gates, pg, ax, a, seg, paulis, coeffs)
             ctx.mps = mps
+            ctx.fwd_id = mps.forward_id
             ctx.dev = angles.device
             return torch.tensor(loss, dtype=torch.float64, device=angles.device)
 
         @staticmethod
         def backward(ctx, grad_out):
+            # the handle holds the checkpoints of its last forward only
+            if ctx.mps.forward_id != ctx.fwd_id:
+                raise RuntimeError(
+                    "PauliSumLoss.backward: the MPS ran another forward after this loss was "
+                    "computed, so its checkpoints belong to that forward; use one MPS per "
+                    "loss that is differentiated")
             g = ctx.mps.backward(float(grad_out))
             return torch.from_numpy(g).to(ctx.dev), None, None
 

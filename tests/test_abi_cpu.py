@@ -108,3 +108,36 @@ def test_sample_workspace_bytes():
     assert T.lib().tnsim_sample_workspace_bytes(C.byref(cfg), 0) == 0
     bad = T.Config(1, 1024, 1e-12, 0, 1, 0, 0.0, 0, 1)
     assert T.lib().tnsim_sample_workspace_bytes(C.byref(bad), 16) == 0
+
+
+class _StubMPS:
+    """Host stand-in for an MPS handle: counts forwards like the binding does,
+    so the autograd function's bookkeeping is checked without a device."""
+
+    def __init__(self):
+        self.calls = []
+
+    forward_id = property(lambda self: len(self.calls))
+
+    def forward_checkpointed(self, gates, pg, ax, angles, seg, paulis, coeffs):
+        self.calls.append(np.array(angles))
+        return float(np.sum(np.cos(angles)))
+
+    def backward(self, dloss):
+        return -dloss * np.sin(self.calls[-1])
+
+
+def test_pauli_sum_loss_rejects_a_stale_backward():
+    """Two forwards on one handle: the first loss's backward must raise, since
+    the handle now holds the second forward's checkpoints."""
+    torch = pytest.importorskip("torch")
+    m = _StubMPS()
+    spec = ([], [], [], [0], [], [])
+    a = torch.tensor([0.3, 1.1], dtype=torch.float64, requires_grad=True)
+    b = torch.tensor([2.0, -0.5], dtype=torch.float64, requires_grad=True)
+    la = T.pauli_sum_loss(a, m, spec)
+    lb = T.pauli_sum_loss(b, m, spec)
+    lb.backward()
+    assert np.allclose(b.grad.numpy(), -np.sin([2.0, -0.5]))
+    with pytest.raises(RuntimeError, match="another forward"):
+        la.backward()

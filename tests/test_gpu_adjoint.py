@@ -113,3 +113,23 @@ def test_autograd_function(T):
     ref = O.parameter_shift(lambda x: W.ansatz_gates(x, n, nl), angles, n, 32, 0.0, spec[4],
                             spec[5])
     assert np.linalg.norm(a.grad.numpy() - ref) / np.linalg.norm(ref) < 1e-8
+
+
+def test_autograd_two_forwards_on_one_handle(T):
+    """A second forward on the same MPS replaces the checkpoints: the second
+    loss differentiates correctly and the first one's backward raises."""
+    import torch
+
+    n, nl = 5, 2
+    spec = _spec(n, nl)
+    m = T.MPS(n, 32, 0.0)
+    a1 = torch.tensor(W.ansatz_angles(n, nl, 3), dtype=torch.float64, requires_grad=True)
+    a2 = torch.tensor(W.ansatz_angles(n, nl, 4), dtype=torch.float64, requires_grad=True)
+    l1 = T.pauli_sum_loss(a1, m, spec)
+    l2 = T.pauli_sum_loss(a2, m, spec)
+    l2.backward()
+    ref = O.parameter_shift(lambda x: W.ansatz_gates(x, n, nl), a2.detach().numpy(), n, 32, 0.0,
+                            spec[4], spec[5])
+    assert np.linalg.norm(a2.grad.numpy() - ref) / np.linalg.norm(ref) < 1e-8
+    with pytest.raises(RuntimeError, match="another forward"):
+        l1.backward()
