@@ -80,6 +80,7 @@ def lib():
         L.om_amplitude.argtypes = [P, C.POINTER(C.c_uint8), dp, dp]
         L.om_statevector.argtypes = [P, dp]
         L.om_sample.argtypes = [P, C.c_int, dp, C.POINTER(C.c_uint8), dp]
+        L.om_canonicalize.argtypes = [P, C.c_int]
         L.om_set_threads.argtypes = [C.c_int]
         L.om_get_threads.restype = C.c_int
         _lib = L
@@ -244,6 +245,12 @@ class OracleMPS:
                                     bits.ctypes.data_as(C.POINTER(C.c_uint8)), _dp(logp)),
                     "sample")
         return bits, logp
+
+    def canonicalize(self, truncate: bool = False) -> None:
+        """Exact left-canonical form with Schmidt values on every bond, from any
+        gauge (two SVD sweeps; the state is normalised).  With truncate, the
+        second sweep applies the truncation rule with chi_max and cutoff."""
+        self._check(lib().om_canonicalize(self._h, 1 if truncate else 0), "canonicalize")
 
     def statevector(self) -> np.ndarray:
         out = np.zeros(2 ** self.n, dtype=np.complex128)

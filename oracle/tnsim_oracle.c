@@ -527,6 +527,140 @@ int om_apply_2q(om_mps *m, int q0, int q1, const double *g_ri) {
   return OM_OK;
 }
 
+/* ------------------------------------------------------------------ canonical form */
+
+/* Canonicalisation (Sec. IV.A: the MPS is brought to left- and right-canonical
+   form before sampling).  Restores the gauge this simulator keeps (every site
+   left-canonical, lambda_q the Schmidt values of bond q) exactly, from any
+   gauge:
+   1. left to right, q = 0 .. n-2: SVD of site q as a (dim[q]*2) x dim[q+1]
+      matrix, A_q <- U (numerically non-zero columns only), and
+      A_{q+1} <- (U^H A_q) A_{q+1}; afterwards sites 0 .. n-2 are
+      left-canonical and site n-1 carries the norm, which is divided out;
+   2. right to left, b = n-2 .. 0: the Schmidt decomposition of bond b is the
+      SVD of C[a, (t, c)] = A_{b+1}[a, t, c] * lambda_{b+1}[c] (lambda = 1 at
+      the right end): sites 0 .. b form an orthonormal left basis and the part
+      right of bond b+1 was put in its Schmidt basis by the previous step.
+      C = U S V^H gives lambda_b = S / N, A_b <- A_b U, A_{b+1} <- U^H A_{b+1} / N.
+   With truncate = 0 only numerically zero values are dropped (the floor of
+   the truncation rule).  With truncate = 1, step 2 applies the truncation
+   rule with chi_max and cutoff, adding each cut's discarded weight to the
+   statistics; a cut changes the state, so the bonds right of it (already
+   swept) no longer carry its Schmidt values, and both steps run once more
+   without truncation.  The state is normalised. */
+static int canon_pass(om_mps *m, int truncate) {
+  const int n = m->n;
+  /* step 1 */
+  for (int q = 0; q + 1 < n; q++) {
+    const int rows = 2 * m->dim[q], cols = m->dim[q + 1], r = rows < cols ? rows : cols;
+    cplx *M = (cplx *)xalloc(sizeof(cplx) * (size_t)rows * cols); /* column-major */
+    for (int i = 0; i < rows; i++)
+      for (int j = 0; j < cols; j++) M[(size_t)j * rows + i] = m->A[q][(size_t)i * cols + j];
+    cplx *U = (cplx *)xalloc(sizeof(cplx) * (size_t)rows * r);
+    double *sig = (double *)xalloc(sizeof(double) * r);
+    int sw = svd_left(M, rows, cols, m->tol, m->max_sweeps, U, sig);
+    if (sw < 0) { free(M); free(U); free(sig); return OM_E_NOCONV; }
+    int k;
+    om_truncation(sig, r, rows, 1 << 30, 0.0, &k, NULL, NULL);
+    /* R = U_k^H M  (k x cols) */
+    cplx *R = (cplx *)xalloc(sizeof(cplx) * (size_t)k * cols);
+    for (int j = 0; j < k; j++)
+      for (int c = 0; c < cols; c++) {
+        cplx acc = 0.0;
+        for (int i = 0; i < rows; i++) acc += conj(U[(size_t)j * rows + i]) * M[(size_t)c * rows + i];
+        R[(size_t)j * cols + c] = acc;
+      }
+    cplx *nA = (cplx *)xalloc(sizeof(cplx) * (size_t)rows * k);
+    for (int i = 0; i < rows; i++)
+      for (int j = 0; j < k; j++) nA[(size_t)i * k + j] = U[(size_t)j * rows + i];
+    /* A_{q+1} <- R A_{q+1}: (k x cols) (cols x 2 dim[q+2]) */
+    const int w = 2 * m->dim[q + 2];
+    cplx *nB = (cplx *)xalloc(sizeof(cplx) * (size_t)k * w);
+    for (int j = 0; j < k; j++)
+      for (int c = 0; c < cols; c++) {
+        cplx f = R[(size_t)j * cols + c];
+        if (f == 0.0) continue;
+        for (int e = 0; e < w; e++) nB[(size_t)j * w + e] += f * m->A[q + 1][(size_t)c * w + e];
+      }
+    free(m->A[q]);
+    free(m->A[q + 1]);
+    m->A[q] = nA;
+    m->A[q + 1] = nB;
+    m->dim[q + 1] = k;
+    free(m->lam[q]);
+    m->lam[q] = (double *)xalloc(sizeof(double) * k); /* rewritten in step 2 */
+    free(M); free(U); free(sig); free(R);
+  }
+  {
+    const size_t cnt = (size_t)m->dim[n - 1] * 2;
+    double nrm2 = 0.0;
+    for (size_t e = 0; e < cnt; e++) nrm2 += creal(m->A[n - 1][e]) * creal(m->A[n - 1][e]) +
+                                             cimag(m->A[n - 1][e]) * cimag(m->A[n - 1][e]);
+    if (!(nrm2 > 0.0)) return OM_E_ARG; /* the zero vector has no canonical form */
+    const double inv = 1.0 / sqrt(nrm2);
+    for (size_t e = 0; e < cnt; e++) m->A[n - 1][e] *= inv;
+  }
+  /* step 2 */
+  for (int b = n - 2; b >= 0; b--) {
+    const int rows = m->dim[b + 1], chiR = m->dim[b + 2], cols = 2 * chiR;
+    const int r = rows < cols ? rows : cols;
+    const double *lr = (b + 1 <= n - 2) ? m->lam[b + 1] : NULL;
+    cplx *M = (cplx *)xalloc(sizeof(cplx) * (size_t)rows * cols); /* column-major */
+    for (int a = 0; a < rows; a++)
+      for (int t = 0; t < 2; t++)
+        for (int c = 0; c < chiR; c++)
+          M[(size_t)(t * chiR + c) * rows + a] =
+              m->A[b + 1][((size_t)a * 2 + t) * chiR + c] * (lr ? lr[c] : 1.0);
+    cplx *U = (cplx *)xalloc(sizeof(cplx) * (size_t)rows * r);
+    double *sig = (double *)xalloc(sizeof(double) * r);
+    int sw = svd_left(M, rows, cols, m->tol, m->max_sweeps, U, sig);
+    free(M);
+    if (sw < 0) { free(U); free(sig); return OM_E_NOCONV; }
+    int k;
+    double eps, N;
+    om_truncation(sig, r, rows, truncate ? m->chi_max : 1 << 30, truncate ? m->cutoff : 0.0, &k,
+                  &eps, &N);
+    if (!(N > 0.0)) N = 1.0;
+    /* A_b <- A_b U_k  (dim[b]*2 x rows) (rows x k) */
+    const int lb = 2 * m->dim[b];
+    cplx *nA = (cplx *)xalloc(sizeof(cplx) * (size_t)lb * k);
+    for (int i = 0; i < lb; i++)
+      for (int a = 0; a < rows; a++) {
+        cplx f = m->A[b][(size_t)i * rows + a];
+        if (f == 0.0) continue;
+        for (int j = 0; j < k; j++) nA[(size_t)i * k + j] += f * U[(size_t)j * rows + a];
+      }
+    /* A_{b+1} <- U_k^H A_{b+1} / N */
+    cplx *nB = (cplx *)xalloc(sizeof(cplx) * (size_t)k * cols);
+    for (int j = 0; j < k; j++)
+      for (int a = 0; a < rows; a++) {
+        cplx f = conj(U[(size_t)j * rows + a]) / N;
+        for (int e = 0; e < cols; e++) nB[(size_t)j * cols + e] += f * m->A[b + 1][(size_t)a * cols + e];
+      }
+    double *nl = (double *)xalloc(sizeof(double) * k);
+    for (int j = 0; j < k; j++) nl[j] = sig[j] / N;
+    free(m->A[b]);
+    free(m->A[b + 1]);
+    free(m->lam[b]);
+    m->A[b] = nA;
+    m->A[b + 1] = nB;
+    m->lam[b] = nl;
+    m->dim[b + 1] = k;
+    if (truncate) {
+      m->sum_eps += eps;
+      m->prod_keep *= (1.0 - eps);
+    }
+    free(U); free(sig);
+  }
+  return OM_OK;
+}
+
+int om_canonicalize(om_mps *m, int truncate) {
+  int r = canon_pass(m, truncate);
+  if (r == OM_OK && truncate) r = canon_pass(m, 0);
+  return r;
+}
+
 /* Gates of one layer: q1[g] = -1 marks a one-qubit gate (matrix in the first
    4 complex entries of its 16-entry slot).  Qubits must be disjoint. */
 int om_apply_layer(om_mps *m, const int32_t *q0, const int32_t *q1, const double *g_ri,
@@ -583,8 +717,10 @@ static cplx transfer(const om_mps *bra, const om_mps *ket, const int *pidx) {
     int ra = bra->dim[q + 1], rb = ket->dim[q + 1];
     const cplx *B = bra->A[q], *K = ket->A[q];
     const cplx *P = PAULI_M[pidx ? pidx[q] : 0];
-    /* F[a,s',b'] = sum_a' E[a,a'] K[a',s',b'] */
+    /* F[a,s',b'] = sum_a' E[a,a'] K[a',s',b'] (rows a on separate threads; every
+       entry is summed over a' in increasing order, as in a serial run) */
     cplx *F = (cplx *)xalloc(sizeof(cplx) * (size_t)la * 2 * rb);
+#pragma omp parallel for schedule(static) if ((long)la * lb * rb >= 65536)
     for (int a = 0; a < la; a++)
       for (int ap = 0; ap < lb; ap++) {
         cplx e = E[(size_t)a * lb + ap];
@@ -601,11 +737,13 @@ static cplx transfer(const om_mps *bra, const om_mps *ket, const int *pidx) {
           F2[((size_t)a * 2 + s) * rb + bp] = acc;
         }
     free(F);
-    /* E'[b,b'] = sum_{a,s} conj(B[a,s,b]) F2[a,s,b'] */
+    /* E'[b,b'] = sum_{a,s} conj(B[a,s,b]) F2[a,s,b'] (rows b on separate
+       threads; every entry is summed over (a, s) in increasing order) */
     cplx *E2 = (cplx *)xalloc(sizeof(cplx) * (size_t)ra * rb);
-    for (int a = 0; a < la; a++)
-      for (int s = 0; s < 2; s++)
-        for (int b = 0; b < ra; b++) {
+#pragma omp parallel for schedule(static) if ((long)ra * la * rb >= 65536)
+    for (int b = 0; b < ra; b++)
+      for (int a = 0; a < la; a++)
+        for (int s = 0; s < 2; s++) {
           cplx w = conj(B[((size_t)a * 2 + s) * ra + b]);
           if (w == 0.0) continue;
           const cplx *f = F2 + ((size_t)a * 2 + s) * rb;

@@ -49,6 +49,15 @@ MUTANTS = {
                                             "u[(size_t)shot * n + q] < p1 / (p0 + p1) ? 0 : 1"),
     "sampling projects the other outcome": ("const cplx *wb = bit ? w1 : w0;",
                                             "const cplx *wb = bit ? w0 : w1;"),
+    "canonical sweep without the Schmidt weight": (
+        "m->A[b + 1][((size_t)a * 2 + t) * chiR + c] * (lr ? lr[c] : 1.0);",
+        "m->A[b + 1][((size_t)a * 2 + t) * chiR + c] * 1.0;"),
+    "canonical sweep drops the remainder": (
+        "for (int e = 0; e < w; e++) nB[(size_t)j * w + e] += f * m->A[q + 1][(size_t)c * w + e];",
+        "for (int e = 0; e < w; e++) nB[(size_t)j * w + e] += (j == c) * m->A[q + 1][(size_t)c * w + e];"),
+    "canonical sweep rotates with conj(U)": (
+        "for (int j = 0; j < k; j++) nA[(size_t)i * k + j] += f * U[(size_t)j * rows + a];",
+        "for (int j = 0; j < k; j++) nA[(size_t)i * k + j] += f * conj(U[(size_t)j * rows + a]);"),
 }
 
 PIN_CALLS = [
@@ -68,6 +77,9 @@ PIN_CALLS = [
     pins.test_sampling_in_any_gauge,
     pins.test_sampling_product_state_closed_form,
     pins.test_sampling_ghz_closed_form,
+    pins.test_canonicalize_generic_gauge_against_brute_force,
+    pins.test_canonicalize_leaves_a_canonical_state_unchanged,
+    pins.test_canonicalize_truncation_is_the_optimal_cut,
 ]
 
 

@@ -506,3 +506,99 @@ def test_sampling_frequencies():
     freq = np.bincount(idx, minlength=2 ** n) / len(idx)
     prob = np.abs(statevector(n, gates)) ** 2
     assert 0.5 * np.abs(freq - prob).sum() < 0.03
+
+
+# ---------------------------------------------------------------- canonical form (Sec. IV.A)
+
+def _dense(sites):
+    """Dense state of a chain of site tensors (index x = sum_q b_q 2^q),
+    contracted here with numpy, independently of the oracle."""
+    t = np.ones((1, 1), dtype=np.complex128)
+    for a in sites:
+        t = np.einsum("xa,asb->sxb", t, a).reshape(-1, a.shape[2])
+    return t[:, 0]
+
+
+def _generic_mps(n, dims, seed):
+    """Sites of complex Gaussian entries: no canonical structure at all."""
+    rng = np.random.default_rng(seed)
+    sites = [(rng.standard_normal((dims[q], 2, dims[q + 1]))
+              + 1j * rng.standard_normal((dims[q], 2, dims[q + 1]))) for q in range(n)]
+    lams = [np.ones(dims[q + 1]) for q in range(n - 1)]
+    return sites, lams
+
+
+def _left_canonical_defect(m):
+    worst = 0.0
+    for q in range(m.n - 1):
+        a = m.site(q).reshape(-1, m.site(q).shape[2])
+        worst = max(worst, np.max(np.abs(a.conj().T @ a - np.eye(a.shape[1]))))
+    return worst
+
+
+def test_canonicalize_generic_gauge_against_brute_force():
+    """Canonicalisation from a state with no structure (Gaussian sites, bond
+    dimensions above the ranks the cuts allow): afterwards every site is
+    left-canonical, the state equals the input divided by its norm, and
+    lambda_b are the Schmidt values of that state at every cut (numpy SVD of
+    the brute-force state vector); bond b keeps exactly its rank."""
+    n = 9
+    dims = [1, 3, 5, 9, 13, 13, 7, 4, 3, 1]
+    sites, lams = _generic_mps(n, dims, 71)
+    psi = _dense(sites)
+    psi = psi / np.linalg.norm(psi)
+    m = O.OracleMPS(n, 64)
+    m.set_state(sites, lams)
+    m.canonicalize()
+    assert _left_canonical_defect(m) < 1e-12
+    after = _dense([m.site(q) for q in range(n)])
+    assert abs(np.linalg.norm(after) - 1.0) < 1e-12
+    assert abs(abs(np.vdot(psi, after)) - 1.0) < 1e-12
+    assert abs(np.vdot(psi, after) - 1.0) < 1e-12  # same state, same phase (no gate acted)
+    for b in range(n - 1):
+        ref = schmidt_values(psi, n, b)
+        rank = int(np.sum(ref ** 2 > 1e-26))
+        assert m.bond_dims()[b] == min(rank, 2 ** (b + 1), 2 ** (n - b - 1))
+        assert np.max(np.abs(m.lam(b) - ref[: m.bond_dims()[b]])) < 1e-12
+
+
+def test_canonicalize_leaves_a_canonical_state_unchanged():
+    """On an exact canonical state (an untruncated circuit) the Schmidt
+    values are already on the bonds: canonicalisation keeps them and the
+    state."""
+    cfg = W.config_small()
+    m = O.OracleMPS(cfg.n, cfg.chi_max, cfg.cutoff)
+    m.run_layers(cfg.layers)
+    before = m.statevector()
+    lam0 = [m.lam(b) for b in range(cfg.n - 1)]
+    m.canonicalize()
+    assert abs(abs(np.vdot(before, m.statevector())) - 1.0) < 1e-12
+    for b in range(cfg.n - 1):
+        assert np.max(np.abs(m.lam(b) - lam0[b])) < 1e-12
+
+
+def test_canonicalize_truncation_is_the_optimal_cut():
+    """Truncating canonicalisation with chi_max = 12 on an 8-qubit state whose
+    only bond above 12 is the middle one (rank 16): the result is the best
+    rank-12 approximation at that cut (Eckart-Young), so 1 - F equals the
+    discarded weight sum_{j>12} sigma_j^2 of the exact state there, which is
+    also what the statistics record; the other bonds keep their exact ranks."""
+    n = 8
+    layers = W.brickwork_haar(n, 8, 515)
+    full = O.OracleMPS(n, 64)
+    full.run_layers(layers)
+    psi = full.statevector()
+    sig = schmidt_values(psi, n, 3)
+    assert int(np.sum(sig ** 2 > 1e-26)) == 16
+    eps = float(np.sum(sig[12:] ** 2))
+    m = O.OracleMPS(n, 12, 0.0)
+    m.set_state([full.site(q) for q in range(n)], [full.lam(b) for b in range(n - 1)])
+    m.canonicalize(truncate=True)
+    assert list(m.bond_dims()) == [2, 4, 8, 12, 8, 4, 2]
+    after = m.statevector()
+    assert abs((1 - fidelity_dense(psi, after)) - eps) < 1e-12
+    assert abs(m.stats()["sum_eps"] - eps) < 1e-12
+    assert _left_canonical_defect(m) < 1e-12
+    for b in range(n - 1):
+        ref = schmidt_values(after, n, b)
+        assert np.max(np.abs(m.lam(b) - ref[: m.bond_dims()[b]])) < 1e-12
