@@ -637,14 +637,14 @@ static int canon_pass(om_mps *m, int truncate) {
         cplx f = conj(U[(size_t)j * rows + a]) / N;
         for (int e = 0; e < cols; e++) nB[(size_t)j * cols + e] += f * m->A[b + 1][(size_t)a * cols + e];
       }
-    double *nl = (double *)xalloc(sizeof(double) * k);
-    for (int j = 0; j < k; j++) nl[j] = sig[j] / N;
+    double *schmidt = (double *)xalloc(sizeof(double) * k);
+    for (int j = 0; j < k; j++) schmidt[j] = sig[j] / N;
     free(m->A[b]);
     free(m->A[b + 1]);
     free(m->lam[b]);
     m->A[b] = nA;
     m->A[b + 1] = nB;
-    m->lam[b] = nl;
+    m->lam[b] = schmidt;
     m->dim[b + 1] = k;
     if (truncate) {
       m->sum_eps += eps;
