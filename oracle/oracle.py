@@ -81,6 +81,7 @@ def lib():
         L.om_statevector.argtypes = [P, dp]
         L.om_sample.argtypes = [P, C.c_int, dp, C.POINTER(C.c_uint8), dp]
         L.om_canonicalize.argtypes = [P, C.c_int]
+        L.om_apply_2q_propagate.argtypes = [P, C.c_int, C.c_int, dp]
         L.om_set_threads.argtypes = [C.c_int]
         L.om_get_threads.restype = C.c_int
         _lib = L
@@ -138,6 +139,12 @@ class OracleMPS:
         g = _c128(g).reshape(16)
         st = lib().om_apply_2q(self._h, q0, q1, _dp(g.view(np.float64)))
         return st
+
+    def apply_2q_propagate(self, q0: int, q1: int, g) -> int:
+        """Two-qubit gate by bond propagation (distant qubits; neighbours take
+        the ordinary two-site path)."""
+        gg = _c128(g)
+        return lib().om_apply_2q_propagate(self._h, q0, q1, _dp(gg.view(np.float64)))
 
     def apply(self, gate) -> None:
         q0, q1, m = gate

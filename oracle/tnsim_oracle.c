@@ -548,10 +548,10 @@ int om_apply_2q(om_mps *m, int q0, int q1, const double *g_ri) {
    statistics; a cut changes the state, so the bonds right of it (already
    swept) no longer carry its Schmidt values, and both steps run once more
    without truncation.  The state is normalised. */
-static int canon_pass(om_mps *m, int truncate) {
-  const int n = m->n;
-  /* step 1 */
-  for (int q = 0; q + 1 < n; q++) {
+/* Step 1 on sites lo .. hi: sites lo .. hi-1 become left-canonical, the
+   rest of the window's content moves into site hi. */
+static int canon_left_sweep(om_mps *m, int lo, int hi) {
+  for (int q = lo; q < hi; q++) {
     const int rows = 2 * m->dim[q], cols = m->dim[q + 1], r = rows < cols ? rows : cols;
     cplx *M = (cplx *)xalloc(sizeof(cplx) * (size_t)rows * cols); /* column-major */
     for (int i = 0; i < rows; i++)
@@ -588,20 +588,21 @@ static int canon_pass(om_mps *m, int truncate) {
     m->A[q + 1] = nB;
     m->dim[q + 1] = k;
     free(m->lam[q]);
-    m->lam[q] = (double *)xalloc(sizeof(double) * k); /* rewritten in step 2 */
+    m->lam[q] = (double *)xalloc(sizeof(double) * k); /* rewritten by step 2 */
     free(M); free(U); free(sig); free(R);
   }
-  {
-    const size_t cnt = (size_t)m->dim[n - 1] * 2;
-    double nrm2 = 0.0;
-    for (size_t e = 0; e < cnt; e++) nrm2 += creal(m->A[n - 1][e]) * creal(m->A[n - 1][e]) +
-                                             cimag(m->A[n - 1][e]) * cimag(m->A[n - 1][e]);
-    if (!(nrm2 > 0.0)) return OM_E_ARG; /* the zero vector has no canonical form */
-    const double inv = 1.0 / sqrt(nrm2);
-    for (size_t e = 0; e < cnt; e++) m->A[n - 1][e] *= inv;
-  }
-  /* step 2 */
-  for (int b = n - 2; b >= 0; b--) {
+  return OM_OK;
+}
+
+/* Step 2 on bonds hi-1 .. lo (sites lo .. hi-1 left-canonical, bond hi in
+   Schmidt form or the right end).  With truncate, the rule applies with
+   chi_max and cutoff; each cut's discarded weight (relative to the weight
+   of the state at that point) goes to eps_out (sum) and keep_out (product
+   of 1 - eps); k_out gets the dimension of bond lo. */
+static int canon_right_sweep(om_mps *m, int lo, int hi, int truncate, double *eps_out,
+                             double *keep_out, int *k_out) {
+  const int n = m->n;
+  for (int b = hi - 1; b >= lo; b--) {
     const int rows = m->dim[b + 1], chiR = m->dim[b + 2], cols = 2 * chiR;
     const int r = rows < cols ? rows : cols;
     const double *lr = (b + 1 <= n - 2) ? m->lam[b + 1] : NULL;
@@ -646,19 +647,130 @@ static int canon_pass(om_mps *m, int truncate) {
     m->A[b + 1] = nB;
     m->lam[b] = schmidt;
     m->dim[b + 1] = k;
-    if (truncate) {
-      m->sum_eps += eps;
-      m->prod_keep *= (1.0 - eps);
-    }
+    if (eps_out) *eps_out += eps;
+    if (keep_out) *keep_out *= (1.0 - eps);
+    if (k_out) *k_out = k;
     free(U); free(sig);
   }
   return OM_OK;
+}
+
+static int canon_pass(om_mps *m, int truncate) {
+  const int n = m->n;
+  int r = canon_left_sweep(m, 0, n - 1);
+  if (r != OM_OK) return r;
+  {
+    const size_t cnt = (size_t)m->dim[n - 1] * 2;
+    double nrm2 = 0.0;
+    for (size_t e = 0; e < cnt; e++) nrm2 += creal(m->A[n - 1][e]) * creal(m->A[n - 1][e]) +
+                                             cimag(m->A[n - 1][e]) * cimag(m->A[n - 1][e]);
+    if (!(nrm2 > 0.0)) return OM_E_ARG; /* the zero vector has no canonical form */
+    const double inv = 1.0 / sqrt(nrm2);
+    for (size_t e = 0; e < cnt; e++) m->A[n - 1][e] *= inv;
+  }
+  return canon_right_sweep(m, 0, n - 1, truncate, truncate ? &m->sum_eps : NULL,
+                           truncate ? &m->prod_keep : NULL, NULL);
 }
 
 int om_canonicalize(om_mps *m, int truncate) {
   int r = canon_pass(m, truncate);
   if (r == OM_OK && truncate) r = canon_pass(m, 0);
   return r;
+}
+
+/* ------------------------------------------------------------------ bond propagation */
+
+/* A gate on distant qubits by bond propagation (Sec. III.A, non-local gates):
+   the 4x4 gate, cast as a 2x2x2x2 tensor, is split by SVD into
+   G = sum_r X_r (x) Y_r (X_r on the qubit at the left site a, Y_r on the one
+   at the right site b, the singular values folded into Y_r; r <= 4 terms).
+   X_r is contracted into site a, whose right bond gains the propagating index
+   r; the index is carried through every site between a and b (the
+   intermediate sites become I_r (x) A_j); Y_r is contracted into site b.
+   The chain then holds G|psi> exactly, with bonds a .. b-1 of dimension
+   r * chi.  Then (readings of the paper, which does not fix the gauge or the
+   truncation of this method): the sites a .. b-1 are decomposed in
+   succession from left to right without truncation (Sec. III.A: each
+   intermediate qubit is contracted and decomposed in turn; every step is an
+   SVD whose left vectors stay on the site and whose remainder moves right),
+   and then the bonds b-1 .. a get their Schmidt values from right to left,
+   where the truncation rule applies (chi_max, cutoff), as in a canonical
+   sweep.  The recorded discarded weight of the gate is the sum over its
+   cuts. */
+int om_apply_2q_propagate(om_mps *m, int q0, int q1, const double *g_ri) {
+  if (q0 < 0 || q0 >= m->n || q1 < 0 || q1 >= m->n || q0 == q1) return OM_E_ARG;
+  const cplx *G = (const cplx *)g_ri;
+  if (q1 == q0 + 1 || q1 == q0 - 1) return apply_2q_adjacent(m, q0, q1, G);
+  const int a = q0 < q1 ? q0 : q1, b = q0 < q1 ? q1 : q0;
+  /* Gm[(x', x), (y', y)] with x the qubit on site a, y the one on site b;
+     the gate's rows are 2 s_q0' + s_q1', its columns 2 s_q0 + s_q1 */
+  cplx Gm[16]; /* column-major 4 x 4: Gm[col * 4 + row] */
+  for (int xp = 0; xp < 2; xp++)
+    for (int x = 0; x < 2; x++)
+      for (int yp = 0; yp < 2; yp++)
+        for (int y = 0; y < 2; y++) {
+          const int row = q0 == a ? 2 * xp + yp : 2 * yp + xp;
+          const int col = q0 == a ? 2 * x + y : 2 * y + x;
+          Gm[(2 * yp + y) * 4 + (2 * xp + x)] = G[row * 4 + col];
+        }
+  cplx Ug[16];
+  double sg[4];
+  if (svd_left(Gm, 4, 4, 0.0, 60, Ug, sg) < 0) return OM_E_NOCONV;
+  int rg;
+  om_truncation(sg, 4, 4, 4, 0.0, &rg, NULL, NULL);
+  /* X_r[x', x] = U[(x', x), r];  Y_r[y', y] = sum_i conj(U[i, r]) Gm[i, (y', y)] */
+  cplx X[4][4], Y[4][4];
+  for (int r = 0; r < rg; r++)
+    for (int e = 0; e < 4; e++) {
+      X[r][e] = Ug[r * 4 + e];
+      cplx acc = 0.0;
+      for (int i = 0; i < 4; i++) acc += conj(Ug[r * 4 + i]) * Gm[e * 4 + i];
+      Y[r][e] = acc;
+    }
+  /* the chain with the propagating index merged into bonds a .. b-1
+     (bond j index r * dim[j+1] + c) */
+  int *od = (int *)xalloc(sizeof(int) * (m->n + 1));
+  memcpy(od, m->dim, sizeof(int) * (m->n + 1));
+  for (int q = a; q <= b; q++) {
+    const int L = od[q], R = od[q + 1];
+    const int nL = q == a ? L : rg * L, nR = q == b ? R : rg * R;
+    cplx *nA = (cplx *)xalloc(sizeof(cplx) * (size_t)nL * 2 * nR);
+    for (int r = 0; r < rg; r++)
+      for (int l = 0; l < L; l++)
+        for (int sp = 0; sp < 2; sp++)
+          for (int c = 0; c < R; c++) {
+            cplx v;
+            if (q == a)
+              v = X[r][2 * sp + 0] * m->A[q][((size_t)l * 2 + 0) * R + c] +
+                  X[r][2 * sp + 1] * m->A[q][((size_t)l * 2 + 1) * R + c];
+            else if (q == b)
+              v = Y[r][2 * sp + 0] * m->A[q][((size_t)l * 2 + 0) * R + c] +
+                  Y[r][2 * sp + 1] * m->A[q][((size_t)l * 2 + 1) * R + c];
+            else
+              v = m->A[q][((size_t)l * 2 + sp) * R + c];
+            const int li = q == a ? l : r * L + l, ri = q == b ? c : r * R + c;
+            nA[((size_t)li * 2 + sp) * nR + ri] = v;
+          }
+    free(m->A[q]);
+    m->A[q] = nA;
+  }
+  for (int q = a + 1; q <= b; q++) m->dim[q] = rg * od[q];
+  for (int j = a; j < b; j++) {
+    free(m->lam[j]);
+    m->lam[j] = (double *)xalloc(sizeof(double) * m->dim[j + 1]); /* rewritten below */
+  }
+  free(od);
+  int st = canon_left_sweep(m, a, b);
+  double eps = 0.0, keep = 1.0;
+  int k = 0;
+  if (st == OM_OK) st = canon_right_sweep(m, a, b, 1, &eps, &keep, &k);
+  if (st != OM_OK) return st;
+  m->sum_eps += eps;
+  m->prod_keep *= keep;
+  m->n2q += 1;
+  m->last_k = k;
+  m->last_eps = eps;
+  return OM_OK;
 }
 
 /* Gates of one layer: q1[g] = -1 marks a one-qubit gate (matrix in the first

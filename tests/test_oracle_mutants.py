@@ -55,6 +55,15 @@ MUTANTS = {
     "canonical sweep drops the remainder": (
         "for (int e = 0; e < w; e++) nB[(size_t)j * w + e] += f * m->A[q + 1][(size_t)c * w + e];",
         "for (int e = 0; e < w; e++) nB[(size_t)j * w + e] += (j == c) * m->A[q + 1][(size_t)c * w + e];"),
+    "propagation: right factor without conjugate": (
+        "for (int i = 0; i < 4; i++) acc += conj(Ug[r * 4 + i]) * Gm[e * 4 + i];",
+        "for (int i = 0; i < 4; i++) acc += Ug[r * 4 + i] * Gm[e * 4 + i];"),
+    "propagation: gate orientation ignored": (
+        "const int row = q0 == a ? 2 * xp + yp : 2 * yp + xp;",
+        "const int row = 2 * xp + yp;"),
+    "propagation: propagating index order mixed up": (
+        "const int li = q == a ? l : r * L + l, ri = q == b ? c : r * R + c;",
+        "const int li = q == a ? l : r * L + l, ri = q == b ? c : c * rg + r;"),
     "canonical sweep rotates with conj(U)": (
         "for (int j = 0; j < k; j++) nA[(size_t)i * k + j] += f * U[(size_t)j * rows + a];",
         "for (int j = 0; j < k; j++) nA[(size_t)i * k + j] += f * conj(U[(size_t)j * rows + a]);"),
@@ -80,6 +89,9 @@ PIN_CALLS = [
     pins.test_canonicalize_generic_gauge_against_brute_force,
     pins.test_canonicalize_leaves_a_canonical_state_unchanged,
     pins.test_canonicalize_truncation_is_the_optimal_cut,
+    lambda: pins.test_propagation_matches_statevector("haar"),
+    pins.test_propagation_ghz_and_operator_rank,
+    pins.test_propagation_truncation_is_a_right_to_left_schmidt_cut,
 ]
 
 

@@ -602,3 +602,95 @@ def test_canonicalize_truncation_is_the_optimal_cut():
     for b in range(n - 1):
         ref = schmidt_values(after, n, b)
         assert np.max(np.abs(m.lam(b) - ref[: m.bond_dims()[b]])) < 1e-12
+
+
+# ---------------------------------------------------------------- bond propagation (Sec. III.A)
+
+def _dense_gate(psi, n, q0, q1, g):
+    """G on qubits (q0, q1) of a dense state (index x = sum_q b_q 2^q), rows of
+    G in the basis |s_q0 s_q1> with s_q0 major."""
+    t = psi.reshape([2] * n)  # axis k <-> qubit n-1-k
+    a0, a1 = n - 1 - q0, n - 1 - q1
+    t = np.moveaxis(t, (a0, a1), (0, 1)).reshape(4, -1)
+    t = (np.asarray(g) @ t).reshape([2, 2] + [2] * (n - 2))
+    return np.moveaxis(t, (0, 1), (a0, a1)).reshape(-1)
+
+
+@pytest.mark.parametrize("gate", ["haar", "cnot"])
+def test_propagation_matches_statevector(gate):
+    """Gates on distant qubits by bond propagation, both orientations and
+    distances 2 .. 7, without truncation: the brute-force state vector."""
+    n = 8
+    rng = np.random.default_rng(808)
+    m = O.OracleMPS(n, 64)
+    m.run_layers(W.brickwork_haar(n, 4, 809))
+    psi = m.statevector()
+    for (q0, q1) in [(0, 2), (5, 1), (1, 7), (7, 0), (3, 6), (6, 4)]:
+        g = W.haar_u4(rng) if gate == "haar" else W.cnot()
+        assert m.apply_2q_propagate(q0, q1, g) == O.OK
+        psi = _dense_gate(psi, n, q0, q1, g)
+        assert np.max(np.abs(m.statevector() - psi)) < 1e-12
+    assert _left_canonical_defect(m) < 1e-12
+    for b in range(n - 1):
+        ref = schmidt_values(psi, n, b)
+        assert np.max(np.abs(m.lam(b) - ref[: m.bond_dims()[b]])) < 1e-12
+
+
+def test_propagation_ghz_and_operator_rank():
+    """CNOTs from qubit 0 to every other qubit, in scrambled order, by bond
+    propagation after H on qubit 0: GHZ with bond dimension 2 (Sec. V.A).  A
+    product gate (operator rank 1) adds no entanglement; the identity leaves
+    the state as it is."""
+    n = 9
+    m = O.OracleMPS(n, 16)
+    m.apply((0, -1, W.hadamard()))
+    for t in [5, 1, 8, 3, 2, 7, 4, 6]:
+        assert m.apply_2q_propagate(0, t, W.cnot()) == O.OK
+    psi = m.statevector()
+    s2 = 1 / math.sqrt(2)
+    assert abs(psi[0] - s2) < 1e-14 and abs(psi[-1] - s2) < 1e-14
+    assert np.sum(np.abs(psi) > 1e-12) == 2
+    assert list(m.bond_dims()) == [2] * (n - 1)
+    before = m.statevector()
+    assert m.apply_2q_propagate(1, 6, np.kron(W.rx(0.3), W.ry(1.1))) == O.OK
+    assert list(m.bond_dims()) == [2] * (n - 1)
+    assert m.apply_2q_propagate(7, 2, np.eye(4)) == O.OK
+    assert np.max(np.abs(m.statevector() - _dense_gate(before, n, 1, 6, np.kron(W.rx(0.3), W.ry(1.1))))) < 1e-13
+
+
+def test_propagation_truncation_is_a_right_to_left_schmidt_cut():
+    """With chi_max below what the gate creates, the cuts happen from the
+    right: the result equals the exact state G|psi> cut to its best rank
+    chi_max at bond b-1, renormalised, then at b-2, ..., down to bond a
+    (brute force, numpy SVD at each cut); the recorded discarded weight is
+    the sum over the cuts, and each bond keeps the Schmidt values of its
+    cut (a later cut further left changes the state, so for bonds right of
+    bond a these are the values at the time of their own cut)."""
+    n, chi = 9, 6
+    rng = np.random.default_rng(909)
+    src = O.OracleMPS(n, 64)
+    src.run_layers(W.brickwork_haar(n, 3, 910))
+    psi = src.statevector()
+    m = O.OracleMPS(n, chi, 0.0)
+    m.set_state([src.site(q) for q in range(n)], [src.lam(b) for b in range(n - 1)])
+    q0, q1 = 2, 6
+    g = W.haar_u4(rng)
+    assert m.apply_2q_propagate(q0, q1, g) == O.OK
+    phi = _dense_gate(psi, n, q0, q1, g)
+    eps = 0.0
+    kept = {}
+    for b in range(q1 - 1, q0 - 1, -1):  # bonds b-1 .. a of the gate, right to left
+        mat = phi.reshape(2 ** (n - b - 1), 2 ** (b + 1))
+        u, s, vh = np.linalg.svd(mat, full_matrices=False)
+        k = min(chi, int(np.sum(s ** 2 > (2 ** (n - b - 1)) * 2.0 ** -53 * s[0] ** 2)))
+        eps += float(np.sum(s[k:] ** 2) / np.sum(s ** 2))
+        kept[b] = s[:k] / np.linalg.norm(s[:k])
+        phi = (u[:, :k] * s[:k]) @ vh[:k]
+        phi = phi.reshape(-1) / np.linalg.norm(phi)
+    got = m.statevector()
+    assert 1 - fidelity_dense(phi, got) < 1e-12
+    assert abs(m.stats()["sum_eps"] - eps) < 1e-12
+    assert max(m.bond_dims()) <= chi
+    assert list(m.bond_dims()[q0:q1]) == [len(kept[b]) for b in range(q0, q1)]
+    for b in range(q0, q1):
+        assert np.max(np.abs(m.lam(b) - kept[b])) < 1e-12
