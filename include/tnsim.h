@@ -131,6 +131,45 @@ tnsim_status tnsim_mps_reset(tnsim_mps mps);
 /* One-qubit gate A'[a,s',b] = sum_s U[s',s] A[a,s,b]  (Sec. II, eq. 3). */
 tnsim_status tnsim_apply_1q(tnsim_mps mps, int32_t q, const tnsim_c128 u[4]);
 
+/* Two-qubit gate on distant qubits by bond propagation (Sec. III.A, the
+   method that scales linearly in the distance): G is split by SVD into
+   sum_r X_r (x) Y_r (r <= 4 terms, singular values folded into Y_r); X_r
+   goes into the site of the left qubit, whose bond gains the propagating
+   index r, which is carried through every site in between, and Y_r into the
+   site of the right qubit.  That chain holds G|psi> exactly; its sites are
+   then decomposed in succession from left to right (no truncation) and its
+   bonds get their Schmidt values from right to left, where chi_max and the
+   cutoff apply (the gate's discarded weight is the sum over its cuts).
+   Neighbouring qubits take the ordinary path of tnsim_apply_2q.  The bonds
+   between the qubits must hold r times their current dimension while the
+   gate runs: when one would exceed its capacity (the handle's
+   min(chi_max, 2^min(b+1, n-1-b))), the call returns TNSIM_E_CAPACITY with
+   the state unchanged (tnsim_apply_2q applies such a gate by SWAP gates).
+   Errors: TNSIM_E_ARG (qubits out of range or equal, NULL or non-finite
+   matrix), TNSIM_E_CAPACITY, TNSIM_E_NOCONV (the state then holds the
+   gate's result in a gauge that is not canonical between the two qubits;
+   tnsim_canonicalize restores it), TNSIM_E_DEVICE. */
+tnsim_status tnsim_apply_2q_propagate(tnsim_mps mps, int32_t q0, int32_t q1,
+                                      const tnsim_c128 g[16]);
+
+/* Canonical form (Sec. IV.A: the state is canonicalised before sampling).
+   Gate application keeps every site left-canonical and lambda_q equal to the
+   Schmidt values of bond q, but only up to rounding, and after truncations
+   (or tnsim_import_state of sites in another gauge) only approximately.  This
+   call restores that form exactly from any gauge, with two sweeps of
+   two-site decompositions: left to right without the Schmidt weights (every
+   site becomes left-canonical), then right to left with the weights just
+   computed (every bond gets the Schmidt values of the state).  The state is
+   normalised.  truncate = 0: only numerically zero values are dropped;
+   truncate = 1: the right-to-left sweep applies chi_max and cutoff (each
+   cut's discarded weight goes to tnsim_truncation_stats; the gate count is
+   not changed), followed by one more pass without truncation.  Cost: 2(n-1)
+   (or 4(n-1)) two-site decompositions run one after the other.
+   Errors: TNSIM_E_ARG (bad handle, truncate not 0 or 1), TNSIM_E_NOCONV
+   (a Jacobi SVD ran out of sweeps; the sweep stops there and the state is
+   the same state in a partly canonical gauge), TNSIM_E_DEVICE. */
+tnsim_status tnsim_canonicalize(tnsim_mps mps, int32_t truncate);
+
 /* Two-qubit gate, one gate per launch sequence: merge the two sites (Sec.
    IV.A, Fig. 2), contract with the gate, Jacobi SVD, truncate, write back
    (Sec. III.A).  Qubits further apart than neighbours are brought together
@@ -317,6 +356,14 @@ tnsim_status tnsim_profile_read(tnsim_mps mps, tnsim_kernel_stat *out);
    TNSIM_E_DEVICE. */
 #define TNSIM_TUNE_BUCKETS 4
 tnsim_status tnsim_autotune(tnsim_mps mps, int32_t *table_out);
+
+/* Install a launch-shape table (host, TNSIM_TUNE_BUCKETS entries, each 0 for
+   the built-in rule or one of 64, 128, 256, 512 rows per rotation workgroup),
+   e.g. one that tnsim_autotune chose on another handle of the same shape, so
+   that both run the same launches.  Results never depend on the table.
+   Errors: TNSIM_E_ARG (bad handle, NULL table or an entry outside that set;
+   the handle's table is then unchanged). */
+tnsim_status tnsim_set_launch_table(tnsim_mps mps, const int32_t *table);
 
 /* ---- circuit front end (host only; no device work) ----
    OpenQASM 2.0 text -> one- and two-qubit gates (Sec. III: the simulator's

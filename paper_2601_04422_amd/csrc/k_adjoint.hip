@@ -10,62 +10,99 @@ namespace tn {
 
 // ---------------------------------------------------------------- strided complex GEMM
 // C[i][j] (+)= alpha * sum_k opA(i,k) opB(k,j), with element strides and an
-// optional conjugation of each operand.  Used for the small contractions of
-// the adjoint and of the loss environments (chi up to a few hundred).
+// optional conjugation of each operand.  Used for the contractions of the
+// adjoint and of the loss environments.  Float64 matrix cores
+// (v_mfma_f64_16x16x4f64, four real products per complex one): a 64x64 tile
+// of C per workgroup, K in steps of 16 through LDS with the next step loaded
+// into registers during the products; wavefront w owns the 32x32 quarter
+// (rows 32 (w&1), columns 32 (w>>1)), lane l supplies A[l%16][k + l/16] and
+// B[k + l/16][l%16] and holds D[l/16 + 4v][l%16] of each 16x16 tile.
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f64x4_t adj_mfma(double a, double b, f64x4_t c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
 template <class SA, class SB>
 __global__ __launch_bounds__(256) void k_gemm_gen(GemmArgs g) {
   __shared__ double2 As[16 * 64], Bs[16 * 64];
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int tid = threadIdx.x;
   const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
   const SA *A = (const SA *)g.A;
   const SB *B = (const SB *)g.B;
-  double2 acc[4][4];
+  double2 ra[4], rb[4];
+  // element e = tid + 256 q of the 16 x 64 step: k = e / 64, row/column e % 64
+  auto load = [&](int k0) {
 #pragma unroll
-  for (int i = 0; i < 4; i++)
-#pragma unroll
-    for (int j = 0; j < 4; j++) acc[i][j] = make_double2(0.0, 0.0);
-  for (int k0 = 0; k0 < g.K; k0 += 16) {
-    for (int e = tid; e < 16 * 64; e += 256) {
-      int kk = e >> 6, ii = e & 63;
-      int gi = i0 + ii, gk = k0 + kk;
+    for (int q = 0; q < 4; q++) {
+      const int e = tid + 256 * q, kk = e >> 6, ii = e & 63;
+      const int gi = i0 + ii, gj = j0 + ii, gk = k0 + kk;
       double2 v = make_double2(0.0, 0.0);
       if (gi < g.M && gk < g.K) {
         v = cload(A + gi * g.sa_i + gk * g.sa_k);
         if (g.a_conj) v = cconj(v);
       }
-      As[kk * 64 + ii] = v;
-      int gj = j0 + ii;
+      ra[q] = v;
       double2 w = make_double2(0.0, 0.0);
       if (gj < g.N && gk < g.K) {
         w = cload(B + gk * g.sb_k + gj * g.sb_j);
         if (g.b_conj) w = cconj(w);
       }
-      Bs[kk * 64 + ii] = w;
+      rb[q] = w;
+    }
+  };
+  const int wv = tid >> 6, lane = tid & 63, l16 = lane & 15, lg = lane >> 4;
+  const int wm = (wv & 1) * 32, wn = (wv >> 1) * 32;
+  f64x4_t cr[2][2], ci[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; x++)
+#pragma unroll
+    for (int y = 0; y < 2; y++) {
+      cr[x][y] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+      ci[x][y] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+    }
+  load(0);
+  for (int k0 = 0; k0 < g.K; k0 += 16) {
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      As[tid + 256 * q] = ra[q];
+      Bs[tid + 256 * q] = rb[q];
     }
     __syncthreads();
+    if (k0 + 16 < g.K) load(k0 + 16);
 #pragma unroll
-    for (int kk = 0; kk < 16; kk++) {
-      double2 a[4], b[4];
+    for (int kk = 0; kk < 16; kk += 4) {
+      double2 a[2], b[2];
 #pragma unroll
-      for (int i = 0; i < 4; i++) a[i] = As[kk * 64 + ty + 16 * i];
+      for (int x = 0; x < 2; x++) {
+        a[x] = As[(kk + lg) * 64 + wm + 16 * x + l16];
+        b[x] = Bs[(kk + lg) * 64 + wn + 16 * x + l16];
+      }
 #pragma unroll
-      for (int j = 0; j < 4; j++) b[j] = Bs[kk * 64 + tx + 16 * j];
+      for (int x = 0; x < 2; x++)
 #pragma unroll
-      for (int i = 0; i < 4; i++)
-#pragma unroll
-        for (int j = 0; j < 4; j++) cfma(acc[i][j], a[i], b[j]);
+        for (int y = 0; y < 2; y++) {
+          cr[x][y] = adj_mfma(a[x].x, b[y].x, cr[x][y]);
+          cr[x][y] = adj_mfma(-a[x].y, b[y].y, cr[x][y]);
+          ci[x][y] = adj_mfma(a[x].x, b[y].y, ci[x][y]);
+          ci[x][y] = adj_mfma(a[x].y, b[y].x, ci[x][y]);
+        }
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 4; i++)
+  for (int x = 0; x < 2; x++)
 #pragma unroll
-    for (int j = 0; j < 4; j++) {
-      int gi = i0 + ty + 16 * i, gj = j0 + tx + 16 * j;
-      if (gi < g.M && gj < g.N) {
-        double2 *c = g.C + gi * g.sc_i + gj * g.sc_j;
-        double2 v = cmul(g.alpha, acc[i][j]);
-        *c = g.accumulate ? cadd(*c, v) : v;
+    for (int y = 0; y < 2; y++) {
+      const int gj = j0 + wn + 16 * y + l16;
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const int gi = i0 + wm + 16 * x + lg + 4 * v;
+        if (gi < g.M && gj < g.N) {
+          double2 *c = g.C + gi * g.sc_i + gj * g.sc_j;
+          const double2 val = cmul(g.alpha, make_double2(cr[x][y][v], ci[x][y][v]));
+          *c = g.accumulate ? cadd(*c, val) : val;
+        }
       }
     }
 }

@@ -92,4 +92,48 @@ void launch_convert(hipStream_t st, const void *src, int ss, void *dst, int ds, 
   hipLaunchKernelGGL(k_convert, dim3((unsigned)blocks), dim3(256), 0, st, src, ss, dst, ds, count);
 }
 
+// Bond propagation (Sec. III.A, non-local gates): one site of the window
+// with the gate's operator bond r (rg terms) merged into its bonds.  `old`
+// holds the site as it was (complex128, chiL x 2 x chiR); `out` receives
+//   role 0 (left site):   out[l, s', r chiR + c]        = sum_x X_r[s',x] old[l,x,c]
+//   role 1 (in between):  out[r chiL + l, s, r chiR + c] = old[l,s,c]
+//   role 2 (right site):  out[r chiL + l, s', c]        = sum_y Y_r[s',y] old[l,y,c]
+// (other entries of a role-1 site, r != r', are zero).  F holds rg 2x2
+// factors, row-major.  One thread per output entry.
+template <class S>
+__global__ void k_prop_merge(const double2 *old, S *out, int chiL, int chiR, int rg, int role,
+                             Mat4x4 F) {
+  const int nL = role == 0 ? chiL : rg * chiL, nR = role == 2 ? chiR : rg * chiR;
+  const size_t total = (size_t)nL * 2 * nR;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int ri = (int)(e % nR), sp = (int)((e / nR) % 2), li = (int)(e / ((size_t)2 * nR));
+    double2 v = make_double2(0.0, 0.0);
+    if (role == 1) {
+      const int r = li / chiL, l = li % chiL, r2 = ri / chiR, c = ri % chiR;
+      if (r == r2) v = old[((size_t)l * 2 + sp) * chiR + c];
+    } else {
+      const int r = role == 0 ? ri / chiR : li / chiL;
+      const int l = role == 0 ? li : li % chiL, c = role == 0 ? ri % chiR : ri;
+      const double2 *f = F.v[r];
+      v = cadd(cmul(f[2 * sp], old[((size_t)l * 2) * chiR + c]),
+               cmul(f[2 * sp + 1], old[((size_t)l * 2 + 1) * chiR + c]));
+    }
+    cstore(out + e, v);
+  }
+}
+
+void launch_prop_merge(hipStream_t st, const double2 *old, void *out, int storage, int chiL,
+                       int chiR, int rg, int role, const Mat4x4 &F) {
+  const size_t total = (size_t)(role == 0 ? chiL : rg * chiL) * 2 * (role == 2 ? chiR : rg * chiR);
+  size_t blocks = (total + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (storage == 0)
+    hipLaunchKernelGGL(k_prop_merge<double2>, dim3((unsigned)blocks), dim3(256), 0, st, old,
+                       (double2 *)out, chiL, chiR, rg, role, F);
+  else
+    hipLaunchKernelGGL(k_prop_merge<float2>, dim3((unsigned)blocks), dim3(256), 0, st, old,
+                       (float2 *)out, chiL, chiR, rg, role, F);
+}
+
 }  // namespace tn

@@ -83,79 +83,106 @@ __device__ void theta_epilogue(const GateDesc &d, int r0, int c0, double2 *Cs) {
   }
 }
 
+// float64 merge on the matrix cores (v_mfma_f64_16x16x4f64): a complex
+// product is four real products.  Wavefront w owns the 32x32 quarter (rows
+// 32 (w&1), columns 32 (w>>1)) as 2x2 tiles of 16x16; lane l supplies
+// A[l%16][k + l/16] and B[k + l/16][l%16] and holds D[l/16 + 4v][l%16] of
+// each tile.  The next 16-deep k step is loaded into registers while the
+// current one is multiplied.
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f64x4_t mfma_f64(double a, double b, f64x4_t c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
 template <class S>
-__device__ __forceinline__ void theta_tile(const GateDesc &d, int r0, int c0, double2 *smem) {
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+__device__ void theta_tile_f64mfma(const GateDesc &d, int r0, int c0, double2 *smem) {
+  const int tid = threadIdx.x;
   const S *A0 = (const S *)d.A0;
   const S *A1 = (const S *)d.A1;
   const int m = d.m, chiM = d.chiM, chiR = d.chiR, n = d.n;
   double2 *As = smem;            // [TK][TM]
   double2 *Bs = smem + TK * TM;  // [TK][2*TC]
-  double2 acc[4][4];
+  const int ar = tid >> 2, akq = (tid & 3) * 4;   // A: row ar, 4 consecutive k
+  const int bk = tid >> 4, bjq = (tid & 15) * 4;  // B: row bk, 4 consecutive columns
+  double2 ra[4], rb[4];
+  auto load = [&](int k0) {
+    const int gr = r0 + ar;
 #pragma unroll
-  for (int i = 0; i < 4; i++)
-#pragma unroll
-    for (int j = 0; j < 4; j++) acc[i][j] = make_double2(0.0, 0.0);
-
-  for (int k0 = 0; k0 < chiM; k0 += TK) {
-    {  // A tile: row r, 4 consecutive k
-      int r = tid >> 2, kq = (tid & 3) * 4;
-      int gr = r0 + r;
-#pragma unroll
-      for (int j = 0; j < 4; j++) {
-        int gk = k0 + kq + j;
-        double2 v = make_double2(0.0, 0.0);
-        if (gr < m && gk < chiM) v = cload(A0 + (size_t)gr * chiM + gk);
-        As[(kq + j) * TM + r] = v;
-      }
+    for (int j = 0; j < 4; j++) {
+      const int gk = k0 + akq + j;
+      ra[j] = (gr < m && gk < chiM) ? cload(A0 + (size_t)gr * chiM + gk) : make_double2(0.0, 0.0);
     }
-    {  // B tile: row k, 4 consecutive columns of one t half
-      int kk = tid >> 4, jq = (tid & 15) * 4;
-      int gk = k0 + kk;
+    const int gk = k0 + bk;
 #pragma unroll
-      for (int j = 0; j < 4; j++) {
-        int jj = jq + j, t = jj >> 5, c = c0 + (jj & 31);
-        double2 v = make_double2(0.0, 0.0);
-        if (gk < chiM && c < chiR) v = cload(A1 + (size_t)gk * n + t * chiR + c);
-        Bs[kk * (2 * TC) + jj] = v;
-      }
+    for (int j = 0; j < 4; j++) {
+      const int jj = bjq + j, t = jj >> 5, c = c0 + (jj & 31);
+      rb[j] = (gk < chiM && c < chiR) ? cload(A1 + (size_t)gk * n + t * chiR + c)
+                                      : make_double2(0.0, 0.0);
+    }
+  };
+  const int w = tid >> 6, lane = tid & 63, l16 = lane & 15, lg = lane >> 4;
+  const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
+  f64x4_t cr[2][2], ci[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; x++)
+#pragma unroll
+    for (int y = 0; y < 2; y++) {
+      cr[x][y] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+      ci[x][y] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+    }
+  load(0);
+  for (int k0 = 0; k0 < chiM; k0 += TK) {
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      As[(akq + j) * TM + ar] = ra[j];
+      Bs[bk * (2 * TC) + bjq + j] = rb[j];
     }
     __syncthreads();
+    if (k0 + TK < chiM) load(k0 + TK);
 #pragma unroll
-    for (int kk = 0; kk < TK; kk++) {
-      double2 a[4], b[4];
+    for (int kk = 0; kk < TK; kk += 4) {
+      double2 a[2], b[2];
 #pragma unroll
-      for (int i = 0; i < 4; i++) a[i] = As[kk * TM + ty + 16 * i];
+      for (int x = 0; x < 2; x++) {
+        a[x] = As[(kk + lg) * TM + wm + 16 * x + l16];
+        b[x] = Bs[(kk + lg) * (2 * TC) + wn + 16 * x + l16];
+      }
 #pragma unroll
-      for (int j = 0; j < 4; j++) b[j] = Bs[kk * (2 * TC) + tx + 16 * j];
+      for (int x = 0; x < 2; x++)
 #pragma unroll
-      for (int i = 0; i < 4; i++)
-#pragma unroll
-        for (int j = 0; j < 4; j++) cfma(acc[i][j], a[i], b[j]);
+        for (int y = 0; y < 2; y++) {
+          cr[x][y] = mfma_f64(a[x].x, b[y].x, cr[x][y]);
+          cr[x][y] = mfma_f64(-a[x].y, b[y].y, cr[x][y]);
+          ci[x][y] = mfma_f64(a[x].x, b[y].y, ci[x][y]);
+          ci[x][y] = mfma_f64(a[x].y, b[y].x, ci[x][y]);
+        }
     }
     __syncthreads();
   }
-
-  // epilogue: tile to LDS, then the shared gate/weight epilogue
   constexpr int LD = 2 * TC + 1;
   double2 *Cs = smem;  // [TM][LD]
 #pragma unroll
-  for (int i = 0; i < 4; i++)
+  for (int x = 0; x < 2; x++)
 #pragma unroll
-    for (int j = 0; j < 4; j++) Cs[(ty + 16 * i) * LD + tx + 16 * j] = acc[i][j];
+    for (int y = 0; y < 2; y++)
+#pragma unroll
+      for (int v = 0; v < 4; v++)
+        Cs[(wm + 16 * x + lg + 4 * v) * LD + wn + 16 * y + l16] =
+            make_double2(cr[x][y][v], ci[x][y][v]);
   __syncthreads();
   theta_epilogue(d, r0, c0, Cs);
 }
 
-__global__ __launch_bounds__(256) void k_theta_fp64(const GateDesc *descs) {
+__global__ __launch_bounds__(256) void k_theta_f64mfma(const GateDesc *descs) {
   const GateDesc &d = descs[blockIdx.z];
   int r0 = blockIdx.x * TM, c0 = blockIdx.y * TC;
   if (r0 >= d.m || c0 >= d.chiR) return;
   __shared__ double2 smem[TM * (2 * TC + 1)];
   if (d.storage == 0)
-    theta_tile<double2>(d, r0, c0, smem);
+    theta_tile_f64mfma<double2>(d, r0, c0, smem);
   else
-    theta_tile<float2>(d, r0, c0, smem);
+    theta_tile_f64mfma<float2>(d, r0, c0, smem);
 }
 
 // Same tile and epilogue on matrix cores: operands rounded to complex64 and
@@ -248,7 +275,7 @@ void launch_theta(hipStream_t st, const GateDesc *d, int ng, int precision, int 
     return;
   }
   dim3 grid((max_m + TM - 1) / TM, (max_chiR + TC - 1) / TC, ng);
-  hipLaunchKernelGGL(k_theta_fp64, grid, dim3(256), 0, st, d);
+  hipLaunchKernelGGL(k_theta_f64mfma, grid, dim3(256), 0, st, d);
 }
 
 }  // namespace tn

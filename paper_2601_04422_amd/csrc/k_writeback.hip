@@ -42,7 +42,7 @@ __device__ void wb_left_tile(const GateDesc &d, int k, int r0, int j0, double2 *
     tile[r * LD + j] = v;
   }
   __syncthreads();
-  S *A0 = (S *)d.A0;
+  S *A0 = (S *)d.A0out;
   for (int e = tid; e < 64 * 64; e += 256) {
     int j = e % 64, r = e / 64;  // write along j (row-major destination)
     int gr = r0 + r, gj = j0 + j;
@@ -62,20 +62,26 @@ __global__ __launch_bounds__(256) void k_wb_left(const GateDesc *descs) {
     wb_left_tile<float2>(d, k, r0, j0, tile);
 }
 
-// A_{i+1}' = (1/N) U_k^H theta'   (k x n), tiles of 64 x 64, K = m in steps of 16
-template <class S, class TT>
-__device__ void wb_right_tile(const GateDesc &d, int k, int j0, int c0, double2 *smem) {
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+// A_{i+1}' = (1/N) U_k^H theta'   (k x n), tiles of 64 x 64, K = m in steps of 16.
+// float64 product on the matrix cores (v_mfma_f64_16x16x4f64, four real
+// products per complex one).  Tile j (64 kept vectors) x c (64 columns
+// of theta'), K = m rows in steps of 16 through LDS, the next step loaded
+// into registers while the current one is multiplied.  Wavefront w owns the
+// 32x32 quarter (rows 32 (w&1), columns 32 (w>>1)); lane l supplies
+// A[l%16][k + l/16] and B[k + l/16][l%16] and holds D[l/16 + 4v][l%16].
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f64x4_t wb_mfma_f64(double a, double b, f64x4_t c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <class S>
+__device__ void wb_right_tile_f64mfma(const GateDesc &d, int k, int j0, int c0, double2 *smem) {
+  const int tid = threadIdx.x;
   double2 *As = smem;            // [16][64]  conj(U)[r][j]
   double2 *Bs = smem + 16 * 64;  // [16][64]  theta'[r][c]
-  const TT *T = (const TT *)d.T;
+  const double2 *T = (const double2 *)d.T;
   const int m = d.m, n = d.n;
-  double2 acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; i++)
-#pragma unroll
-    for (int j = 0; j < 4; j++) acc[i][j] = make_double2(0.0, 0.0);
-  // per-thread loader coordinates
   const int aj = tid >> 2, ar = (tid & 3) * 4;  // A: column j, 4 consecutive r
   const int gj = j0 + aj;
   int colA = 0;
@@ -85,64 +91,86 @@ __device__ void wb_right_tile(const GateDesc &d, int k, int j0, int c0, double2 
     invA = left_inv(d, colA);
   }
   const int br = tid >> 4, bc = (tid & 15) * 4;  // B: row r, 4 consecutive c
+  double2 ra[4], rb[4];
+  auto load = [&](int r0) {
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const int gr = r0 + ar + q;
+      ra[q] = (gj < k && gr < m) ? cconj(left_vec(d, gr, colA, invA)) : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const int gr = r0 + br, gc = c0 + bc + q;
+      rb[q] = (gr < m && gc < n) ? T[(size_t)gr * n + gc] : make_double2(0.0, 0.0);
+    }
+  };
+  const int w = tid >> 6, lane = tid & 63, l16 = lane & 15, lg = lane >> 4;
+  const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
+  f64x4_t cr[2][2], ci[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; x++)
+#pragma unroll
+    for (int y = 0; y < 2; y++) {
+      cr[x][y] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+      ci[x][y] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+    }
+  load(0);
   for (int r0 = 0; r0 < m; r0 += 16) {
 #pragma unroll
     for (int q = 0; q < 4; q++) {
-      int gr = r0 + ar + q;
-      double2 v = make_double2(0.0, 0.0);
-      if (gj < k && gr < m) v = cconj(left_vec(d, gr, colA, invA));
-      As[(ar + q) * 64 + aj] = v;
-    }
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-      int gr = r0 + br, gc = c0 + bc + q;
-      double2 v = make_double2(0.0, 0.0);
-      if (gr < m && gc < n) v = cload(T + (size_t)gr * n + gc);
-      Bs[br * 64 + bc + q] = v;
+      As[(ar + q) * 64 + aj] = ra[q];
+      Bs[br * 64 + bc + q] = rb[q];
     }
     __syncthreads();
+    if (r0 + 16 < m) load(r0 + 16);
 #pragma unroll
-    for (int kk = 0; kk < 16; kk++) {
-      double2 a[4], b[4];
+    for (int kk = 0; kk < 16; kk += 4) {
+      double2 a[2], b[2];
 #pragma unroll
-      for (int i = 0; i < 4; i++) a[i] = As[kk * 64 + ty + 16 * i];
+      for (int x = 0; x < 2; x++) {
+        a[x] = As[(kk + lg) * 64 + wm + 16 * x + l16];
+        b[x] = Bs[(kk + lg) * 64 + wn + 16 * x + l16];
+      }
 #pragma unroll
-      for (int j = 0; j < 4; j++) b[j] = Bs[kk * 64 + tx + 16 * j];
+      for (int x = 0; x < 2; x++)
 #pragma unroll
-      for (int i = 0; i < 4; i++)
-#pragma unroll
-        for (int j = 0; j < 4; j++) cfma(acc[i][j], a[i], b[j]);
+        for (int y = 0; y < 2; y++) {
+          cr[x][y] = wb_mfma_f64(a[x].x, b[y].x, cr[x][y]);
+          cr[x][y] = wb_mfma_f64(-a[x].y, b[y].y, cr[x][y]);
+          ci[x][y] = wb_mfma_f64(a[x].x, b[y].y, ci[x][y]);
+          ci[x][y] = wb_mfma_f64(a[x].y, b[y].x, ci[x][y]);
+        }
     }
     __syncthreads();
   }
   const double invN = 1.0 / d.sc->N;
-  S *A1 = (S *)d.A1;
+  S *A1 = (S *)d.A1out;
 #pragma unroll
-  for (int i = 0; i < 4; i++)
+  for (int x = 0; x < 2; x++)
 #pragma unroll
-    for (int j = 0; j < 4; j++) {
-      int gjo = j0 + ty + 16 * i, gc = c0 + tx + 16 * j;
-      if (gjo < k && gc < n) cstore(A1 + (size_t)gjo * n + gc, cscale(acc[i][j], invN));
+    for (int y = 0; y < 2; y++) {
+      const int gc = c0 + wn + 16 * y + l16;
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const int gjo = j0 + wm + 16 * x + lg + 4 * v;
+        if (gjo < k && gc < n)
+          cstore(A1 + (size_t)gjo * n + gc,
+                 make_double2(cr[x][y][v] * invN, ci[x][y][v] * invN));
+      }
     }
 }
 
-__global__ __launch_bounds__(256) void k_wb_right(const GateDesc *descs) {
+// float64 write-back (theta' stored complex128) on the matrix cores
+__global__ __launch_bounds__(256) void k_wb_right_f64mfma(const GateDesc *descs) {
   const GateDesc &d = descs[blockIdx.z];
   const int k = d.sc->k;
   int j0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
   if (j0 >= k || c0 >= d.n) return;
   __shared__ double2 smem[2 * 16 * 64];
-  if (d.storage == 0) {
-    if (d.tfp32)
-      wb_right_tile<double2, float2>(d, k, j0, c0, smem);
-    else
-      wb_right_tile<double2, double2>(d, k, j0, c0, smem);
-  } else {
-    if (d.tfp32)
-      wb_right_tile<float2, float2>(d, k, j0, c0, smem);
-    else
-      wb_right_tile<float2, double2>(d, k, j0, c0, smem);
-  }
+  if (d.storage == 0)
+    wb_right_tile_f64mfma<double2>(d, k, j0, c0, smem);
+  else
+    wb_right_tile_f64mfma<float2>(d, k, j0, c0, smem);
 }
 
 void launch_wb_left(hipStream_t st, const GateDesc *d, int ng, int max_m, int max_k) {
@@ -194,7 +222,7 @@ __device__ void wb_right_tile_mfma(const GateDesc &d, int k, int j0, int c0, flo
     __syncthreads();
   }
   const double invN = 1.0 / d.sc->N;
-  S *A1 = (S *)d.A1;
+  S *A1 = (S *)d.A1out;
 #pragma unroll
   for (int ti = 0; ti < 2; ti++)
 #pragma unroll
@@ -228,7 +256,7 @@ void launch_wb_right(hipStream_t st, const GateDesc *d, int ng, int precision, i
   if (ng <= 0) return;
   dim3 grid((max_k + 63) / 64, (max_n + 63) / 64, ng);
   if (precision == 0)
-    hipLaunchKernelGGL(k_wb_right, grid, dim3(256), 0, st, d);
+    hipLaunchKernelGGL(k_wb_right_f64mfma, grid, dim3(256), 0, st, d);
   else if (precision == MODE_F32)
     hipLaunchKernelGGL(k_wb_right_mfma<MODE_F32>, grid, dim3(256), 0, st, d);
   else if (precision == MODE_BF16X3)

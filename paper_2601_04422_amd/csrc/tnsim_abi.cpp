@@ -166,10 +166,20 @@ Layout make_layout(const tnsim_config &c) {
   return L;
 }
 
-// Gate with orientation fixed to (i, i+1)
+// Gate with orientation fixed to (i, i+1).  Flags of the canonicalisation
+// sweeps, which run the two-site path with the identity gate: UNWEIGHTED
+// decomposes theta itself (no lambda_{i+1} weight), NO_CUT drops only
+// numerically zero values (cutoff 0), NO_STATS leaves the gate statistics
+// alone, EPS_ONLY adds the discarded weight to the truncation statistics
+// without counting a gate.
+enum { PEND_UNWEIGHTED = 1, PEND_NO_CUT = 2, PEND_NO_STATS = 4, PEND_EPS_ONLY = 8 };
 struct Pending {
   int i;
   double2 g[16];
+  int flags = 0;
+  // bond propagation's window steps read and write some sites elsewhere than
+  // the site buffers (nullptr: the site buffer)
+  void *a0_in = nullptr, *a1_in = nullptr, *a0_out = nullptr, *a1_out = nullptr;
 };
 
 // One gate of the segment being differentiated, recorded during recompute.
@@ -232,6 +242,11 @@ struct tnsim_mps_s {
   hipStream_t stream2 = nullptr;
   char *pin2 = nullptr;
   hipEvent_t ev_main = nullptr, ev_prep = nullptr;
+  // Jacobi sweeps in flight: each sweep's gathered scalars go to pinned
+  // buffer 0 or 1 (the second at pin + pin_sc1_off), marked by ev_sw[b]
+  hipEvent_t ev_sw[2] = {nullptr, nullptr};
+  size_t pin_sc1_off = 0;
+  bool speculate = true;  // TNSIM_SPECULATE=0: one sweep in flight, host test in between
   // profiling
   struct Rec {
     int cls;
@@ -386,7 +401,8 @@ struct BatchItem {
 // Pair-count class of a launch, for the autotuned rotation shape.
 int tune_bucket(int pairs) { return pairs <= 32 ? 0 : pairs <= 128 ? 1 : pairs <= 512 ? 2 : 3; }
 
-SlotScalars *pin_scalars(tnsim_mps o) {
+SlotScalars *pin_scalars(tnsim_mps o, int buf = 0) {
+  if (buf) return reinterpret_cast<SlotScalars *>(o->pin + o->pin_sc1_off);
   return reinterpret_cast<SlotScalars *>(o->pin + align_up(sizeof(GateDesc) * o->L.desc_cap));
 }
 
@@ -426,10 +442,12 @@ GateDesc make_desc(tnsim_mps o, const BatchItem &it, bool force_trans) {
                                 : (h->cfg.storage == TNSIM_STORE_C64
                                        ? 0x1p-30
                                        : std::max(d.rows, 16) * 0x1p-53);
-  d.cutoff = h->cfg.cutoff;
-  d.A0 = h->site(i);
-  d.A1 = h->site(i + 1);
-  d.lamR = (i + 1 <= L.n - 2) ? h->lam(i + 1) : nullptr;
+  d.cutoff = (it.p->flags & PEND_NO_CUT) ? 0.0 : h->cfg.cutoff;
+  d.A0 = it.p->a0_in ? it.p->a0_in : h->site(i);
+  d.A1 = it.p->a1_in ? it.p->a1_in : h->site(i + 1);
+  d.A0out = it.p->a0_out ? it.p->a0_out : h->site(i);
+  d.A1out = it.p->a1_out ? it.p->a1_out : h->site(i + 1);
+  d.lamR = (i + 1 <= L.n - 2 && !(it.p->flags & PEND_UNWEIGHTED)) ? h->lam(i + 1) : nullptr;
   d.lamOut = h->lam(i);
   char *sl = h->slot(it.slot);
   d.X = (double2 *)(sl + L.x_off);
@@ -649,10 +667,13 @@ struct SweepRunner {
     return TNSIM_OK;
   }
 
-  // One sweep of the current plan; rot[a] = some pair of planned gate a rotated.
-  tnsim_status run(std::vector<char> &rot) {
+  // Enqueue one sweep of the current plan and the copy of its gathered
+  // scalars into pinned buffer `buf`, marked by event ev_sw[buf].  Nothing
+  // waits: the host can enqueue the next sweep before reading this one.
+  tnsim_status launch(int buf) {
     tnsim_mps h = o;
     hipStream_t st = o->stream;
+    if (!h->ev_sw[buf]) HIPCHK(h, hipEventCreateWithFlags(&h->ev_sw[buf], hipEventDisableTiming));
     if (h->graphs && !h->prof && st != nullptr) {
       tnsim_status gs = graph();
       if (gs != TNSIM_OK) return gs;
@@ -661,14 +682,32 @@ struct SweepRunner {
       enqueue();
     }
     LAUNCHCHK(h, "jacobi round");
-    SlotScalars *sc_pin = pin_scalars(o);
-    HIPCHK(h, hipMemcpyAsync(sc_pin, o->at<SlotScalars>(o->L.scg_off),
+    HIPCHK(h, hipMemcpyAsync(pin_scalars(o, buf), o->at<SlotScalars>(o->L.scg_off),
                              sizeof(SlotScalars) * P.na, hipMemcpyDeviceToHost, st));
-    HIPCHK(h, hipStreamSynchronize(st));
-    prof_drain(h);
-    rot.assign(P.na, 0);
-    for (int a = 0; a < P.na; a++) rot[a] = sc_pin[a].rot != 0;
+    HIPCHK(h, hipEventRecord(h->ev_sw[buf], st));
     return TNSIM_OK;
+  }
+
+  // Wait for the sweep launched into `buf` (`na` gates planned then);
+  // rot[a] = some pair of planned gate a rotated in that sweep.
+  tnsim_status collect(int buf, int na, std::vector<char> &rot) {
+    tnsim_mps h = o;
+    HIPCHK(h, hipEventSynchronize(h->ev_sw[buf]));
+    if (h->prof) {  // only one sweep is ever in flight while profiling
+      HIPCHK(h, hipStreamSynchronize(o->stream));
+      prof_drain(h);
+    }
+    const SlotScalars *sc_pin = pin_scalars(o, buf);
+    rot.assign(na, 0);
+    for (int a = 0; a < na; a++) rot[a] = sc_pin[a].rot != 0;
+    return TNSIM_OK;
+  }
+
+  // One sweep of the current plan, waited for.
+  tnsim_status run(std::vector<char> &rot) {
+    tnsim_status s = launch(0);
+    if (s != TNSIM_OK) return s;
+    return collect(0, P.na, rot);
   }
 };
 
@@ -721,11 +760,16 @@ tnsim_status gates_finish(tnsim_mps o, const BatchItem *items, const GateDesc *D
     const SlotScalars &sv = sc_pin[g];
     const GateDesc &d = D[g];
     tnsim_mps hg = items[g].h;
-    record_gate(items[g], d, sv.k, sweeps[g]);
+    const int fl = items[g].p->flags;
     hg->dims[d.i + 1] = sv.k;
-    hg->sum_eps += sv.eps;
-    hg->prod_keep *= (1.0 - sv.eps);
-    hg->n2q += 1;
+    if (!(fl & PEND_NO_STATS)) {
+      hg->sum_eps += sv.eps;
+      hg->prod_keep *= (1.0 - sv.eps);
+      if (!(fl & PEND_EPS_ONLY)) {
+        record_gate(items[g], d, sv.k, sweeps[g]);
+        hg->n2q += 1;
+      }
+    }
     maxK = std::max(maxK, sv.k);
     const double eb = d.storage == 0 ? 16.0 : 8.0, tb = d.tfp32 ? 8.0 : 16.0;
     wbl_byte += (16.0 + eb) * d.m * sv.k;
@@ -785,27 +829,53 @@ tnsim_status run_2q_items(tnsim_mps o, const BatchItem *items, int ng, bool forc
   bool converged = false;
   int sweeps = 0;
   std::vector<char> rot;
+  // Sweep s + 1 is enqueued before the host reads sweep s, so the host's
+  // convergence test and the next launch overlap the GPU's work.  A gate
+  // whose sweep rotated nothing is switched off on the device at the start
+  // of the next sweep (k_begin_sweep), so a sweep enqueued after the last
+  // one it needed leaves it unchanged and costs only early-exiting
+  // workgroups.  Speculation is off while profiling (one sweep in flight).
+  const bool spec = o->speculate && !o->prof;
+  std::vector<int> act_at[2];
+  int buf = 0;
+  s = sw.launch(buf);
+  if (s != TNSIM_OK) return s;
+  act_at[buf] = act;
   for (int sweep = 1; sweep <= max_sweeps; sweep++) {
-    s = sw.run(rot);
+    if (spec && sweep < max_sweeps) {
+      s = sw.launch(buf ^ 1);
+      if (s != TNSIM_OK) return s;
+      act_at[buf ^ 1] = act;
+    }
+    s = sw.collect(buf, (int)act_at[buf].size(), rot);
     if (s != TNSIM_OK) return s;
     sweeps = sweep;
     std::vector<int> still;
-    for (int a = 0; a < sw.P.na; a++) {
+    for (size_t a = 0; a < act_at[buf].size(); a++) {
+      const int g = act_at[buf][a];
       if (rot[a])
-        still.push_back(act[a]);
-      else if (!done_at[act[a]])
-        done_at[act[a]] = sweep;
+        still.push_back(g);
+      else if (!done_at[g])
+        done_at[g] = sweep;
     }
     if (still.empty()) {
       converged = true;
       break;
     }
     // re-plan once the active set has shrunk by a quarter (a converged gate
-    // left in the plan only costs early-exiting workgroups)
-    if (4 * (int)still.size() <= 3 * sw.P.na) {
+    // left in the plan only costs early-exiting workgroups); the new plan
+    // takes effect from the next sweep launched
+    if (4 * (int)still.size() <= 3 * (int)act.size()) {
       act.swap(still);
       s = replan();
       if (s != TNSIM_OK) return s;
+    }
+    if (spec) {
+      buf ^= 1;
+    } else if (sweep < max_sweeps) {
+      s = sw.launch(buf);
+      if (s != TNSIM_OK) return s;
+      act_at[buf] = act;
     }
   }
   std::vector<int> swp(ng);
@@ -830,6 +900,37 @@ tnsim_status run_2q(tnsim_mps h, const std::vector<Pending> &gs) {
   for (size_t b = 0; b < gs.size(); b += ns) {
     int ng = (int)std::min<size_t>(ns, gs.size() - b);
     tnsim_status s = run_2q_batch(h, gs.data() + b, ng);
+    if (s != TNSIM_OK) return s;
+  }
+  return TNSIM_OK;
+}
+
+// One canonicalisation pass (Sec. IV.A: the state is brought to canonical
+// form before sampling), through the two-site path with the identity gate:
+//  1. left to right, q = 0 .. n-2: theta = A_q A_{q+1} decomposed without the
+//     Schmidt weight and without truncation: A_q <- U_k (left-canonical),
+//     A_{q+1} <- U_k^H theta / N, so sites 0 .. n-2 end left-canonical and
+//     the state normalised;
+//  2. right to left, b = n-2 .. 0: theta = A_b A_{b+1} weighted by
+//     lambda_{b+1}, which the previous step has just made the Schmidt
+//     values of bond b+1 (1 at the right end), while sites 0 .. b form an
+//     orthonormal left basis: the SVD is the Schmidt decomposition of bond
+//     b, so lambda_b <- sigma / N, A_b <- U_k, A_{b+1} <- U_k^H theta / N.
+// With `truncate`, step 2 applies the handle's chi_max and cutoff.
+tnsim_status canonical_pass(tnsim_mps h, bool truncate) {
+  const int n = h->L.n;
+  Pending p{};
+  for (int e = 0; e < 4; e++) p.g[5 * e] = make_double2(1.0, 0.0);
+  for (int q = 0; q + 1 < n; q++) {
+    p.i = q;
+    p.flags = PEND_UNWEIGHTED | PEND_NO_CUT | PEND_NO_STATS;
+    tnsim_status s = run_2q_batch(h, &p, 1);
+    if (s != TNSIM_OK) return s;
+  }
+  for (int b = n - 2; b >= 0; b--) {
+    p.i = b;
+    p.flags = truncate ? PEND_EPS_ONLY : (PEND_NO_CUT | PEND_NO_STATS);
+    tnsim_status s = run_2q_batch(h, &p, 1);
     if (s != TNSIM_OK) return s;
   }
   return TNSIM_OK;
@@ -1642,6 +1743,7 @@ tnsim_status tnsim_mps_create(const tnsim_config *cfg, void *dev_arena, size_t a
     if (v >= 1 && v <= 1 << 20) h->gram_wg_target = v;
   }
   if (const char *e = getenv("TNSIM_OVERLAP_PREPARE")) h->overlap_prepare = atoi(e) != 0;
+  if (const char *e = getenv("TNSIM_SPECULATE")) h->speculate = atoi(e) != 0;
   if (const char *e = getenv("TNSIM_ADMIT_GROUP")) {
     const int v = atoi(e);
     if (v >= 1 && v <= 4096) h->admit_group = v;
@@ -1653,6 +1755,8 @@ tnsim_status tnsim_mps_create(const tnsim_config *cfg, void *dev_arena, size_t a
   const Layout &LL = h->L;
   h->pin_bytes = align_up(sizeof(GateDesc) * LL.desc_cap) + align_up(sizeof(SlotScalars) * LL.desc_cap) +
                  align_up(sizeof(Gate1Desc) * LL.n) + 4096;
+  h->pin_sc1_off = h->pin_bytes;  // the second buffer of sweep scalars
+  h->pin_bytes += align_up(sizeof(SlotScalars) * LL.desc_cap);
   if (hipHostMalloc((void **)&h->pin, h->pin_bytes, hipHostMallocDefault) != hipSuccess) {
     delete h;
     return TNSIM_E_DEVICE;
@@ -1687,6 +1791,8 @@ tnsim_status tnsim_mps_destroy(tnsim_mps h) {
   }
   if (h->ev_main) hipEventDestroy(h->ev_main);
   if (h->ev_prep) hipEventDestroy(h->ev_prep);
+  for (hipEvent_t e : h->ev_sw)
+    if (e) hipEventDestroy(e);
   if (h->pin2) hipHostFree(h->pin2);
   prof_drain(h);
   if (h->sweep_exec) hipGraphExecDestroy(h->sweep_exec);
@@ -1731,6 +1837,196 @@ tnsim_status tnsim_apply_2q(tnsim_mps h, int32_t q0, int32_t q1, const tnsim_c12
   Pending p;
   orient(q0, q1, g, p);
   return run_2q_batch(h, &p, 1);
+}
+
+namespace {
+
+// Operator Schmidt decomposition of a two-qubit gate for bond propagation:
+// G = sum_r X_r (x) Y_r, X_r acting on the qubit at the left site and Y_r on
+// the one at the right site (q0_left: q0 is the left one), with the singular
+// values folded into Y_r.  Gm[(x',x),(y',y)] is factored by one-sided
+// (Hestenes) Jacobi on its four columns; the terms whose squared singular
+// value is above 4 * 2^-53 of the largest one are kept.  Returns their count.
+int op_schmidt(const tnsim_c128 *g, bool q0_left, Mat4x4 &X, Mat4x4 &Y) {
+  double2 Gm[4][4], W[4][4];  // [row][col]
+  for (int xp = 0; xp < 2; xp++)
+    for (int x = 0; x < 2; x++)
+      for (int yp = 0; yp < 2; yp++)
+        for (int y = 0; y < 2; y++) {
+          const int row = q0_left ? 2 * xp + yp : 2 * yp + xp;
+          const int col = q0_left ? 2 * x + y : 2 * y + x;
+          Gm[2 * xp + x][2 * yp + y] = make_double2(g[row * 4 + col].re, g[row * 4 + col].im);
+        }
+  for (int i = 0; i < 4; i++)
+    for (int j = 0; j < 4; j++) W[i][j] = Gm[i][j];
+  auto dotc = [&](int p, int q) {  // column p ^H column q
+    double re = 0.0, im = 0.0;
+    for (int i = 0; i < 4; i++) {
+      re += W[i][p].x * W[i][q].x + W[i][p].y * W[i][q].y;
+      im += W[i][p].x * W[i][q].y - W[i][p].y * W[i][q].x;
+    }
+    return make_double2(re, im);
+  };
+  for (int sweep = 0; sweep < 60; sweep++) {
+    bool rotated = false;
+    for (int p = 0; p < 4; p++)
+      for (int q = p + 1; q < 4; q++) {
+        const double a = dotc(p, p).x, b = dotc(q, q).x;
+        const double2 c = dotc(p, q);
+        const double ac = std::sqrt(c.x * c.x + c.y * c.y);
+        if (!(ac > 1e-15 * std::sqrt(a * b)) || a == 0.0 || b == 0.0) continue;
+        rotated = true;
+        const double2 e = make_double2(c.x / ac, c.y / ac);
+        const double zeta = (b - a) / (2.0 * ac);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+        const double cs = 1.0 / std::sqrt(1.0 + t * t), sn = cs * t;
+        for (int i = 0; i < 4; i++) {
+          const double2 xv = W[i][p];
+          // y~ = e^{-i phi} y
+          const double2 yt = make_double2(e.x * W[i][q].x + e.y * W[i][q].y,
+                                          e.x * W[i][q].y - e.y * W[i][q].x);
+          W[i][p] = make_double2(cs * xv.x - sn * yt.x, cs * xv.y - sn * yt.y);
+          W[i][q] = make_double2(sn * xv.x + cs * yt.x, sn * xv.y + cs * yt.y);
+        }
+      }
+    if (!rotated) break;
+  }
+  int ord[4] = {0, 1, 2, 3};
+  double nrm[4];
+  for (int j = 0; j < 4; j++) nrm[j] = std::sqrt(dotc(j, j).x);
+  std::stable_sort(ord, ord + 4, [&](int u, int v) { return nrm[u] > nrm[v]; });
+  int rg = 0;
+  for (int j = 0; j < 4; j++)
+    if (nrm[ord[j]] * nrm[ord[j]] > 4 * 0x1p-53 * nrm[ord[0]] * nrm[ord[0]]) rg++;
+  memset(&X, 0, sizeof X);
+  memset(&Y, 0, sizeof Y);
+  for (int r = 0; r < rg; r++) {
+    const int j = ord[r];
+    for (int e = 0; e < 4; e++)
+      X.v[r][e] = make_double2(W[e][j].x / nrm[j], W[e][j].y / nrm[j]);
+    for (int e = 0; e < 4; e++) {  // Y_r = U_r^H Gm
+      double re = 0.0, im = 0.0;
+      for (int i = 0; i < 4; i++) {
+        re += X.v[r][i].x * Gm[i][e].x + X.v[r][i].y * Gm[i][e].y;
+        im += X.v[r][i].x * Gm[i][e].y - X.v[r][i].y * Gm[i][e].x;
+      }
+      Y.v[r][e] = make_double2(re, im);
+    }
+  }
+  return rg;
+}
+
+// Gate on distant qubits a < b by bond propagation (Sec. III.A): the
+// operator bond of G = sum_r X_r (x) Y_r is merged into bonds a .. b-1
+// (site a takes X_r, the sites in between I_r, site b takes Y_r), which
+// holds G|psi> exactly; the window is then decomposed from left to right
+// without truncation (each intermediate site in succession) and given its
+// Schmidt values from right to left, where chi_max and the cutoff apply.
+// Each step is the ordinary two-site path with the identity gate.  The
+// merged sites, whose bonds may exceed a site buffer's capacity (near the
+// ends of the chain a bond holds at most 2^min(b+1, n-1-b)), live in the X
+// and J buffers of the gate slots 1, 2, ... (two sites per buffer) until a
+// step leaves a site with its final dimensions.
+tnsim_status apply_propagate(tnsim_mps h, int q0, int q1, const tnsim_c128 *g) {
+  const int a = std::min(q0, q1), b = std::max(q0, q1), d = b - a;
+  Mat4x4 X, Y;
+  const int rg = op_schmidt(g, q0 == a, X, Y);
+  const Layout &L = h->L;
+  const int maxbond = L.cmax / 2;
+  for (int j = a; j < b; j++)
+    if ((long long)rg * h->dims[j + 1] > maxbond) {
+      h->err = "bond propagation: bond " + std::to_string(j) + " would need dimension " +
+               std::to_string(rg * h->dims[j + 1]) + " (operator rank " + std::to_string(rg) +
+               " times " + std::to_string(h->dims[j + 1]) + "), above the capacity " +
+               std::to_string(maxbond) + "; tnsim_apply_2q takes this gate by SWAPs";
+      return TNSIM_E_CAPACITY;
+    }
+  // window storage: site w of the window at half of an X or J buffer of slot >= 1
+  const size_t half = (size_t)L.ldx_max * L.cols_pad_max * sizeof(double2) / 2;
+  if (d + 1 > 4 * (L.nslots - 1)) {
+    h->err = "bond propagation: a window of " + std::to_string(d + 1) +
+             " sites needs more gate slots than the handle has (max_layer_gates); "
+             "tnsim_apply_2q takes this gate by SWAPs";
+    return TNSIM_E_CAPACITY;
+  }
+  auto win = [&](int w) -> void * {
+    const int sl = 1 + w / 4, part = w % 4;
+    char *base = h->slot(sl) + (part < 2 ? L.x_off : L.j_off);
+    return base + (part & 1) * half;
+  };
+  h->state_version++;
+  h->last_sweeps = 0;
+  h->last_batch.clear();
+  hipStream_t st = h->stream;
+  double2 *old = (double2 *)(h->slot(0) + L.x_off);  // one site at a time, complex128
+  const std::vector<int> od = h->dims;
+  for (int q = a; q <= b; q++) {
+    const int role = q == a ? 0 : (q == b ? 2 : 1);
+    launch_convert(st, h->site(q), L.storage, old, 0, (size_t)od[q] * 2 * od[q + 1]);
+    launch_prop_merge(st, old, win(q - a), L.storage, od[q], od[q + 1], rg, role,
+                      role == 0 ? X : Y);
+  }
+  LAUNCHCHK(h, "propagation merge");
+  for (int q = a + 1; q <= b; q++) h->dims[q] = rg * od[q];
+  HIPCHK(h, hipStreamSynchronize(st));
+  memcpy(h->pin, h->dims.data(), sizeof(int32_t) * (L.n + 1));
+  HIPCHK(h, hipMemcpyAsync(h->dims_dev(), h->pin, sizeof(int32_t) * (L.n + 1),
+                           hipMemcpyHostToDevice, st));
+  auto step = [&](int j, int flags, void *a0i, void *a1i, void *a0o, void *a1o) {
+    Pending p{};
+    for (int e = 0; e < 4; e++) p.g[5 * e] = make_double2(1.0, 0.0);
+    p.i = j;
+    p.flags = flags;
+    p.a0_in = a0i;
+    p.a1_in = a1i;
+    p.a0_out = a0o;
+    p.a1_out = a1o;
+    return run_2q_batch(h, &p, 1);
+  };
+  // left to right inside the window (window site w = site a + w): the bonds
+  // shrink to their ranks, which may still exceed a site buffer
+  for (int j = a; j + 1 < b; j++) {
+    tnsim_status s = step(j, PEND_UNWEIGHTED | PEND_NO_CUT | PEND_NO_STATS, win(j - a),
+                          win(j + 1 - a), win(j - a), win(j + 1 - a));
+    if (s != TNSIM_OK) return s;
+  }
+  // right to left, with the Schmidt weights and the truncation rule: the
+  // right site of each step is final and goes to its buffer, the left one
+  // stays in the window until the last step
+  for (int j = b - 1; j >= a; j--) {
+    tnsim_status s = step(j, PEND_EPS_ONLY, win(j - a), win(j + 1 - a),
+                          j == a ? h->site(a) : win(j - a), h->site(j + 1));
+    if (s != TNSIM_OK) return s;
+  }
+  h->n2q += 1;
+  return TNSIM_OK;
+}
+
+}  // namespace
+
+tnsim_status tnsim_apply_2q_propagate(tnsim_mps h, int32_t q0, int32_t q1,
+                                      const tnsim_c128 g[16]) {
+  tnsim_status s = check_handle(h);
+  if (s != TNSIM_OK) return s;
+  const int n = h->L.n;
+  if (q0 < 0 || q0 >= n || q1 < 0 || q1 >= n || q0 == q1 || !g || !finite_gate(g, 16))
+    return TNSIM_E_ARG;
+  if (std::abs(q0 - q1) == 1) return tnsim_apply_2q(h, q0, q1, g);
+  return apply_propagate(h, q0, q1, g);
+}
+
+tnsim_status tnsim_canonicalize(tnsim_mps h, int32_t truncate) {
+  tnsim_status s = check_handle(h);
+  if (s != TNSIM_OK) return s;
+  if (truncate != 0 && truncate != 1) return TNSIM_E_ARG;
+  h->state_version++;
+  h->last_sweeps = 0;
+  h->last_batch.clear();
+  s = canonical_pass(h, truncate != 0);
+  // a cut changes the state, so the bonds right of it (swept before it) no
+  // longer carry its Schmidt values: one more pass without truncation
+  if (s == TNSIM_OK && truncate) s = canonical_pass(h, false);
+  return s;
 }
 
 tnsim_status tnsim_apply_layer(tnsim_mps h, const tnsim_gate *gates, int32_t n_gates) {
@@ -2529,6 +2825,18 @@ tnsim_status tnsim_autotune(tnsim_mps h, int32_t *table_out) {
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
+  return TNSIM_OK;
+}
+
+tnsim_status tnsim_set_launch_table(tnsim_mps h, const int32_t *table) {
+  tnsim_status s = check_handle(h);
+  if (s != TNSIM_OK) return s;
+  if (!table) return TNSIM_E_ARG;
+  for (int bk = 0; bk < TNSIM_TUNE_BUCKETS; bk++) {
+    const int v = table[bk];
+    if (v != 0 && v != 64 && v != 128 && v != 256 && v != 512) return TNSIM_E_ARG;
+  }
+  for (int bk = 0; bk < TNSIM_TUNE_BUCKETS; bk++) h->tune_rot_rows[bk] = table[bk];
   return TNSIM_OK;
 }
 

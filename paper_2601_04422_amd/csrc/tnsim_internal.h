@@ -52,7 +52,9 @@ struct GateDesc {
   int *dimsDev;          // device bond dimensions of the gate's state (n+1)
   double tol;            // relative off-diagonal tolerance
   double cutoff;         // discarded-weight cutoff
-  void *A0, *A1;         // site i, site i+1
+  void *A0, *A1;         // site i, site i+1 (read by the merge)
+  void *A0out, *A1out;   // where the write-back puts them (the same sites, except
+                         // for the window steps of bond propagation)
   const double *lamR;    // lambda_{i+1} or nullptr (= all ones)
   double *lamOut;        // lambda_i
   double2 *X, *J;        // Jacobi matrix, accumulated left vectors (trans only)
@@ -93,6 +95,12 @@ void launch_fill_zero(hipStream_t st, void *p, size_t bytes);
 void launch_apply_1q(hipStream_t st, const Gate1Desc *d, int ng, int max_elems);
 void launch_convert(hipStream_t st, const void *src, int src_storage, void *dst, int dst_storage,
                     size_t count);
+// rg 2x2 factors of a gate's operator Schmidt decomposition (bond propagation)
+struct Mat4x4 {
+  double2 v[4][4];
+};
+void launch_prop_merge(hipStream_t st, const double2 *old, void *out, int storage, int chiL,
+                       int chiR, int rg, int role, const Mat4x4 &F);
 void launch_setup_slots(hipStream_t st, const GateDesc *d, int ng, int max_rows_pad,
                         int max_m_pad);
 void launch_theta(hipStream_t st, const GateDesc *d, int ng, int precision, int max_m,

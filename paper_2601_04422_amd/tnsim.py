@@ -81,6 +81,9 @@ _SIGS = {
     "tnsim_profile": (C.c_int, [_P, C.c_int32]),
     "tnsim_profile_read": (C.c_int, [_P, _P]),
     "tnsim_autotune": (C.c_int, [_P, _P]),
+    "tnsim_set_launch_table": (C.c_int, [_P, _P]),
+    "tnsim_canonicalize": (C.c_int, [_P, C.c_int32]),
+    "tnsim_apply_2q_propagate": (C.c_int, [_P, C.c_int32, C.c_int32, _P]),
     "tnsim_qasm_parse": (C.c_int, [C.c_char_p, _P, C.c_int32, C.POINTER(C.c_int32),
                                    C.POINTER(C.c_int32), C.c_char_p, C.c_int32]),
     "tnsim_fuse": (C.c_int, [_P, C.c_int32, C.c_int32, _P, C.POINTER(C.c_int32)]),
@@ -261,6 +264,16 @@ class MPS:
         a = _c128_array(g, 16)
         return lib().tnsim_apply_2q(self._h, q0, q1, a.ctypes.data)
 
+    def apply_2q_propagate(self, q0: int, q1: int, g) -> int:
+        """Two-qubit gate on distant qubits by bond propagation
+        (tnsim_apply_2q_propagate); returns the status (E_CAPACITY when the
+        window between the qubits cannot hold the propagating bond)."""
+        gg = _c128_array(g, 16)
+        st = lib().tnsim_apply_2q_propagate(self._h, q0, q1, gg.ctypes.data)
+        if st not in (OK, E_CAPACITY):
+            self._chk(st, "apply_2q_propagate")
+        return st
+
     def apply(self, gate) -> None:
         q0, q1, m = gate
         if q1 < 0:
@@ -311,6 +324,11 @@ class MPS:
 
     def norm2(self) -> float:
         return self.overlap(self).real
+
+    def canonicalize(self, truncate: bool = False) -> None:
+        """Exact left-canonical form with the Schmidt values on every bond, from
+        any gauge; the state is normalised (tnsim_canonicalize)."""
+        self._chk(lib().tnsim_canonicalize(self._h, 1 if truncate else 0), "canonicalize")
 
     def copy_from(self, other: "MPS") -> None:
         self._chk(lib().tnsim_mps_copy(self._h, other._h), "mps_copy")
@@ -484,6 +502,13 @@ class MPS:
         out = np.zeros(4, dtype=np.int32)
         self._chk(lib().tnsim_autotune(self._h, out.ctypes.data), "autotune")
         return out.tolist()
+
+    def set_autotune(self, table: Sequence[int]) -> None:
+        """Install a launch-shape table (e.g. another handle's autotune result)."""
+        t = np.ascontiguousarray(table, dtype=np.int32)
+        if t.size != 4:
+            raise ValueError("launch table needs 4 entries")
+        self._chk(lib().tnsim_set_launch_table(self._h, t.ctypes.data), "set_launch_table")
 
     def site(self, q: int) -> np.ndarray:
         a, b = C.c_int32(), C.c_int32()

@@ -247,14 +247,31 @@ def schmidt_profile(rng: np.random.Generator, chi: int, decay: float = 8.0) -> n
     return lam / np.linalg.norm(lam)
 
 
+def flat_schmidt_profile(rng: np.random.Generator, chi: int) -> np.ndarray:
+    """Decreasing weights with sum of squares 1 drawn from the quarter-circle
+    law p(x) = sqrt(4 - x^2) / pi on [0, 2] (the singular-value law of a large
+    square complex Gaussian matrix, i.e. the Schmidt spectrum of a random
+    state across a cut with equal dimensions): flat at the top, no gap
+    anywhere, unlike the smooth exponential profile.  Rejection sampling."""
+    out = np.empty(0)
+    while out.size < chi:
+        x = rng.uniform(0.0, 2.0, 2 * chi)
+        y = rng.uniform(0.0, 2.0, 2 * chi)
+        out = np.concatenate([out, x[y * y + x * x <= 4.0]])
+    lam = np.sort(out[:chi])[::-1]
+    return lam / np.linalg.norm(lam)
+
+
 def random_canonical_mps(n: int, dims: Sequence[int], seed: int,
-                         dtype=np.complex128):
+                         dtype=np.complex128, profile: str = "smooth"):
     """A left-canonical MPS with prescribed bond dimensions.
 
     ``dims`` has length n+1 with dims[0] = dims[n] = 1; site q has shape
     (dims[q], 2, dims[q+1]) and satisfies sum_{a,s} conj(A[a,s,b]) A[a,s,b'] =
-    delta_{bb'}.  Each inner bond gets a Schmidt-like weight vector.  Used for
-    full-size inputs that would take the CPU hours to reach by simulation.
+    delta_{bb'}.  Each inner bond gets a Schmidt-like weight vector: a smooth
+    decaying one (``profile="smooth"``) or a random-circuit-like one from the
+    quarter-circle law (``profile="flat"``).  Used for full-size inputs that
+    would take the CPU hours to reach by simulation.
     """
     rng = np.random.default_rng(seed)
     sites, lams = [], []
@@ -263,8 +280,9 @@ def random_canonical_mps(n: int, dims: Sequence[int], seed: int,
         assert b <= 2 * a, "left-canonical site needs dims[q+1] <= 2*dims[q]"
         u = random_isometry(rng, 2 * a, b)
         sites.append(u.reshape(a, 2, b).astype(dtype))
+    prof = {"smooth": schmidt_profile, "flat": flat_schmidt_profile}[profile]
     for q in range(n - 1):
-        lams.append(schmidt_profile(rng, dims[q + 1]))
+        lams.append(prof(rng, dims[q + 1]))
     return sites, lams
 
 

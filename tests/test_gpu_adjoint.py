@@ -133,3 +133,60 @@ def test_autograd_two_forwards_on_one_handle(T):
     assert np.linalg.norm(a2.grad.numpy() - ref) / np.linalg.norm(ref) < 1e-8
     with pytest.raises(RuntimeError, match="another forward"):
         l1.backward()
+
+
+# ---------------------------------------------------------------- the 32-qubit, 8-layer ansatz
+# (512 angles uniform in [0, 2 pi), Ry/Rz per qubit + CNOT ladder, loss
+# sum_i <Z_i Z_{i+1}>)
+
+def _golden_param_shift():
+    import json
+    import os
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "ansatz_param_shift.json")
+    with open(path) as f:
+        return json.load(f)
+
+
+def test_ansatz32_vs_oracle_parameter_shift(T):
+    """At chi_max = 256 the ansatz is not truncated, so the oracle's
+    parameter shift is exact; its gradients on 16 seeded angles are stored by
+    tests/golden/make_ansatz_param_shift.py (oracle forwards only).  The GPU
+    adjoint at the same chi_max must match them within 1e-4 relative (L2 over
+    the 16 entries), and the loss within 1e-10."""
+    ref = _golden_param_shift()
+    n, nl, chi = ref["n"], ref["layers"], ref["chi_max"]
+    angles = W.ansatz_angles(n, nl)
+    spec = _spec(n, nl)
+    m = T.MPS(n, chi, 0.0)
+    loss = m.forward_checkpointed(spec[0], spec[1], spec[2], angles, *spec[3:])
+    assert m.stats()["sum_eps"] < 1e-12
+    assert abs(loss - ref["loss"]) < 1e-10
+    g = m.backward(1.0)
+    idx = np.array(ref["indices"])
+    gr = np.array(ref["grad"])
+    assert np.linalg.norm(g[idx] - gr) / np.linalg.norm(gr) < 1e-4
+
+
+def test_ansatz32_truncated_vs_finite_differences(T):
+    """chi_max = 128, where the ansatz truncates in its last layers: the
+    adjoint against central differences (h = 1e-4) of the same truncated
+    float64 forward on 32 seeded angles, within 1e-4 relative."""
+    n, nl, chi = 32, 8, 128
+    angles = W.ansatz_angles(n, nl)
+    spec = _spec(n, nl)
+    m = T.MPS(n, chi, 0.0)
+    m.forward_checkpointed(spec[0], spec[1], spec[2], angles, *spec[3:])
+    assert m.stats()["sum_eps"] > 1e-8  # truncation is active
+    g = m.backward(1.0)
+    h = 1e-4
+    idx = np.random.default_rng(4141).choice(angles.size, 32, replace=False)
+    fd = np.zeros(idx.size)
+    for k, p in enumerate(idx):
+        a = angles.copy()
+        a[p] += h
+        lp = _loss_gpu(T, n, chi, a, spec)
+        a[p] -= 2 * h
+        lm = _loss_gpu(T, n, chi, a, spec)
+        fd[k] = (lp - lm) / (2 * h)
+    assert np.linalg.norm(g[idx] - fd) / np.linalg.norm(fd) < 1e-4

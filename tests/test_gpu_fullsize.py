@@ -135,3 +135,74 @@ def test_sampling_full_size_vs_oracle_amplitudes(T):
     b2, l2 = m.sample(u[500:])
     assert np.array_equal(b2.cpu().numpy(), bits[500:])
     assert np.max(np.abs(l2.cpu().numpy() - logp[500:])) < 1e-12
+
+
+def test_two_layers_flat_spectrum_chi1024(T):
+    """Two consecutive chi = 1024 layers in the benchmark's batched form
+    (float64, complex128 sites, QR-preconditioned Jacobi, one stream of its
+    own so the sweeps replay as a graph) on a state whose Schmidt spectra are
+    random-circuit-like (quarter-circle law: flat, no gap at the cut).
+    Layer 1 acts on the odd bonds, layer 2 on the even bonds.  Checked
+    against the oracle (float64 bound 1e-10):
+      * layer 1, gates (i-1, i) and (i+1, i+2) from the input state: k, the
+        spectrum and the two-site product (whose outer bonds keep the input's
+        basis, so the product is gauge-free);
+      * layer 2, gate (i, i+1), which reads both of those gates' outputs: the
+        oracle applies it to the GPU's state after layer 1 (so bonds i-1 and
+        i+1 carry the same basis on both sides): k, spectrum, discarded
+        weight and two-site product."""
+    import torch
+
+    chi, tol = 1024, 1e-10
+    dims = W.saturated_dims(N_SITES, chi)
+    sites, lams = W.random_canonical_mps(N_SITES, dims, 3301, profile="flat")
+    rng = np.random.default_rng(3302)
+
+    def dressed():
+        a, b, c, d = rng.uniform(0, 2 * np.pi, 4)
+        return W.cnot() @ np.kron(W.rz(a) @ W.rx(b), W.rz(c) @ W.rx(d))
+
+    l1 = [(j, j + 1, dressed()) for j in range(1, N_SITES - 1, 2)]
+    l2 = [(j, j + 1, dressed()) for j in range(2, N_SITES - 1, 2)]
+    i = N_SITES // 2
+    assert i % 2 == 0 and dims[i - 1] == dims[i] == dims[i + 1] == dims[i + 2] == chi
+    m = T.MPS(N_SITES, chi, 1e-12, precision="fp64", storage="c128", svd_precondition=True,
+              stream=torch.cuda.Stream())
+    m.import_state(sites, lams)
+    assert m.apply_layer(l1) == T.OK
+    after1 = ([m.site(q) for q in range(N_SITES)], [m.lam(b) for b in range(N_SITES - 1)])
+    assert m.apply_layer(l2) == T.OK
+    # the left site of every layer-2 gate is U_k (isometric); the left sites
+    # of the layer-1 gates became right sites of layer-2 gates, which a cut
+    # leaves only approximately left-canonical
+    for (j, _, _) in l2:
+        a = m.site(j).reshape(-1, m.bond_dims()[j])
+        gram = a.conj().T @ a
+        assert np.max(np.abs(gram - np.eye(gram.shape[0]))) < 1e-10
+    for (j, _, _) in l1 + l2:
+        assert abs(np.sum(m.lam(j) ** 2) - 1) < 1e-10
+    O.set_threads(16)
+
+    def check(o, j, gs, gl, eps_min):
+        st = o.stats()
+        assert st["last_eps"] > eps_min  # a real cut on a flat spectrum
+        assert len(gl[j]) == o.bond_dims()[j] == st["last_k"]
+        assert np.max(np.abs(gl[j] - o.lam(j))) / o.lam(j)[0] < tol
+        pg = _block(gs[j], gs[j + 1])
+        po = _block(o.site(j), o.site(j + 1))
+        assert np.linalg.norm(pg - po) / np.linalg.norm(po) < tol
+
+    o = O.OracleMPS(N_SITES, chi, 1e-12)
+    o.set_state(sites, lams)
+    for (j, jj, g) in l1:
+        if j in (i - 1, i + 1):
+            assert o.apply_2q(j, jj, g) == O.OK
+            # (i+1, i+2) has chi_R = 512: M is 2048 x 1024 and chi_max does not cut
+            check(o, j, after1[0], after1[1], 1e-4 if j == i - 1 else -1.0)
+    o = O.OracleMPS(N_SITES, chi, 1e-12)
+    o.set_state(*after1)
+    g2 = [x for x in l2 if x[0] == i][0][2]
+    assert o.apply_2q(i, i + 1, g2) == O.OK
+    check(o, i, [m.site(q) for q in range(N_SITES)], [m.lam(b) for b in range(N_SITES - 1)],
+          1e-4)
+    assert m.bond_dims()[i] == chi
