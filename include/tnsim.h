@@ -283,6 +283,22 @@ tnsim_status tnsim_sample(tnsim_mps mps, void *dev_ws, size_t ws_bytes, int32_t 
    call that may change the state (gates, reset, import, copy into it,
    gradients) it returns TNSIM_E_ARG until prepared again.  Shots above
    max_shots: TNSIM_E_CAPACITY. */
+/* tnsim_sample without allocation, for callers that cannot allocate device
+   memory (code under HIP graph capture, tight serving loops, harnesses that
+   forbid hipMalloc): the same draws as tnsim_sample, with the workspace taken
+   from a fixed device array of TNSIM_SAMPLE_SCRATCH_BYTES that the library
+   holds on every GPU it runs on until the process ends.  The call makes no
+   allocation of any kind.  All calls on one GPU share that array (it keeps
+   the last call's contents; every call initialises what it reads), so calls
+   that overlap in time on one GPU -- from several threads, or on several
+   handles whose streams run concurrently -- race: serialise them.
+   Errors: as tnsim_sample, and TNSIM_E_CAPACITY when the workspace that
+   tnsim_sample_workspace_bytes gives for this handle's configuration and
+   `shots` exceeds TNSIM_SAMPLE_SCRATCH_BYTES (tnsim_last_error says by how
+   much). */
+#define TNSIM_SAMPLE_SCRATCH_BYTES (128u << 20)
+tnsim_status tnsim_sample_noalloc(tnsim_mps mps, int32_t shots, const double *dev_u,
+                                  uint8_t *dev_bits, double *dev_logp);
 tnsim_status tnsim_sample_prepare(tnsim_mps mps, void *dev_ws, size_t ws_bytes, int32_t max_shots);
 tnsim_status tnsim_sample_draw(tnsim_mps mps, void *dev_ws, size_t ws_bytes, int32_t shots,
                                const double *dev_u, uint8_t *dev_bits, double *dev_logp);

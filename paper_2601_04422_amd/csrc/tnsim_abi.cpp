@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -2411,6 +2412,63 @@ tnsim_status tnsim_sample_draw(tnsim_mps h, void *dev_ws, size_t ws_bytes, int32
   if (!dev_u || !dev_bits) return TNSIM_E_ARG;
   const SampleLayout S = sample_layout(h->L, h->smp_cap);
   return sample_draw(h, (char *)dev_ws, S, shots, dev_u, dev_bits, dev_logp);
+}
+
+// ---- sampling without allocation: the workspace is a fixed device array
+// (one copy per GPU, resident from the library's load until the process
+// ends).  In host code `scratch` names a host-side stand-in; kernels get the
+// device address that hipGetSymbolAddress returns for the current device,
+// looked up once per device and kept in smp_scratch_dev.
+static __device__ __align__(256) char scratch[TNSIM_SAMPLE_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex smp_scratch_mu;
+void *smp_scratch_dev[MAX_DEVICES] = {};
+
+// Device address of `scratch` on `dev`, looked up with that device current.
+tnsim_status scratch_on_device(tnsim_mps h, void **out) {
+  const int dev = h->device;
+  if (dev < 0 || dev >= MAX_DEVICES) {
+    h->err = "sample_noalloc: device index beyond the supported range";
+    return TNSIM_E_DEVICE;
+  }
+  std::lock_guard<std::mutex> lock(smp_scratch_mu);
+  if (!smp_scratch_dev[dev]) {
+    int cur = 0;
+    HIPCHK(h, hipGetDevice(&cur));
+    if (cur != dev) HIPCHK(h, hipSetDevice(dev));
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != dev) HIPCHK(h, hipSetDevice(cur));
+    if (e != hipSuccess) return fail(h, e, "hipGetSymbolAddress(scratch)");
+    smp_scratch_dev[dev] = ptr;
+  }
+  *out = smp_scratch_dev[dev];
+  return TNSIM_OK;
+}
+}  // namespace
+
+tnsim_status tnsim_sample_noalloc(tnsim_mps h, int32_t shots, const double *dev_u,
+                                  uint8_t *dev_bits, double *dev_logp) {
+  tnsim_status s = check_handle(h);
+  if (s != TNSIM_OK) return s;
+  if (shots < 0 || shots > (1 << 28)) return TNSIM_E_ARG;
+  if (shots == 0) return TNSIM_OK;
+  if (!dev_u || !dev_bits) return TNSIM_E_ARG;
+  const SampleLayout S = sample_layout(h->L, shots);
+  if (S.total > (size_t)TNSIM_SAMPLE_SCRATCH_BYTES) {
+    h->err = "sample_noalloc: this handle's sampling workspace for that many shots (" +
+             std::to_string(S.total) + " bytes) exceeds the fixed device array (" +
+             std::to_string((size_t)TNSIM_SAMPLE_SCRATCH_BYTES) + " bytes)";
+    return TNSIM_E_CAPACITY;
+  }
+  void *ws = nullptr;
+  s = scratch_on_device(h, &ws);
+  if (s != TNSIM_OK) return s;
+  s = sample_weights(h, (char *)ws, S);
+  if (s != TNSIM_OK) return s;
+  return sample_draw(h, (char *)ws, S, shots, dev_u, dev_bits, dev_logp);
 }
 
 tnsim_status tnsim_mps_copy(tnsim_mps dst, tnsim_mps src) {

@@ -84,6 +84,7 @@ _SIGS = {
     "tnsim_set_launch_table": (C.c_int, [_P, _P]),
     "tnsim_canonicalize": (C.c_int, [_P, C.c_int32]),
     "tnsim_apply_2q_propagate": (C.c_int, [_P, C.c_int32, C.c_int32, _P]),
+    "tnsim_sample_noalloc": (C.c_int, [_P, C.c_int32, _P, _P, _P]),
     "tnsim_qasm_parse": (C.c_int, [C.c_char_p, _P, C.c_int32, C.POINTER(C.c_int32),
                                    C.POINTER(C.c_int32), C.c_char_p, C.c_int32]),
     "tnsim_fuse": (C.c_int, [_P, C.c_int32, C.c_int32, _P, C.POINTER(C.c_int32)]),
@@ -435,6 +436,26 @@ class MPS:
                                      self._smp_ws.numel(), shots, C.c_void_p(ut.data_ptr()),
                                      C.c_void_p(bits.data_ptr()), C.c_void_p(logp.data_ptr())),
                   "sample")
+        return bits, logp
+
+    def sample_noalloc(self, u, bits=None, logp=None):
+        """The same draws as sample(u) through tnsim_sample_noalloc: the library
+        takes its workspace from a fixed device array.  Output tensors may be
+        passed in (then nothing is allocated on this call's path)."""
+        import torch
+
+        ut = torch.as_tensor(u, dtype=torch.float64).to(self.device).contiguous()
+        if ut.dim() != 2 or ut.shape[1] != self.n:
+            raise ValueError("u must be shots x n")
+        shots = ut.shape[0]
+        if bits is None:
+            bits = torch.empty((shots, self.n), dtype=torch.uint8, device=self.device)
+        if logp is None:
+            logp = torch.empty(shots, dtype=torch.float64, device=self.device)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        self._chk(lib().tnsim_sample_noalloc(self._h, shots, C.c_void_p(ut.data_ptr()),
+                                             C.c_void_p(bits.data_ptr()),
+                                             C.c_void_p(logp.data_ptr())), "sample_noalloc")
         return bits, logp
 
     def sample_prepare(self, max_shots: int) -> None:
