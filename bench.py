@@ -130,15 +130,21 @@ def parse():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--prep-layers", type=int, default=20)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "f32acc", "bf16x3", "bf16x6"],
-                    help="merge and write-back arithmetic of the batched path")
-    ap.add_argument("--storage", default="c128", choices=["c128", "c64"])
+    ap.add_argument("--precision", default=None, choices=["fp64", "f32acc", "bf16x3", "bf16x6"],
+                    help="merge and write-back arithmetic of the batched path (default: fp64 "
+                         "for the headline, bf16x6 for the batch, nonlocal, sample and qasm "
+                         "workloads)")
+    ap.add_argument("--storage", default=None, choices=["c128", "c64"],
+                    help="site storage (default: c128 for the headline, c64 for the others)")
     ap.add_argument("--profile-steps", type=int, default=-1,
                     help="layers of the profiled pass (default: all timed layers)")
     ap.add_argument("--chi", type=int, default=1024)
     ap.add_argument("--jacobi-tol", type=float, default=0.0,
                     help="relative Jacobi tolerance of the batched path (0: the library default)")
     ap.add_argument("--no-pergate", action="store_true")
+    ap.add_argument("--variants", default="fp64_c128,fp64_c128_tol30,fp64_c128_tol27,bf16x6_c64,"
+                                          "bf16x6_c64_local,fp64_c128_tol30_local",
+                    help="fidelity workload: batched variants to follow (see bench_fidelity)")
     ap.add_argument("--circuit", action="store_true",
                     help="batched path: the timed layers as one dependency-scheduled "
                          "circuit call instead of one call per sublayer")
@@ -712,11 +718,12 @@ def cpu_baseline_snapshot(gate_inputs, chi, threads, cpus_visible, model):
 def bench_fidelity(args):
     """Per-layer 1 - F of batched variants against the per-gate float64 path,
     every variant starting from the shared float64 snapshot at layer
-    --prep-layers and running the next --steps layers.  Variants (all batched,
-    QR-preconditioned float64 Jacobi): bf16x6 merge and write-back with
-    complex64 or complex128 sites, the float64 Jacobi tolerance on complex64
-    sites, and float64 throughout; "bf16x6_c64_local" restarts every layer
-    from the per-gate state, i.e. the error one layer adds."""
+    --prep-layers and running the next --steps layers (--variants picks
+    them): split-bf16 merge and write-back with complex64 or complex128
+    sites, the float64 Jacobi tolerance on complex64 sites, float64
+    throughout with the default tolerance or with 2^-30 or 2^-27; a name
+    ending in _local restarts every layer from the per-gate state, i.e. it
+    measures the error one layer adds."""
     import torch
 
     from paper_2601_04422_amd import tnsim as T
@@ -727,12 +734,19 @@ def bench_fidelity(args):
     for l in range(P):
         run_layer_batched(ref, layers[l])
     torch.cuda.synchronize()
-    spec = {"bf16x6_c64": dict(precision="bf16x6", storage="c64"),
-            "bf16x6_c128": dict(precision="bf16x6", storage="c128"),
-            "bf16x6_c64_f64tol": dict(precision="bf16x6", storage="c64",
-                                      jacobi_tol=2048 * 2.0 ** -53),
-            "fp64_c128": dict(precision="fp64", storage="c128", svd_precondition=True),
-            "bf16x6_c64_local": dict(precision="bf16x6", storage="c64")}
+    every = {"bf16x6_c64": dict(precision="bf16x6", storage="c64"),
+             "bf16x6_c128": dict(precision="bf16x6", storage="c128"),
+             "bf16x6_c64_f64tol": dict(precision="bf16x6", storage="c64",
+                                       jacobi_tol=2048 * 2.0 ** -53),
+             "fp64_c128": dict(precision="fp64", storage="c128", svd_precondition=True),
+             "fp64_c128_tol30": dict(precision="fp64", storage="c128", svd_precondition=True,
+                                     jacobi_tol=2.0 ** -30),
+             "fp64_c128_tol27": dict(precision="fp64", storage="c128", svd_precondition=True,
+                                     jacobi_tol=2.0 ** -27),
+             "bf16x6_c64_local": dict(precision="bf16x6", storage="c64"),
+             "fp64_c128_tol30_local": dict(precision="fp64", storage="c128",
+                                           svd_precondition=True, jacobi_tol=2.0 ** -30)}
+    spec = {k: every[k] for k in args.variants.split(",")}
     hs = {}
     for k, kw in spec.items():
         hs[k] = T.MPS(n, chi, 1e-12, **kw)
@@ -740,7 +754,9 @@ def bench_fidelity(args):
     curve = {k: [] for k in spec}
     secs = {k: 0.0 for k in list(spec) + ["pergate_fp64"]}
     for l in range(P, P + K):
-        hs["bf16x6_c64_local"].copy_from(ref)
+        for k in spec:
+            if k.endswith("_local"):
+                hs[k].copy_from(ref)
         for k in spec:
             t0 = time.perf_counter()
             run_layer_batched(hs[k], layers[l])
@@ -754,9 +770,11 @@ def bench_fidelity(args):
         for k in spec:
             curve[k].append(1.0 - abs(ref.overlap(hs[k])) ** 2 / (nr * hs[k].norm2()))
         log(f"layer {l}: " + ", ".join(f"{k} {curve[k][-1]:.3g}" for k in spec))
-    return {"metric": f"1 - F against the per-gate float64 path after each of {K} layers, chi={chi}",
-            "value": curve["fp64_c128"][-1], "unit": "1 - F", "n_gpus": 1, "steps": K,
-            "warmup": 0, "ms_per_step": 1e3 * secs["fp64_c128"] / K, "higher_is_better": False,
+    first = next(iter(spec))
+    return {"metric": f"1 - F of {first} against the per-gate float64 path after each of {K} "
+                      f"layers, chi={chi}",
+            "value": curve[first][-1], "unit": "1 - F", "n_gpus": 1, "steps": K,
+            "warmup": 0, "ms_per_step": 1e3 * secs[first] / K, "higher_is_better": False,
             "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
             "config": {"workload": f"n=100 benchmark circuit, layers {P}-{P + K - 1} from the "
                                    f"float64 snapshot after {P} layers, chi_max={chi}"},
@@ -799,6 +817,11 @@ def bench_calib(args):
 
 def main():
     args = parse()
+    headline = args.workload == "chi1024"
+    if args.precision is None:
+        args.precision = "fp64" if headline else "bf16x6"
+    if args.storage is None:
+        args.storage = "c128" if headline else "c64"
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no "
               "multi-GPU path", file=sys.stderr)
