@@ -152,11 +152,56 @@ __device__ __forceinline__ d4_t mfma64(double a, double b, d4_t c) {
 // pair solve mirrors the lower triangle).  In one k-step (4 rows) lane l reads
 // row 4 s + l/16 of the pair's columns 16 t + l%16 (t = 0..3): that is both
 // the A operand (conjugated) and the B operand of v_mfma_f64_16x16x4 for
-// every tile, so four loads feed all 10 upper tiles (40 MFMAs).  Each
-// wavefront takes every fourth 16-row tile; the four partial Grams are summed
-// in LDS in a fixed order at the end.
+// every tile.  Each complex product conj(x) y takes three real products
+// (Gauss): with x = a + ib, y = c + id, P1 = a c, P2 = b d,
+// P3 = (a - b)(c + d), conj(x) y = (P1 + P2) + i (P3 - P1 + P2).  Waves 0
+// and 1 compute tiles 0-4, which use all four column groups, waves 2 and 3
+// tiles 5-9, which use groups 1-3 (15 MFMAs per k-step either way); the two
+// waves of a set take alternate 16-row tiles, and their partial Grams are
+// summed in LDS in a fixed order at the end.
 constexpr int GT_A[10] = {0, 0, 0, 0, 1, 1, 1, 2, 2, 3};
 constexpr int GT_B[10] = {0, 1, 2, 3, 1, 2, 3, 2, 3, 3};
+
+template <int SET>
+__device__ __forceinline__ void gram_tiles(const double2 *const xc[4], int rbeg, int rend,
+                                           int half, int l16, int lg, d4_t (&p1)[5],
+                                           d4_t (&p2)[5], d4_t (&p3)[5]) {
+  constexpr int U0 = SET * 5, T0 = SET;  // tiles U0..U0+4 use column groups T0..3
+  // one k-step of the tile is loaded ahead of the one being multiplied
+  auto load_step = [&](double2 *x, int r) {
+#pragma unroll
+    for (int t = T0; t < 4; t++) x[t] = r < rend ? xc[t][r] : make_double2(0.0, 0.0);
+  };
+  auto mfma_step = [&](const double2 *x) {
+    double dm[4], sp[4];  // a - b of the A operand, c + d of the B operand
+#pragma unroll
+    for (int t = T0; t < 4; t++) {
+      dm[t] = x[t].x - x[t].y;
+      sp[t] = x[t].x + x[t].y;
+    }
+#pragma unroll
+    for (int u = 0; u < 5; u++) {
+      const int ta = GT_A[U0 + u], tb = GT_B[U0 + u];
+      const double2 a = x[ta], b = x[tb];  // G_pq += conj(x_rp) x_rq
+      p1[u] = mfma64(a.x, b.x, p1[u]);
+      p2[u] = mfma64(a.y, b.y, p2[u]);
+      p3[u] = mfma64(dm[ta], sp[tb], p3[u]);
+    }
+  };
+  double2 xa[4], xb[4];
+  int rt = rbeg + half * 16;
+  if (rt < rend) load_step(xa, rt + lg);
+  for (; rt < rend; rt += 32) {
+    load_step(xb, rt + 4 + lg);
+    mfma_step(xa);
+    load_step(xa, rt + 8 + lg);
+    mfma_step(xb);
+    load_step(xb, rt + 12 + lg);
+    mfma_step(xa);
+    if (rt + 32 < rend) load_step(xa, rt + 32 + lg);  // the next tile's first step
+    mfma_step(xb);
+  }
+}
 
 __global__ __launch_bounds__(256, 2) void k_gram_mfma2(const GateDesc *descs, int round,
                                                        int ksplit) {
@@ -175,61 +220,34 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma2(const GateDesc *descs, in
   const double2 *xc[4];
 #pragma unroll
   for (int t = 0; t < 4; t++) xc[t] = d.X + (size_t)pair_col(I, J, t * 16 + l16) * d.ldx;
-  d4_t accR[10], accI[10];
+  d4_t p1[5], p2[5], p3[5];
 #pragma unroll
-  for (int u = 0; u < 10; u++) {
-    accR[u] = d4_t{0.0, 0.0, 0.0, 0.0};
-    accI[u] = d4_t{0.0, 0.0, 0.0, 0.0};
+  for (int u = 0; u < 5; u++) {
+    p1[u] = d4_t{0.0, 0.0, 0.0, 0.0};
+    p2[u] = d4_t{0.0, 0.0, 0.0, 0.0};
+    p3[u] = d4_t{0.0, 0.0, 0.0, 0.0};
   }
-  // k-steps 0 and 1 of the wave's next 16-row tile are loaded while the
-  // current tile is multiplied; steps 2 and 3 while steps 0 and 1 are
-  auto load_step = [&](double2 *x, int r) {
-#pragma unroll
-    for (int t = 0; t < 4; t++) x[t] = r < rend ? xc[t][r] : make_double2(0.0, 0.0);
-  };
-  auto mfma_step = [&](const double2 *x) {
-#pragma unroll
-    for (int u = 0; u < 10; u++) {
-      const double2 a = x[GT_A[u]], b = x[GT_B[u]];  // G_pq += conj(x_rp) x_rq
-      accR[u] = mfma64(a.x, b.x, accR[u]);
-      accR[u] = mfma64(a.y, b.y, accR[u]);
-      accI[u] = mfma64(a.x, b.y, accI[u]);
-      accI[u] = mfma64(-a.y, b.x, accI[u]);
-    }
-  };
-  double2 xa[4], xb[4];  // steps 0, 1 of the current tile
-  int rt = rbeg + wave * 16;
-  if (rt < rend) {
-    load_step(xa, rt + lg);
-    load_step(xb, rt + 4 + lg);
-  }
-  for (; rt < rend; rt += 64) {
-    double2 xc2[4], xd[4];  // steps 2, 3
-    load_step(xc2, rt + 8 + lg);
-    load_step(xd, rt + 12 + lg);
-    mfma_step(xa);
-    mfma_step(xb);
-    if (rt + 64 < rend) {  // next tile's steps 0, 1
-      load_step(xa, rt + 64 + lg);
-      load_step(xb, rt + 68 + lg);
-    }
-    mfma_step(xc2);
-    mfma_step(xd);
-  }
-  // sum of the four wavefronts' partials, in wavefront order
+  const int set = wave >> 1, half = wave & 1;
+  if (set == 0)
+    gram_tiles<0>(xc, rbeg, rend, half, l16, lg, p1, p2, p3);
+  else
+    gram_tiles<1>(xc, rbeg, rend, half, l16, lg, p1, p2, p3);
+  // sum of the two wavefronts of each set, the first one's partial first
   __shared__ double red[10][4][64][2];
-  for (int w = 0; w < 4; w++) {
-    if (wave == w) {
+  for (int h = 0; h < 2; h++) {
+    if (half == h) {
 #pragma unroll
-      for (int u = 0; u < 10; u++)
+      for (int u = 0; u < 5; u++)
 #pragma unroll
         for (int v = 0; v < 4; v++) {
-          if (w == 0) {
-            red[u][v][lane][0] = accR[u][v];
-            red[u][v][lane][1] = accI[u][v];
+          const double gr = p1[u][v] + p2[u][v], gi = p3[u][v] - p1[u][v] + p2[u][v];
+          double *o = red[set * 5 + u][v][lane];
+          if (h == 0) {
+            o[0] = gr;
+            o[1] = gi;
           } else {
-            red[u][v][lane][0] += accR[u][v];
-            red[u][v][lane][1] += accI[u][v];
+            o[0] += gr;
+            o[1] += gi;
           }
         }
     }
@@ -462,7 +480,9 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(const GateDesc *descs, int 
 // one column) and the result (16 lanes = 16 consecutive rows of one column)
 // are both contiguous 256-byte segments.  A wavefront owns whole 16-row tiles
 // (all 64 columns), so it overwrites exactly the rows it read and needs no
-// barrier; two workgroups per CU hide the load latency.
+// barrier; two workgroups per CU hide the load latency.  Each complex product
+// takes three real products (Gauss): with v = a + ib and x = c + id,
+// P1 = a c, P2 = b d, P3 = (a + b)(c + d), v x = (P1 - P2) + i (P3 - P1 - P2).
 __global__ __launch_bounds__(256, 2) void k_rot_mfma3(const GateDesc *descs, int round) {
   const GateDesc &d = descs[blockIdx.y];
   if (!d.sc->active || round >= d.nblk - 1) return;
@@ -521,22 +541,23 @@ __global__ __launch_bounds__(256, 2) void k_rot_mfma3(const GateDesc *descs, int
     load_half(xb + BW / 4, 1, rt);
     double2 xn[BW / 4];
     if (rt + 64 < r1) load_half(xn, 0, rt + 64);
-    d4_t accR[4], accI[4];
+    d4_t p1[4], p2[4], p3[4];
 #pragma unroll
     for (int t = 0; t < 4; t++) {
-      accR[t] = d4_t{0.0, 0.0, 0.0, 0.0};
-      accI[t] = d4_t{0.0, 0.0, 0.0, 0.0};
+      p1[t] = d4_t{0.0, 0.0, 0.0, 0.0};
+      p2[t] = d4_t{0.0, 0.0, 0.0, 0.0};
+      p3[t] = d4_t{0.0, 0.0, 0.0, 0.0};
     }
 #pragma unroll
     for (int s = 0; s < PW / 4; s++) {
       const double2 b = xb[s];  // X^T[k][row]
+      const double bs = b.x + b.y;
 #pragma unroll
       for (int t = 0; t < 4; t++) {
         const double2 a = Vs[(4 * s + lg) * LDG + t * 16 + l16];  // V^T[col][k]
-        accR[t] = mfma64(a.x, b.x, accR[t]);
-        accR[t] = mfma64(-a.y, b.y, accR[t]);
-        accI[t] = mfma64(a.x, b.y, accI[t]);
-        accI[t] = mfma64(a.y, b.x, accI[t]);
+        p1[t] = mfma64(a.x, b.x, p1[t]);
+        p2[t] = mfma64(a.y, b.y, p2[t]);
+        p3[t] = mfma64(a.x + a.y, bs, p3[t]);
       }
       __builtin_amdgcn_sched_barrier(0);  // keep each step's V reads in that step
     }
@@ -547,7 +568,8 @@ __global__ __launch_bounds__(256, 2) void k_rot_mfma3(const GateDesc *descs, int
 #pragma unroll
         for (int v = 0; v < 4; v++) {
           const int c = t * 16 + lg + 4 * v;
-          base[(size_t)pair_col(I, J, c) * ld + r] = make_double2(accR[t][v], accI[t][v]);
+          base[(size_t)pair_col(I, J, c) * ld + r] =
+              make_double2(p1[t][v] - p2[t][v], p3[t][v] - p1[t][v] - p2[t][v]);
         }
     }
 #pragma unroll
