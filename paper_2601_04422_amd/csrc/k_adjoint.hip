@@ -53,13 +53,14 @@ __global__ __launch_bounds__(256) void k_gemm_gen(GemmArgs g) {
   };
   const int wv = tid >> 6, lane = tid & 63, l16 = lane & 15, lg = lane >> 4;
   const int wm = (wv & 1) * 32, wn = (wv >> 1) * 32;
-  f64x4_t cr[2][2], ci[2][2];
+  f64x4_t c1[2][2], c2[2][2], c3[2][2];  // Gauss: a c, b d, (a + b)(c + d)
 #pragma unroll
   for (int x = 0; x < 2; x++)
 #pragma unroll
     for (int y = 0; y < 2; y++) {
-      cr[x][y] = f64x4_t{0.0, 0.0, 0.0, 0.0};
-      ci[x][y] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+      c1[x][y] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+      c2[x][y] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+      c3[x][y] = f64x4_t{0.0, 0.0, 0.0, 0.0};
     }
   load(0);
   for (int k0 = 0; k0 < g.K; k0 += 16) {
@@ -82,10 +83,9 @@ __global__ __launch_bounds__(256) void k_gemm_gen(GemmArgs g) {
       for (int x = 0; x < 2; x++)
 #pragma unroll
         for (int y = 0; y < 2; y++) {
-          cr[x][y] = adj_mfma(a[x].x, b[y].x, cr[x][y]);
-          cr[x][y] = adj_mfma(-a[x].y, b[y].y, cr[x][y]);
-          ci[x][y] = adj_mfma(a[x].x, b[y].y, ci[x][y]);
-          ci[x][y] = adj_mfma(a[x].y, b[y].x, ci[x][y]);
+          c1[x][y] = adj_mfma(a[x].x, b[y].x, c1[x][y]);
+          c2[x][y] = adj_mfma(a[x].y, b[y].y, c2[x][y]);
+          c3[x][y] = adj_mfma(a[x].x + a[x].y, b[y].x + b[y].y, c3[x][y]);
         }
     }
     __syncthreads();
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(256) void k_gemm_gen(GemmArgs g) {
         const int gi = i0 + wm + 16 * x + lg + 4 * v;
         if (gi < g.M && gj < g.N) {
           double2 *c = g.C + gi * g.sc_i + gj * g.sc_j;
-          const double2 val = cmul(g.alpha, make_double2(cr[x][y][v], ci[x][y][v]));
+          const double2 val = cmul(g.alpha, make_double2((c1[x][y][v] - c2[x][y][v]), (c3[x][y][v] - c1[x][y][v] - c2[x][y][v])));
           *c = g.accumulate ? cadd(*c, val) : val;
         }
       }

@@ -123,13 +123,14 @@ __device__ void theta_tile_f64mfma(const GateDesc &d, int r0, int c0, double2 *s
   };
   const int w = tid >> 6, lane = tid & 63, l16 = lane & 15, lg = lane >> 4;
   const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
-  f64x4_t cr[2][2], ci[2][2];
+  f64x4_t c1[2][2], c2[2][2], c3[2][2];  // Gauss: a c, b d, (a + b)(c + d)
 #pragma unroll
   for (int x = 0; x < 2; x++)
 #pragma unroll
     for (int y = 0; y < 2; y++) {
-      cr[x][y] = f64x4_t{0.0, 0.0, 0.0, 0.0};
-      ci[x][y] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+      c1[x][y] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+      c2[x][y] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+      c3[x][y] = f64x4_t{0.0, 0.0, 0.0, 0.0};
     }
   load(0);
   for (int k0 = 0; k0 < chiM; k0 += TK) {
@@ -152,10 +153,9 @@ __device__ void theta_tile_f64mfma(const GateDesc &d, int r0, int c0, double2 *s
       for (int x = 0; x < 2; x++)
 #pragma unroll
         for (int y = 0; y < 2; y++) {
-          cr[x][y] = mfma_f64(a[x].x, b[y].x, cr[x][y]);
-          cr[x][y] = mfma_f64(-a[x].y, b[y].y, cr[x][y]);
-          ci[x][y] = mfma_f64(a[x].x, b[y].y, ci[x][y]);
-          ci[x][y] = mfma_f64(a[x].y, b[y].x, ci[x][y]);
+          c1[x][y] = mfma_f64(a[x].x, b[y].x, c1[x][y]);
+          c2[x][y] = mfma_f64(a[x].y, b[y].y, c2[x][y]);
+          c3[x][y] = mfma_f64(a[x].x + a[x].y, b[y].x + b[y].y, c3[x][y]);
         }
     }
     __syncthreads();
@@ -169,7 +169,7 @@ __device__ void theta_tile_f64mfma(const GateDesc &d, int r0, int c0, double2 *s
 #pragma unroll
       for (int v = 0; v < 4; v++)
         Cs[(wm + 16 * x + lg + 4 * v) * LD + wn + 16 * y + l16] =
-            make_double2(cr[x][y][v], ci[x][y][v]);
+            make_double2((c1[x][y][v] - c2[x][y][v]), (c3[x][y][v] - c1[x][y][v] - c2[x][y][v]));
   __syncthreads();
   theta_epilogue(d, r0, c0, Cs);
 }

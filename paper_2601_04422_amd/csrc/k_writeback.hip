@@ -106,13 +106,14 @@ __device__ void wb_right_tile_f64mfma(const GateDesc &d, int k, int j0, int c0, 
   };
   const int w = tid >> 6, lane = tid & 63, l16 = lane & 15, lg = lane >> 4;
   const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
-  f64x4_t cr[2][2], ci[2][2];
+  f64x4_t c1[2][2], c2[2][2], c3[2][2];  // Gauss: a c, b d, (a + b)(c + d)
 #pragma unroll
   for (int x = 0; x < 2; x++)
 #pragma unroll
     for (int y = 0; y < 2; y++) {
-      cr[x][y] = f64x4_t{0.0, 0.0, 0.0, 0.0};
-      ci[x][y] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+      c1[x][y] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+      c2[x][y] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+      c3[x][y] = f64x4_t{0.0, 0.0, 0.0, 0.0};
     }
   load(0);
   for (int r0 = 0; r0 < m; r0 += 16) {
@@ -135,10 +136,9 @@ __device__ void wb_right_tile_f64mfma(const GateDesc &d, int k, int j0, int c0, 
       for (int x = 0; x < 2; x++)
 #pragma unroll
         for (int y = 0; y < 2; y++) {
-          cr[x][y] = wb_mfma_f64(a[x].x, b[y].x, cr[x][y]);
-          cr[x][y] = wb_mfma_f64(-a[x].y, b[y].y, cr[x][y]);
-          ci[x][y] = wb_mfma_f64(a[x].x, b[y].y, ci[x][y]);
-          ci[x][y] = wb_mfma_f64(a[x].y, b[y].x, ci[x][y]);
+          c1[x][y] = wb_mfma_f64(a[x].x, b[y].x, c1[x][y]);
+          c2[x][y] = wb_mfma_f64(a[x].y, b[y].y, c2[x][y]);
+          c3[x][y] = wb_mfma_f64(a[x].x + a[x].y, b[y].x + b[y].y, c3[x][y]);
         }
     }
     __syncthreads();
@@ -155,7 +155,7 @@ __device__ void wb_right_tile_f64mfma(const GateDesc &d, int k, int j0, int c0, 
         const int gjo = j0 + wm + 16 * x + lg + 4 * v;
         if (gjo < k && gc < n)
           cstore(A1 + (size_t)gjo * n + gc,
-                 make_double2(cr[x][y][v] * invN, ci[x][y][v] * invN));
+                 make_double2((c1[x][y][v] - c2[x][y][v]) * invN, (c3[x][y][v] - c1[x][y][v] - c2[x][y][v]) * invN));
       }
     }
 }
