@@ -167,7 +167,7 @@ __device__ __forceinline__ void gram_tiles(const double2 *const xc[4], int rbeg,
                                            int half, int l16, int lg, d4_t (&p1)[5],
                                            d4_t (&p2)[5], d4_t (&p3)[5]) {
   constexpr int U0 = SET * 5, T0 = SET;  // tiles U0..U0+4 use column groups T0..3
-  // one k-step of the tile is loaded ahead of the one being multiplied
+  // loads of the 16-lane column groups T0..3 for one k-step (4 rows)
   auto load_step = [&](double2 *x, int r) {
 #pragma unroll
     for (int t = T0; t < 4; t++) x[t] = r < rend ? xc[t][r] : make_double2(0.0, 0.0);
@@ -188,18 +188,27 @@ __device__ __forceinline__ void gram_tiles(const double2 *const xc[4], int rbeg,
       p3[u] = mfma64(dm[ta], sp[tb], p3[u]);
     }
   };
-  double2 xa[4], xb[4];
-  int rt = rbeg + half * 16;
-  if (rt < rend) load_step(xa, rt + lg);
-  for (; rt < rend; rt += 32) {
-    load_step(xb, rt + 4 + lg);
-    mfma_step(xa);
-    load_step(xa, rt + 8 + lg);
-    mfma_step(xb);
-    load_step(xb, rt + 12 + lg);
-    mfma_step(xa);
-    if (rt + 32 < rend) load_step(xa, rt + 32 + lg);  // the next tile's first step
-    mfma_step(xb);
+  // the wavefront's k-steps: 16-row tiles base, base + 32, ... (the other
+  // wavefront of the set takes the tiles in between), 4 steps per tile;
+  // loads run three steps ahead of the products
+  const int base = rbeg + half * 16;
+  const int nstep = base < rend ? (rend - base + 31) / 32 * 4 : 0;
+  auto row_of = [&](int n) { return base + 32 * (n >> 2) + 4 * (n & 3) + lg; };
+  double2 x0[4], x1[4], x2[4], x3[4];
+  if (nstep > 0) {
+    load_step(x0, row_of(0));
+    load_step(x1, row_of(1));
+    load_step(x2, row_of(2));
+  }
+  for (int n = 0; n < nstep; n += 4) {
+    load_step(x3, row_of(n + 3));
+    mfma_step(x0);
+    if (n + 4 < nstep) load_step(x0, row_of(n + 4));
+    mfma_step(x1);
+    if (n + 4 < nstep) load_step(x1, row_of(n + 5));
+    mfma_step(x2);
+    if (n + 4 < nstep) load_step(x2, row_of(n + 6));
+    mfma_step(x3);
   }
 }
 
@@ -269,16 +278,40 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma2(const GateDesc *descs, in
 
 constexpr int LDG = PW + 1;
 constexpr int EIG_THREADS = 1024;  // 16 wavefronts hide the LDS latency of the pair solve
+constexpr int EIG_OFFD = (PW / 2) * (PW / 2 - 1) / 2;  // off-diagonal 2x2 blocks (i < j)
 
-// Cyclic two-sided Jacobi on the pair Gram G (64x64, in LDS) with the
-// rotations accumulated in V.  A round applies the 32 disjoint rotations of
-// the round-robin pairing at once: G <- R^H G R, V <- V R.  Entries of G are
-// updated as 2x2 blocks (rows of one pair x columns of another), so every
-// entry is read and written once per round.  The rotations of round r + 1
-// are computed by the first wavefront while the others apply round r to V
-// (parameters double-buffered), so a round costs two barriers.  At most
-// `inner_sweeps` sweeps; the outer sweeps finish what a capped inner solve
-// leaves.
+// Circle-method tournament over the 64 columns of a pair solve: in round r
+// slot 0 pairs column 63 with column r, slot k >= 1 pairs (r + k) mod 63
+// with (r - k) mod 63.  Neighbouring slots hold neighbouring columns, so the
+// LDS addresses of neighbouring lanes (row * 65 + column) fall in distinct
+// banks.  Columns are not reordered within a pair.
+__device__ __forceinline__ void eig_pair(int r, int k, int &p, int &q) {
+  if (k == 0) {
+    p = PW - 1;
+    q = r;
+  } else {
+    p = r + k;
+    if (p >= PW - 1) p -= PW - 1;
+    q = r - k;
+    if (q < 0) q += PW - 1;
+  }
+}
+
+// Off-diagonal entry (a, b), a != b, of the Hermitian pair Gram: only the
+// upper triangle is stored, entry (a, b) at min(a, b) * 65 + max(a, b).
+__device__ __forceinline__ int gslot(int a, int b) { return a < b ? a * LDG + b : b * LDG + a; }
+
+// Cyclic two-sided Jacobi on the pair Gram G (64x64 Hermitian, in LDS) with
+// the rotations accumulated in V.  A round applies the 32 disjoint rotations
+// of the tournament at once: G <- R^H G R, V <- V R.  G keeps its upper
+// triangle only (the diagonal in a separate array): the 496 off-diagonal
+// 2x2 blocks (rows of pair i x columns of pair j, i < j) are updated by one
+// thread each, and the 2x2 diagonal block of a rotating pair takes its
+// exact values (new diagonal entries, zero coupling) when the rotation is
+// computed.  The rotations of round r + 1 are computed by the first
+// wavefront while the others apply round r to V (parameters double-
+// buffered), so a round costs two barriers.  At most `inner_sweeps` sweeps;
+// the outer sweeps finish what a capped inner solve leaves.
 __global__ __launch_bounds__(EIG_THREADS) void k_eig(const GateDesc *descs, int round, int ksplit) {
   const GateDesc &d = descs[blockIdx.y];
   const int pairIdx = blockIdx.x;
@@ -291,29 +324,32 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(const GateDesc *descs, int 
   }
   __shared__ double2 Gs[PW * LDG];
   __shared__ double2 Vs[PW * LDG];
+  __shared__ double dg[PW];           // diagonal of G
   __shared__ double rc[2][PW / 2];    // cos
   __shared__ double2 rse[2][PW / 2];  // s * e^{i phi}
-  __shared__ double rdp[2][PW / 2], rdq[2][PW / 2];  // new diagonal entries
-  __shared__ int rp[2][PW / 2], rq[2][PW / 2], ract[2][PW / 2];
+  __shared__ int rp[2][PW / 2], rq[2][PW / 2];
   __shared__ int anyr[2];  // some rotation in the round held by that buffer
   __shared__ int sweep_rot, first_rot;
   const int tid = threadIdx.x;
-  const double tol = d.tol;
+  const double tol2 = d.tol * d.tol;
   const double small = small_norm2(d);
   unsigned nrot_local = 0;  // rotations applied by this thread (profiling)
 
   for (int e = tid; e < PW * PW; e += EIG_THREADS) {
-    int r = e / PW, c = e % PW;
-    // the Gram kernels store the upper 16x16 tiles; lower ones are mirrored
-    const bool lower = (r >> 4) > (c >> 4);
-    const int src = lower ? c * PW + r : e;
-    double2 sm = make_double2(0.0, 0.0);
-    for (int kc = 0; kc < ksplit; kc++) {
-      double2 v = d.Gp[((size_t)kc * d.gpStride + pairIdx) * (PW * PW) + src];
-      sm.x += v.x;
-      sm.y += v.y;
+    const int r = e / PW, c = e % PW;
+    // upper entries lie in the upper 16x16 tiles that the Gram kernels store
+    if (r <= c) {
+      double2 sm = make_double2(0.0, 0.0);
+      for (int kc = 0; kc < ksplit; kc++) {
+        const double2 v = d.Gp[((size_t)kc * d.gpStride + pairIdx) * (PW * PW) + e];
+        sm.x += v.x;
+        sm.y += v.y;
+      }
+      if (r < c)
+        Gs[r * LDG + c] = sm;
+      else
+        dg[r] = sm.x;
     }
-    Gs[r * LDG + c] = lower ? cconj(sm) : sm;
     Vs[r * LDG + c] = make_double2(r == c ? 1.0 : 0.0, 0.0);
   }
   if (tid == 0) first_rot = 0;
@@ -321,37 +357,57 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(const GateDesc *descs, int 
 
   // Rotations of round r into buffer b, from the current G (first wavefront
   // only: lanes < 32 hold one pair each, the ballot gives the round's flag).
+  // With delta = b - a and h = |g|^2 for the pair's 2x2 block [[a, g],
+  // [conj g, b]], the rotation that zeroes g has tangent t = w |g|,
+  // w = 2 sign(delta) / (|delta| + sqrt(delta^2 + 4h)), cosine
+  // c = 1 / sqrt(1 + w^2 h), s e^{i phi} = c w g, and the new diagonal is
+  // (a - w h, b + w h).  The pair's own block is set to those values here:
+  // no other thread reads or writes it until the round is applied.
   auto params = [&](int r, int b) {
     int act = 0;
     if (tid < PW / 2) {
       int p, q;
-      rr_pair(r, tid, PW, p, q);
+      eig_pair(r, tid, p, q);
       rp[b][tid] = p;
       rq[b][tid] = q;
-      const double a = Gs[p * LDG + p].x, bb = Gs[q * LDG + q].x;
-      const double2 g = Gs[p * LDG + q];
-      const double ag = sqrt(cabs2(g));
+      const double a = dg[p], bb = dg[q];
+      const int gs = gslot(p, q);
+      const double2 g = p < q ? Gs[gs] : cconj(Gs[gs]);
+      const double h = cabs2(g);
       double c = 1.0;
       double2 se = make_double2(0.0, 0.0);
-      if (a > small && bb > small && ag > tol * sqrt(a) * sqrt(bb)) {
+      if (a > small && bb > small && h > tol2 * a * bb) {
         act = 1;
-        const double2 e = make_double2(g.x / ag, g.y / ag);  // e^{i phi}
-        const double zeta = (bb - a) / (2.0 * ag);
-        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        c = 1.0 / sqrt(1.0 + t * t);
-        const double sn = c * t;
-        se = make_double2(sn * e.x, sn * e.y);
-        rdp[b][tid] = a - t * ag;
-        rdq[b][tid] = bb + t * ag;
+        const double delta = bb - a;
+        const double w = (delta >= 0.0 ? 2.0 : -2.0) / (fabs(delta) + sqrt(delta * delta + 4.0 * h));
+        c = 1.0 / sqrt(1.0 + w * w * h);
+        const double cw = c * w;
+        se = make_double2(cw * g.x, cw * g.y);
+        dg[p] = a - w * h;
+        dg[q] = bb + w * h;
+        Gs[gs] = make_double2(0.0, 0.0);
         nrot_local++;
       }
       rc[b][tid] = c;
       rse[b][tid] = se;
-      ract[b][tid] = act;
     }
     const unsigned long long m = __ballot(act);
     if (tid == 0) anyr[b] = m != 0ull;
   };
+
+  // this thread's off-diagonal block: the upper triangle of 32 x 32 pair
+  // indices folded into 16 rows of 31 (row a with row 31 - a)
+  int bi = 0, bj = 0;
+  if (tid < EIG_OFFD) {
+    const int a = tid / (PW / 2 - 1), col = tid - (PW / 2 - 1) * a;
+    if (col < PW / 2 - 1 - a) {
+      bi = a;
+      bj = a + 1 + col;
+    } else {
+      bi = PW / 2 - 1 - a;
+      bj = col + 1;
+    }
+  }
 
   for (int sweep = 0; sweep < d.innerSweeps; sweep++) {
     if (tid == 0) sweep_rot = 0;
@@ -360,61 +416,40 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(const GateDesc *descs, int 
     for (int r = 0; r < PW - 1; r++) {
       const int b = r & 1;
       const bool any = anyr[b] != 0;
-      if (any) {
+      if (any && tid < EIG_OFFD) {
         // R = [[c, s e^{i phi}], [-s e^{-i phi}, c]] on columns (p, q);
         // block (row pair i, column pair j): B <- R_i^H B R_j.  A pair that
         // does not rotate has c = 1, s = 0, which leaves its entries exactly
-        // as they are, so every block is updated without branches; each
-        // thread loads both of its blocks before computing.
-        constexpr int GPT = (PW / 2) * (PW / 2) / EIG_THREADS;  // blocks per thread
-        static_assert(GPT * EIG_THREADS == (PW / 2) * (PW / 2), "whole blocks per thread");
-        const int j = tid & 31, i0 = tid >> 5;
-        const int pj = rp[b][j], qj = rq[b][j];
-        const double cj = rc[b][j];
-        const double2 sej = rse[b][j], secj = cconj(sej);
-        double2 blk[GPT][4];
-        int pis[GPT], qis[GPT];
-#pragma unroll
-        for (int h = 0; h < GPT; h++) {
-          const int i = i0 + (EIG_THREADS / 32) * h;
-          pis[h] = rp[b][i];
-          qis[h] = rq[b][i];
-          blk[h][0] = Gs[pis[h] * LDG + pj];
-          blk[h][1] = Gs[pis[h] * LDG + qj];
-          blk[h][2] = Gs[qis[h] * LDG + pj];
-          blk[h][3] = Gs[qis[h] * LDG + qj];
+        // as they are, so every block is updated without branches.
+        const int pi = rp[b][bi], qi = rq[b][bi], pj = rp[b][bj], qj = rq[b][bj];
+        const int s00 = gslot(pi, pj), s01 = gslot(pi, qj), s10 = gslot(qi, pj), s11 = gslot(qi, qj);
+        double2 b00 = Gs[s00], b01 = Gs[s01], b10 = Gs[s10], b11 = Gs[s11];
+        if (pi > pj) b00 = cconj(b00);
+        if (pi > qj) b01 = cconj(b01);
+        if (qi > pj) b10 = cconj(b10);
+        if (qi > qj) b11 = cconj(b11);
+        {  // columns: [x_p x_q] R_j
+          const double cj = rc[b][bj];
+          const double2 sej = rse[b][bj], secj = cconj(sej);
+          const double2 n00 = csub(cscale(b00, cj), cmul(secj, b01));
+          const double2 n01 = cadd(cmul(sej, b00), cscale(b01, cj));
+          const double2 n10 = csub(cscale(b10, cj), cmul(secj, b11));
+          const double2 n11 = cadd(cmul(sej, b10), cscale(b11, cj));
+          b00 = n00; b01 = n01; b10 = n10; b11 = n11;
         }
-#pragma unroll
-        for (int h = 0; h < GPT; h++) {
-          const int i = i0 + (EIG_THREADS / 32) * h;
-          double2 b00 = blk[h][0], b01 = blk[h][1], b10 = blk[h][2], b11 = blk[h][3];
-          {  // columns: [x_p x_q] R_j
-            double2 n00 = csub(cscale(b00, cj), cmul(secj, b01));
-            double2 n01 = cadd(cmul(sej, b00), cscale(b01, cj));
-            double2 n10 = csub(cscale(b10, cj), cmul(secj, b11));
-            double2 n11 = cadd(cmul(sej, b10), cscale(b11, cj));
-            b00 = n00; b01 = n01; b10 = n10; b11 = n11;
-          }
-          {  // rows: R_i^H [row_p; row_q]
-            const double ci = rc[b][i];
-            const double2 sei = rse[b][i], seci = cconj(sei);
-            double2 n00 = csub(cscale(b00, ci), cmul(sei, b10));
-            double2 n01 = csub(cscale(b01, ci), cmul(sei, b11));
-            double2 n10 = cadd(cmul(seci, b00), cscale(b10, ci));
-            double2 n11 = cadd(cmul(seci, b01), cscale(b11, ci));
-            b00 = n00; b01 = n01; b10 = n10; b11 = n11;
-          }
-          if (i == j && ract[b][i]) {  // the annihilated pair: exact values
-            b00 = make_double2(rdp[b][i], 0.0);
-            b11 = make_double2(rdq[b][i], 0.0);
-            b01 = make_double2(0.0, 0.0);
-            b10 = make_double2(0.0, 0.0);
-          }
-          Gs[pis[h] * LDG + pj] = b00;
-          Gs[pis[h] * LDG + qj] = b01;
-          Gs[qis[h] * LDG + pj] = b10;
-          Gs[qis[h] * LDG + qj] = b11;
+        {  // rows: R_i^H [row_p; row_q]
+          const double ci = rc[b][bi];
+          const double2 sei = rse[b][bi], seci = cconj(sei);
+          const double2 n00 = csub(cscale(b00, ci), cmul(sei, b10));
+          const double2 n01 = csub(cscale(b01, ci), cmul(sei, b11));
+          const double2 n10 = cadd(cmul(seci, b00), cscale(b10, ci));
+          const double2 n11 = cadd(cmul(seci, b01), cscale(b11, ci));
+          b00 = n00; b01 = n01; b10 = n10; b11 = n11;
         }
+        Gs[s00] = pi < pj ? b00 : cconj(b00);
+        Gs[s01] = pi < qj ? b01 : cconj(b01);
+        Gs[s10] = qi < pj ? b10 : cconj(b10);
+        Gs[s11] = qi < qj ? b11 : cconj(b11);
       }
       __syncthreads();  // G after round r
       if (tid < 64 && r + 1 < PW - 1) params(r + 1, b ^ 1);
