@@ -360,25 +360,35 @@ tnsim_status tnsim_profile(tnsim_mps mps, int32_t enable);
 /* out has TNSIM_K_COUNT entries (synchronising). */
 tnsim_status tnsim_profile_read(tnsim_mps mps, tnsim_kernel_stat *out);
 
-/* Launch-shape autotuner (synchronising).  Times the Jacobi rotation kernel
-   on this handle's workspace slots (zeroed scratch; the state is not touched)
-   for every candidate number of rows per workgroup (64, 128, 256, 512) in
+/* Launch-shape autotuner (synchronising).  Times two Jacobi kernels on this
+   handle's workspace slots (zeroed scratch; the state is not touched) in
    each of TNSIM_TUNE_BUCKETS pair-count classes (<= 32, <= 128, <= 512 and
    more pairs per launch, largest gate the handle can hold) and keeps the
-   fastest; later sweeps use the table instead of the built-in rule.  The
-   choice does not change any result: every row is computed the same way.
-   table_out (host, TNSIM_TUNE_BUCKETS entries, may be NULL) receives the rows
-   per workgroup chosen for each class.  Errors: TNSIM_E_ARG (bad handle),
+   fastest shape of each; later sweeps use the table instead of the built-in
+   rules:
+     - the rotation: rows per workgroup, one of 64, 128, 256, 512;
+     - the pair Grams: K-split, the number of row chunks (1, 2, 4, 8, 16)
+       whose partial Grams the pair solve adds up, within the handle's pool
+       of partials (room for a K-split of 4 with every slot in use).
+   The rotation shape does not change any result (every row is computed the
+   same way); the K-split changes the order in which a Gram's row sums are
+   added, so results agree to rounding with those of the built-in rule.
+   table_out (host, TNSIM_TUNE_ENTRIES entries, may be NULL) receives the
+   rows per rotation workgroup of each class in entries 0..3 and the Gram
+   K-split of each class in entries 4..7.  Errors: TNSIM_E_ARG (bad handle),
    TNSIM_E_DEVICE. */
 #define TNSIM_TUNE_BUCKETS 4
+#define TNSIM_TUNE_ENTRIES (2 * TNSIM_TUNE_BUCKETS)
 tnsim_status tnsim_autotune(tnsim_mps mps, int32_t *table_out);
 
-/* Install a launch-shape table (host, TNSIM_TUNE_BUCKETS entries, each 0 for
-   the built-in rule or one of 64, 128, 256, 512 rows per rotation workgroup),
-   e.g. one that tnsim_autotune chose on another handle of the same shape, so
-   that both run the same launches.  Results never depend on the table.
-   Errors: TNSIM_E_ARG (bad handle, NULL table or an entry outside that set;
-   the handle's table is then unchanged). */
+/* Install a launch-shape table (host, TNSIM_TUNE_ENTRIES entries laid out as
+   tnsim_autotune's: rows per rotation workgroup, 0 for the built-in rule or
+   one of 64, 128, 256, 512, then Gram K-splits, 0 for the built-in rule or a
+   power of two up to 16; a K-split beyond what a launch's pool of partials
+   or its rows allow is reduced to fit), e.g. one that tnsim_autotune chose
+   on another handle of the same shape, so that both run the same launches.
+   Errors: TNSIM_E_ARG (bad handle, NULL table or an entry outside those
+   sets; the handle's table is then unchanged). */
 tnsim_status tnsim_set_launch_table(tnsim_mps mps, const int32_t *table);
 
 /* ---- circuit front end (host only; no device work) ----

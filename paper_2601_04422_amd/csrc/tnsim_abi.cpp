@@ -136,7 +136,8 @@ Layout make_layout(const tnsim_config &c) {
   L.slot_bytes = s;
   L.slot0_off = off;
   off = align_up(off + L.slot_bytes * L.nslots);
-  L.gp_blocks = std::max(L.nslots, KSPLIT_MAX) * L.npairs_max;
+  // partial pair Grams: room for a K-split of GP_PER_SLOT with every slot active
+  L.gp_blocks = std::max(L.nslots * GP_PER_SLOT, KSPLIT_MAX) * L.npairs_max;
   L.gp_off = off;
   off = align_up(off + sizeof(double2) * (size_t)L.gp_blocks * PW * PW);
   L.desc_off = off;
@@ -271,6 +272,7 @@ struct tnsim_mps_s {
   bool pair_skip = true;  // skip Grams of block pairs known orthogonal (TNSIM_PAIR_SKIP=0: off)
   int gram_wg_target = 1024;  // K-split the pair Grams up to this many workgroups
   int tune_rot_rows[TNSIM_TUNE_BUCKETS] = {0, 0, 0, 0};  // autotuned, 0 = built-in rule
+  int tune_gram_ks[TNSIM_TUNE_BUCKETS] = {0, 0, 0, 0};   // autotuned, 0 = built-in rule
   hipGraphExec_t sweep_exec = nullptr;
   long long sweep_key[7] = {-1, -1, -1, -1, -1, -1, -1};
   int64_t sw_gates = 0, sw_sum = 0;
@@ -580,7 +582,8 @@ struct SweepRunner {
       if (d->trans) P.maxMtrans = std::max(P.maxMtrans, d->m);
     }
     const int pairs = P.na * P.maxPairs;
-    int ks = (o->gram_wg_target + pairs - 1) / pairs;
+    const int tuned_ks = o->tune_gram_ks[tune_bucket(pairs)];
+    int ks = tuned_ks > 0 ? tuned_ks : (o->gram_wg_target + pairs - 1) / pairs;
     ks = std::min(ks, KSPLIT_MAX);
     ks = std::min(ks, std::max(1, (P.maxRows + 31) / 32));
     // each gate's partials go to its handle's pool, at its position among the
@@ -2839,6 +2842,7 @@ tnsim_status tnsim_autotune(tnsim_mps h, int32_t *table_out) {
     d.V = (double2 *)(sl + L.v_off);
     d.pairFlag = (int *)(sl + L.pf_off);
     d.sc = (SlotScalars *)(sl + L.sc_off);
+    d.gpStride = L.npairs_max;
     launch_fill_zero(h->stream, d.X, sizeof(double2) * (size_t)L.ldx_max * cols);
     launch_fill_zero(h->stream, d.V, sizeof(double2) * (size_t)npairs * PW * PW);
   }
@@ -2880,6 +2884,33 @@ tnsim_status tnsim_autotune(tnsim_mps h, int32_t *table_out) {
     }
     h->tune_rot_rows[bk] = best;
     if (table_out) table_out[bk] = best;
+    // pair Grams: rows split over 1, 2, 4, ... workgroups (partials summed by
+    // the pair solve), within the partial-Gram pool and 32 rows per chunk
+    int best_ks = 0;
+    best_ms = 0.0f;
+    for (int ks = 1; ks <= KSPLIT_MAX; ks *= 2) {
+      if (ks > 1 && (ks > (rows + 31) / 32 || (long long)ng * ks * L.npairs_max > L.gp_blocks))
+        break;
+      for (int g = 0; g < ng; g++)
+        D[g].Gp = h->at<double2>(L.gp_off) + (size_t)g * ks * L.npairs_max * PW * PW;
+      memcpy(h->pin, D.data(), sizeof(GateDesc) * ng);
+      HIPCHK(h, hipMemcpyAsync(ddev, h->pin, sizeof(GateDesc) * ng, hipMemcpyHostToDevice,
+                               h->stream));
+      launch_gram(h->stream, ddev, ng, 0, npairs, ks);  // warm-up
+      HIPCHK(h, hipEventRecord(e0, h->stream));
+      for (int r = 0; r < 3; r++) launch_gram(h->stream, ddev, ng, r, npairs, ks);
+      HIPCHK(h, hipEventRecord(e1, h->stream));
+      LAUNCHCHK(h, "autotune");
+      HIPCHK(h, hipEventSynchronize(e1));
+      float ms = 0.0f;
+      HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
+      if (best_ks == 0 || ms < best_ms) {
+        best_ks = ks;
+        best_ms = ms;
+      }
+    }
+    h->tune_gram_ks[bk] = best_ks;
+    if (table_out) table_out[TNSIM_TUNE_BUCKETS + bk] = best_ks;
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
@@ -2891,10 +2922,14 @@ tnsim_status tnsim_set_launch_table(tnsim_mps h, const int32_t *table) {
   if (s != TNSIM_OK) return s;
   if (!table) return TNSIM_E_ARG;
   for (int bk = 0; bk < TNSIM_TUNE_BUCKETS; bk++) {
-    const int v = table[bk];
+    const int v = table[bk], k = table[TNSIM_TUNE_BUCKETS + bk];
     if (v != 0 && v != 64 && v != 128 && v != 256 && v != 512) return TNSIM_E_ARG;
+    if (k < 0 || k > KSPLIT_MAX || (k & (k - 1)) != 0) return TNSIM_E_ARG;
   }
-  for (int bk = 0; bk < TNSIM_TUNE_BUCKETS; bk++) h->tune_rot_rows[bk] = table[bk];
+  for (int bk = 0; bk < TNSIM_TUNE_BUCKETS; bk++) {
+    h->tune_rot_rows[bk] = table[bk];
+    h->tune_gram_ks[bk] = table[TNSIM_TUNE_BUCKETS + bk];
+  }
   return TNSIM_OK;
 }
 

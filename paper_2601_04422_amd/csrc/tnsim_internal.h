@@ -12,6 +12,7 @@ namespace tn {
 constexpr int BW = 32;
 constexpr int PW = 64;
 constexpr int KSPLIT_MAX = 16;
+constexpr int GP_PER_SLOT = 4;  // K-split chunks of partial pair Grams held per workspace slot
 // QR preconditioning: Householder panels of QNB columns; a panel of up to
 // QR_MAX_ROWS rows is held in the registers of one 512-thread workgroup
 // (4 rows x 8 complex128 columns per thread).

@@ -35,6 +35,8 @@ class Config(C.Structure):
 KERNEL_CLASSES = ["theta", "gram", "eig", "rot", "colnorm", "trunc", "wb_left", "wb_right",
                   "one_qubit", "other", "qr"]
 KSTAT_DTYPE = np.dtype([("ms", "<f8"), ("launches", "<i8"), ("flops", "<f8"), ("bytes", "<f8")])
+TUNE_BUCKETS = 4  # pair-count classes of the launch-shape table
+TUNE_ENTRIES = 2 * TUNE_BUCKETS  # rows per rotation workgroup, then Gram K-split
 
 GATE_DTYPE = np.dtype([("q0", "<i4"), ("q1", "<i4"), ("m", "<c16", (16,))], align=True)
 assert GATE_DTYPE.itemsize == 264
@@ -517,18 +519,19 @@ class MPS:
                 for i, k in enumerate(KERNEL_CLASSES)}
 
     def autotune(self) -> list:
-        """Time the rotation kernel's launch shapes on this handle's scratch
-        slots and keep the fastest per pair-count class (results unchanged).
-        Returns the rows per workgroup chosen for each class."""
-        out = np.zeros(4, dtype=np.int32)
+        """Time the rotation and pair-Gram launch shapes on this handle's
+        scratch slots and keep the fastest per pair-count class.  Returns the
+        table: rows per rotation workgroup for the 4 classes, then the Gram
+        K-split for the 4 classes."""
+        out = np.zeros(TUNE_ENTRIES, dtype=np.int32)
         self._chk(lib().tnsim_autotune(self._h, out.ctypes.data), "autotune")
         return out.tolist()
 
     def set_autotune(self, table: Sequence[int]) -> None:
         """Install a launch-shape table (e.g. another handle's autotune result)."""
         t = np.ascontiguousarray(table, dtype=np.int32)
-        if t.size != 4:
-            raise ValueError("launch table needs 4 entries")
+        if t.size != TUNE_ENTRIES:
+            raise ValueError(f"launch table needs {TUNE_ENTRIES} entries")
         self._chk(lib().tnsim_set_launch_table(self._h, t.ctypes.data), "set_launch_table")
 
     def site(self, q: int) -> np.ndarray:

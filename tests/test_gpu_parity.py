@@ -317,21 +317,37 @@ def test_qr_preconditioned_amplitudes(T):
     assert np.max(np.abs(gpu_statevector(g) - statevector(9, gates))) < 1e-12
 
 
-def test_autotuned_launch_shapes_leave_results_unchanged(T):
-    """The autotuner only picks rows per rotation workgroup; a tuned handle
-    must give the same state bit for bit as one on the built-in rule."""
+def test_autotuned_launch_shapes(T):
+    """The rows per rotation workgroup never change a result: a handle with
+    the tuned rotation shapes (and the built-in Gram K-split) gives the same
+    state bit for bit as one on the built-in rules.  The tuned Gram K-split
+    only reorders the Gram's row sums: the full tuned table agrees to
+    rounding (same bond dimensions, Schmidt values to 1e-12)."""
     n = 16
     layers = W.brickwork_haar(n, 10, 55)
     a = T.MPS(n, 24, 1e-10, precision="bf16x6", storage="c64")
     b = T.MPS(n, 24, 1e-10, precision="bf16x6", storage="c64")
     table = a.autotune()
-    assert len(table) == 4 and all(t in (64, 128, 256, 512) for t in table)
+    assert len(table) == 8
+    assert all(t in (64, 128, 256, 512) for t in table[:4])
+    assert all(k in (1, 2, 4, 8, 16) for k in table[4:])
+    a.set_autotune(table[:4] + [0, 0, 0, 0])
     a.run_layers(layers)
     b.run_layers(layers)
     for q in range(n):
         assert np.array_equal(a.site(q), b.site(q))
     for k in range(n - 1):
         assert np.array_equal(a.lam(k), b.lam(k))
+    c = T.MPS(n, 24, 1e-10)
+    d = T.MPS(n, 24, 1e-10)
+    c.set_autotune(table)
+    c.run_layers(layers)
+    d.run_layers(layers)
+    assert list(c.bond_dims()) == list(d.bond_dims())
+    for k in range(n - 1):
+        assert np.max(np.abs(c.lam(k) - d.lam(k))) < 1e-12
+    with pytest.raises(Exception):
+        c.set_autotune(table[:4] + [3, 0, 0, 0])
 
 
 # ---------------------------------------------------------------- circuit scheduler
