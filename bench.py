@@ -159,7 +159,7 @@ def parse():
                     help="oracle threads of the secondary workloads")
     ap.add_argument("--workload", default="chi1024",
                     choices=["chi1024", "wide", "ansatz", "batch", "nonlocal", "sample", "qasm",
-                             "fidelity", "calib", "propagate", "canonical"],
+                             "fidelity", "calib", "propagate", "canonical", "peak"],
                     help="chi1024: the headline metric; the others measure the secondary "
                          "workloads (one JSON line each)")
     return ap.parse_args()
@@ -820,6 +820,30 @@ def bench_calib(args):
                                    f"written per launch"}}
 
 
+def bench_peak(args):
+    """Attainable float64 rates of the device: independent chains of the
+    matrix-core instruction the contraction kernels use
+    (v_mfma_f64_16x16x4f64), of vector FMAs (the pair solve), and of both at
+    once (half the wavefronts each), over a grid that fills the chip; best
+    of three launches each."""
+    from paper_2601_04422_amd import tnsim as T
+
+    m = T.MPS(4, 2, precision="fp64", storage="c128")
+    mfma = max(m.probe_fp64("mfma") for _ in range(3))
+    valu = max(m.probe_fp64("valu") for _ in range(3))
+    mixed = max(m.probe_fp64("mixed") for _ in range(3))
+    mfma4 = max(m.probe_fp64("mfma4") for _ in range(3))
+    return {"metric": "attainable float64 rate, matrix cores (v_mfma_f64_16x16x4f64 chains)",
+            "value": mfma, "unit": "TFLOP/s", "n_gpus": 1, "steps": 3, "warmup": 1,
+            "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "8 independent instruction chains per wavefront, 8 "
+                                   "workgroups of 4 wavefronts per CU, 2000 x 8 "
+                                   "instructions per wavefront"},
+            "valu_fma_tflops": valu, "mixed_tflops": mixed, "mfma_4x4x4_tflops": mfma4,
+            "published_peak_tflops": FP64_PEAK_TFLOPS}
+
+
 def main():
     args = parse()
     headline = args.workload == "chi1024"
@@ -835,7 +859,8 @@ def main():
         fn = {"wide": bench_wide, "ansatz": bench_ansatz, "batch": bench_batch,
               "nonlocal": bench_nonlocal, "sample": bench_sample,
               "qasm": bench_qasm, "fidelity": bench_fidelity, "calib": bench_calib,
-              "propagate": bench_propagate, "canonical": bench_canonical}[args.workload]
+              "propagate": bench_propagate, "canonical": bench_canonical,
+              "peak": bench_peak}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return
     import torch
@@ -953,6 +978,13 @@ def main():
         fid_err = 1.0 - abs(ov) ** 2 / (ref.norm2() * mix.norm2())
 
     roof = roofline(prof)
+    if roof.get("bound") == "mfma":
+        # what the device sustains on the same instruction, measured here
+        small = T.MPS(4, 2)
+        att = max(small.probe_fp64("mfma") for _ in range(3))
+        small.close()
+        roof["attainable_mfma_tflops"] = att
+        roof["executed_frac_of_attainable"] = roof["executed_frac"] * FP64_PEAK_TFLOPS / att
 
     cpu = None
     if gate_inputs is not None:

@@ -360,6 +360,24 @@ tnsim_status tnsim_profile(tnsim_mps mps, int32_t enable);
 /* out has TNSIM_K_COUNT entries (synchronising). */
 tnsim_status tnsim_profile_read(tnsim_mps mps, tnsim_kernel_stat *out);
 
+/* Attainable float64 rate of this device (synchronising; a measurement aid,
+   no operation of the method).  unit 0: independent chains of
+   v_mfma_f64_16x16x4f64 (the matrix-core instruction of the Jacobi Grams and
+   rotations, the merge and the write-back); unit 1: independent chains of
+   vector v_fma_f64 (the pair solve's arithmetic); unit 2: both at once
+   (wavefronts 0 and 2 of each workgroup on matrix-core chains, 1 and 3 on
+   four times as many vector FMAs; the combined rate); unit 3: independent
+   chains of the four-block v_mfma_f64_4x4x4f64 (256 multiply-adds each).
+   Eight workgroups of four
+   wavefronts per CU, `iters` x 8 instructions per wavefront (1 <= iters <=
+   2^20), timed with HIP events on the handle's stream after one untimed
+   launch; *tflops_out (host) receives the real flops per second / 1e12.  The
+   published peaks count both units at 78.6 TFLOP/s; this is what the device
+   sustains.  Allocates and frees one small device buffer.  Errors:
+   TNSIM_E_ARG (bad handle, unit outside 0..3, iters or NULL out),
+   TNSIM_E_DEVICE. */
+tnsim_status tnsim_probe_fp64(tnsim_mps mps, int32_t unit, int32_t iters, double *tflops_out);
+
 /* Launch-shape autotuner (synchronising).  Times two Jacobi kernels on this
    handle's workspace slots (zeroed scratch; the state is not touched) in
    each of TNSIM_TUNE_BUCKETS pair-count classes (<= 32, <= 128, <= 512 and

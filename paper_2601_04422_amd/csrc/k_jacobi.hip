@@ -138,6 +138,25 @@ void launch_begin_sweep(hipStream_t st, const GateDesc *d, int ng) {
 // ---------------------------------------------------------------- Gram of a column pair
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
+// Raw buffer access to complex128 elements: a resource over `elems`
+// elements from `base` (accesses past the end read zero and are dropped).
+typedef __amdgpu_buffer_rsrc_t BufRes;
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ BufRes make_res(double2 *base, int elems) {
+  // the resource must be wave-uniform (scalar registers)
+  const unsigned long long a = (unsigned long long)base;
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)a);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(a >> 32));
+  double2 *ub = (double2 *)(((unsigned long long)hi << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(ub, 0, __builtin_amdgcn_readfirstlane(elems * 16),
+                                           0x00020000);
+}
+__device__ __forceinline__ double2 bload(BufRes r, int elem) {
+  return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, elem * 16, 0, 0));
+}
+__device__ __forceinline__ void bstore(BufRes r, int elem, double2 x) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, x), r, elem * 16, 0, 0);
+}
 
 // v_mfma_f64_16x16x4f64 operand layout (lane l = 0..63): A[l%16][l/16],
 // B[l/16][l%16]; result entry v of lane l is D[l/16 + 4v][l%16] (rows
@@ -163,16 +182,26 @@ constexpr int GT_A[10] = {0, 0, 0, 0, 1, 1, 1, 2, 2, 3};
 constexpr int GT_B[10] = {0, 1, 2, 3, 1, 2, 3, 2, 3, 3};
 
 template <int SET>
-__device__ __forceinline__ void gram_tiles(const double2 *const xc[4], int rbeg, int rend,
+__device__ __forceinline__ void gram_tiles(BufRes rI, BufRes rJ, int ld, int rbeg, int rend,
                                            int half, int l16, int lg, d4_t (&p1)[5],
                                            d4_t (&p2)[5], d4_t (&p3)[5]) {
   constexpr int U0 = SET * 5, T0 = SET;  // tiles U0..U0+4 use column groups T0..3
-  // loads of the 16-lane column groups T0..3 for one k-step (4 rows)
+  // loads of the 16-lane column groups T0..3 for one k-step (4 rows): buffer
+  // loads (columns 16 t + l%16 of the pair, block I for t < 2), never
+  // skipped (a row past the chunk reads what lies there, or zero past the
+  // block, and is zeroed when used), so that the loads in flight are counted
+  // exactly
   auto load_step = [&](double2 *x, int r) {
 #pragma unroll
-    for (int t = T0; t < 4; t++) x[t] = r < rend ? xc[t][r] : make_double2(0.0, 0.0);
+    for (int t = T0; t < 4; t++) x[t] = bload(t < 2 ? rI : rJ, (16 * (t & 1) + l16) * ld + r);
   };
-  auto mfma_step = [&](const double2 *x) {
+  auto mfma_step = [&](const double2 *xin, int r) {
+    // the step's own operands only: nothing of a later step is hoisted here
+    // (its loads are still in flight)
+    __builtin_amdgcn_sched_barrier(0);
+    double2 x[4];
+#pragma unroll
+    for (int t = T0; t < 4; t++) x[t] = r < rend ? xin[t] : make_double2(0.0, 0.0);
     double dm[4], sp[4];  // a - b of the A operand, c + d of the B operand
 #pragma unroll
     for (int t = T0; t < 4; t++) {
@@ -187,6 +216,7 @@ __device__ __forceinline__ void gram_tiles(const double2 *const xc[4], int rbeg,
       p2[u] = mfma64(a.y, b.y, p2[u]);
       p3[u] = mfma64(dm[ta], sp[tb], p3[u]);
     }
+    __builtin_amdgcn_sched_barrier(0);
   };
   // the wavefront's k-steps: 16-row tiles base, base + 32, ... (the other
   // wavefront of the set takes the tiles in between), 4 steps per tile;
@@ -194,21 +224,20 @@ __device__ __forceinline__ void gram_tiles(const double2 *const xc[4], int rbeg,
   const int base = rbeg + half * 16;
   const int nstep = base < rend ? (rend - base + 31) / 32 * 4 : 0;
   auto row_of = [&](int n) { return base + 32 * (n >> 2) + 4 * (n & 3) + lg; };
+  if (nstep == 0) return;
   double2 x0[4], x1[4], x2[4], x3[4];
-  if (nstep > 0) {
-    load_step(x0, row_of(0));
-    load_step(x1, row_of(1));
-    load_step(x2, row_of(2));
-  }
+  load_step(x0, row_of(0));
+  load_step(x1, row_of(1));
+  load_step(x2, row_of(2));
   for (int n = 0; n < nstep; n += 4) {
     load_step(x3, row_of(n + 3));
-    mfma_step(x0);
-    if (n + 4 < nstep) load_step(x0, row_of(n + 4));
-    mfma_step(x1);
-    if (n + 4 < nstep) load_step(x1, row_of(n + 5));
-    mfma_step(x2);
-    if (n + 4 < nstep) load_step(x2, row_of(n + 6));
-    mfma_step(x3);
+    mfma_step(x0, row_of(n));
+    load_step(x0, row_of(n + 4));
+    mfma_step(x1, row_of(n + 1));
+    load_step(x1, row_of(n + 5));
+    mfma_step(x2, row_of(n + 2));
+    load_step(x2, row_of(n + 6));
+    mfma_step(x3, row_of(n + 3));
   }
 }
 
@@ -224,11 +253,12 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma2(const GateDesc *descs, in
   chunk = (chunk + 15) / 16 * 16;
   const int rbeg = kc * chunk;
   const int rend = min(d.rows, rbeg + chunk);
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform (scalar)
   const int l16 = lane & 15, lg = lane >> 4;
-  const double2 *xc[4];
-#pragma unroll
-  for (int t = 0; t < 4; t++) xc[t] = d.X + (size_t)pair_col(I, J, t * 16 + l16) * d.ldx;
+  const int ld = d.ldx;
+  const BufRes rI = make_res(d.X + (size_t)I * BW * ld, BW * ld);
+  const BufRes rJ = make_res(d.X + (size_t)J * BW * ld, BW * ld);
   d4_t p1[5], p2[5], p3[5];
 #pragma unroll
   for (int u = 0; u < 5; u++) {
@@ -238,9 +268,9 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma2(const GateDesc *descs, in
   }
   const int set = wave >> 1, half = wave & 1;
   if (set == 0)
-    gram_tiles<0>(xc, rbeg, rend, half, l16, lg, p1, p2, p3);
+    gram_tiles<0>(rI, rJ, ld, rbeg, rend, half, l16, lg, p1, p2, p3);
   else
-    gram_tiles<1>(xc, rbeg, rend, half, l16, lg, p1, p2, p3);
+    gram_tiles<1>(rI, rJ, ld, rbeg, rend, half, l16, lg, p1, p2, p3);
   // sum of the two wavefronts of each set, the first one's partial first
   __shared__ double red[10][4][64][2];
   for (int h = 0; h < 2; h++) {
@@ -546,7 +576,8 @@ __global__ __launch_bounds__(256, 2) void k_rot_mfma3(const GateDesc *descs, int
   }
   const int r1 = min(nrows, r0 + RRW);
   __shared__ double2 Vs[PW * LDG];  // [k][col]
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform (scalar)
   const int l16 = lane & 15, lg = lane >> 4;
   const double2 *V = d.V + (size_t)pairIdx * (PW * PW);
   for (int e = tid; e < PW * PW; e += 256) Vs[(e / PW) * LDG + e % PW] = V[e];
@@ -556,26 +587,33 @@ __global__ __launch_bounds__(256, 2) void k_rot_mfma3(const GateDesc *descs, int
     atomicAdd(&d.ctr[CTR_ROT_BYTE], 32ull * nr * PW + 16ull * PW * PW);
   }
   __syncthreads();
-  // the lane's column for k-step s is pair column 4 s + lg (block I for s < 8)
-  const double2 *xI = base + (size_t)(I * BW + lg) * ld;
-  const double2 *xJ = base + (size_t)(J * BW + lg) * ld;
+  // The lane's column for k-step s is pair column 4 s + lg (block I for
+  // s < 8).  Buffer loads and stores (one resource per block of 32 padded columns, a
+  // 32-bit element offset per access): one register per address, counted
+  // on the vector memory counter only.  Tile q of the wavefront covers rows
+  // r0 + 16 (wave + 4 q) ..; a tile past the chunk uses an empty resource
+  // (loads read zero, stores are dropped), so every wavefront runs an even
+  // number of tiles with no branch around loads or stores, and the loads in
+  // flight are counted exactly: the products of a tile wait only for that
+  // tile's data while the next tile's block I is still on its way.  Columns
+  // are padded to whole 16-row tiles and chunks are whole tiles, so rows
+  // past the matrix land in the column's padding (never read).
+  const BufRes rI = make_res(base + (size_t)I * BW * ld, BW * ld);
+  const BufRes rJ = make_res(base + (size_t)J * BW * ld, BW * ld);
+  const BufRes rZ = make_res(base, 0);
+  const int ntile = (r1 - r0 + 15) / 16;
+  const int mytiles = wave < ntile ? (ntile - wave + 3) / 4 : 0;
+  auto tile_row = [&](int q) { return r0 + 16 * (wave + 4 * q); };
   // k-steps 0..7 read block I, 8..15 block J
-  auto load_half = [&](double2 *xv, int half, int rt) {
-    const int r = rt + l16;
-    const double2 *c0 = (half ? xJ : xI);
+  auto load_half = [&](double2 *xv, int half, int q) {
+    const int rt = tile_row(q);
+    const BufRes r = rt < r1 ? (half ? rJ : rI) : rZ;
+    const int lo = lg * ld + rt + l16;
 #pragma unroll
-    for (int s = 0; s < BW / 4; s++)
-      xv[s] = r < r1 ? c0[(size_t)(4 * s) * ld + r] : make_double2(0.0, 0.0);
+    for (int s = 0; s < BW / 4; s++) xv[s] = bload(r, lo + 4 * s * ld);
   };
-  int rt = r0 + wave * 16;
-  double2 xb[PW / 4];
-  if (rt < r1) load_half(xb, 0, rt);
-  for (; rt < r1; rt += 64) {
-    // block J of this tile, needed after the block-I steps; block I of the
-    // wave's next tile, needed in the next iteration
-    load_half(xb + BW / 4, 1, rt);
-    double2 xn[BW / 4];
-    if (rt + 64 < r1) load_half(xn, 0, rt + 64);
+  // one 16-row tile: block I from xi, block J from xj
+  auto tile = [&](const double2 *xi, const double2 *xj, int q) {
     d4_t p1[4], p2[4], p3[4];
 #pragma unroll
     for (int t = 0; t < 4; t++) {
@@ -585,7 +623,7 @@ __global__ __launch_bounds__(256, 2) void k_rot_mfma3(const GateDesc *descs, int
     }
 #pragma unroll
     for (int s = 0; s < PW / 4; s++) {
-      const double2 b = xb[s];  // X^T[k][row]
+      const double2 b = s < BW / 4 ? xi[s] : xj[s - BW / 4];  // X^T[k][row]
       const double bs = b.x + b.y;
 #pragma unroll
       for (int t = 0; t < 4; t++) {
@@ -596,19 +634,34 @@ __global__ __launch_bounds__(256, 2) void k_rot_mfma3(const GateDesc *descs, int
       }
       __builtin_amdgcn_sched_barrier(0);  // keep each step's V reads in that step
     }
-    const int r = rt + l16;
-    if (r < r1) {
+    // Loads and stores share the vector memory counter, and a load issued
+    // before a store can only be waited for with the store: so the next
+    // tile's block I (issued at this tile's start, long arrived) is waited
+    // for here, before this tile's stores.
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    // output column t * 16 + lg + 4 v of the pair: block I for t < 2
+    const int rt = tile_row(q);
+    const bool live = rt < r1;
+    const BufRes oI = live ? rI : rZ, oJ = live ? rJ : rZ;
+    const int lo = lg * ld + rt + l16;
 #pragma unroll
-      for (int t = 0; t < 4; t++)
+    for (int t = 0; t < 4; t++)
 #pragma unroll
-        for (int v = 0; v < 4; v++) {
-          const int c = t * 16 + lg + 4 * v;
-          base[(size_t)pair_col(I, J, c) * ld + r] =
-              make_double2(p1[t][v] - p2[t][v], p3[t][v] - p1[t][v] - p2[t][v]);
-        }
-    }
-#pragma unroll
-    for (int s = 0; s < BW / 4; s++) xb[s] = xn[s];
+      for (int v = 0; v < 4; v++)
+        bstore(t < 2 ? oI : oJ, lo + (16 * (t & 1) + 4 * v) * ld,
+               make_double2(p1[t][v] - p2[t][v], p3[t][v] - p1[t][v] - p2[t][v]));
+  };
+  // Two block-I buffers take turns (no register copies between tiles).
+  double2 xi0[BW / 4], xi1[BW / 4], xj[BW / 4];
+  load_half(xi0, 0, 0);
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the loop starts with block I in hand
+  for (int q = 0; q < mytiles; q += 2) {
+    load_half(xj, 1, q);
+    load_half(xi1, 0, q + 1);
+    tile(xi0, xj, q);
+    load_half(xj, 1, q + 1);
+    load_half(xi0, 0, q + 2);
+    tile(xi1, xj, q + 1);
   }
 }
 

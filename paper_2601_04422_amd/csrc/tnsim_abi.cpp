@@ -93,7 +93,7 @@ Layout make_layout(const tnsim_config &c) {
   }
   // two-site workspaces
   L.cmax = 2 * maxbond;
-  L.ldx_max = pad_to(L.cmax, 4);
+  L.ldx_max = pad_to(L.cmax, 16);  // whole 16-row tiles of every column (rotation stores)
   L.cols_pad_max = pad_to(L.cmax, PW);
   L.npairs_max = L.cols_pad_max / PW;
   // with QR preconditioning, J and U also serve as scratch for the group
@@ -430,8 +430,8 @@ GateDesc make_desc(tnsim_mps o, const BatchItem &it, bool force_trans) {
   d.qr = h->cfg.svd_precondition && !d.trans && d.m <= QR_MAX_ROWS;
   d.rows = d.qr ? d.n : (d.trans ? d.n : d.m);
   d.cols = d.trans ? d.m : d.n;
-  d.ldx = pad_to(d.rows, 4);
-  d.ldj = pad_to(d.m, 4);
+  d.ldx = pad_to(d.rows, 16);
+  d.ldj = pad_to(d.m, 16);
   d.colsPad = pad_to(d.cols, PW);
   d.nblk = d.colsPad / BW;
   d.chiMax = h->cfg.chi_max;
@@ -1528,7 +1528,7 @@ tnsim_status grad_apply(tnsim_mps h, int gi, GradRec *rec) {
     const SlotScalars *sc_pin = pin_scalars(h);
     rec->k = sc_pin[0].k;
     rec->N = sc_pin[0].N;
-    const int m = 2 * rec->chiL, nn = 2 * rec->chiR, ldj = pad_to(m, 4);
+    const int m = 2 * rec->chiL, nn = 2 * rec->chiR, ldj = pad_to(m, 16);
     char *sl = h->slot(0), *r = G.ws + rec->off;
     HIPCHK(h, hipMemcpyAsync(r + G.rec_T, sl + L.t_off, sizeof(double2) * (size_t)m * nn,
                              hipMemcpyDeviceToDevice, st));
@@ -2791,6 +2791,40 @@ tnsim_status tnsim_profile(tnsim_mps h, int32_t enable) {
     HIPCHK(h, hipStreamSynchronize(h->stream));
   }
   h->prof = enable != 0;
+  return TNSIM_OK;
+}
+
+tnsim_status tnsim_probe_fp64(tnsim_mps h, int32_t unit, int32_t iters, double *tflops_out) {
+  tnsim_status s = check_handle(h);
+  if (s != TNSIM_OK) return s;
+  if (unit < 0 || unit > 3 || iters < 1 || iters > (1 << 20) || !tflops_out) return TNSIM_E_ARG;
+  int dev = 0, cus = 0;
+  HIPCHK(h, hipGetDevice(&dev));
+  HIPCHK(h, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int groups = 8 * std::max(cus, 1);  // eight workgroups of four wavefronts per CU
+  double *out = nullptr;
+  HIPCHK(h, hipMalloc(&out, sizeof(double) * 256 * (size_t)groups));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  double flops = 0.0;
+  float ms = 0.0f;
+  if (e == hipSuccess) {
+    launch_probe(h->stream, unit, groups, iters, out);  // warm-up
+    e = hipEventRecord(e0, h->stream);
+  }
+  if (e == hipSuccess) {
+    flops = launch_probe(h->stream, unit, groups, iters, out);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  hipFree(out);
+  if (e != hipSuccess) return fail(h, e, "probe");
+  *tflops_out = ms > 0.0f ? flops / (ms * 1e-3) / 1e12 : 0.0;
   return TNSIM_OK;
 }
 

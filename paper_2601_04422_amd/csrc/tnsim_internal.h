@@ -93,6 +93,9 @@ struct Gate1Desc {
 void launch_init_state(hipStream_t st, void *const *sites_dev_list, int n, int storage,
                        double *const *lam_list_dev, int nb);
 void launch_fill_zero(hipStream_t st, void *p, size_t bytes);
+// float64 rate probe: unit 0 = matrix cores (16x16x4), 1 = vector FMA, 2 = both at
+// once, 3 = matrix cores (four-block 4x4x4); returns the flops launched
+double launch_probe(hipStream_t st, int unit, int groups, int iters, double *out);
 void launch_apply_1q(hipStream_t st, const Gate1Desc *d, int ng, int max_elems);
 void launch_convert(hipStream_t st, const void *src, int src_storage, void *dst, int dst_storage,
                     size_t count);

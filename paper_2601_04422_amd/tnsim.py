@@ -82,6 +82,7 @@ _SIGS = {
     "tnsim_sample_draw": (C.c_int, [_P, _P, C.c_size_t, C.c_int32, _P, _P, _P]),
     "tnsim_profile": (C.c_int, [_P, C.c_int32]),
     "tnsim_profile_read": (C.c_int, [_P, _P]),
+    "tnsim_probe_fp64": (C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(C.c_double)]),
     "tnsim_autotune": (C.c_int, [_P, _P]),
     "tnsim_set_launch_table": (C.c_int, [_P, _P]),
     "tnsim_canonicalize": (C.c_int, [_P, C.c_int32]),
@@ -517,6 +518,15 @@ class MPS:
         self._chk(lib().tnsim_profile_read(self._h, out.ctypes.data), "profile_read")
         return {k: {f: out[i][f].item() for f in KSTAT_DTYPE.names}
                 for i, k in enumerate(KERNEL_CLASSES)}
+
+    def probe_fp64(self, unit: str, iters: int = 2000) -> float:
+        """Attainable float64 TFLOP/s of the device: unit "mfma" (matrix
+        cores, v_mfma_f64_16x16x4f64), "valu" (vector FMA), "mixed" (both at
+        once, half the wavefronts each) or "mfma4" (v_mfma_f64_4x4x4f64)."""
+        out = C.c_double()
+        u = {"mfma": 0, "valu": 1, "mixed": 2, "mfma4": 3}[unit]
+        self._chk(lib().tnsim_probe_fp64(self._h, u, int(iters), C.byref(out)), "probe_fp64")
+        return out.value
 
     def autotune(self) -> list:
         """Time the rotation and pair-Gram launch shapes on this handle's

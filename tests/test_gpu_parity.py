@@ -317,6 +317,17 @@ def test_qr_preconditioned_amplitudes(T):
     assert np.max(np.abs(gpu_statevector(g) - statevector(9, gates))) < 1e-12
 
 
+def test_fp64_rate_probe(T):
+    """The float64 rate probe runs each form and reports a rate in a sane
+    range (above 1 TFLOP/s, below twice the published 78.6); a unit outside
+    the four is rejected."""
+    m = T.MPS(4, 2)
+    for unit in ("mfma", "valu", "mixed", "mfma4"):
+        r = m.probe_fp64(unit, 200)
+        assert 1.0 < r < 2 * 78.6, (unit, r)
+    assert T.lib().tnsim_probe_fp64(m._h, 4, 10, T.C.byref(T.C.c_double())) == T.E_ARG
+
+
 def test_autotuned_launch_shapes(T):
     """The rows per rotation workgroup never change a result: a handle with
     the tuned rotation shapes (and the built-in Gram K-split) gives the same
