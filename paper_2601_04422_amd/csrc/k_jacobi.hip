@@ -18,6 +18,7 @@
 
 #include "tnsim_internal.h"
 #include "tn_complex.h"
+#include "tn_buffer.h"
 
 namespace tn {
 
@@ -138,26 +139,6 @@ void launch_begin_sweep(hipStream_t st, const GateDesc *d, int ng) {
 // ---------------------------------------------------------------- Gram of a column pair
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
-// Raw buffer access to complex128 elements: a resource over `elems`
-// elements from `base` (accesses past the end read zero and are dropped).
-typedef __amdgpu_buffer_rsrc_t BufRes;
-typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ BufRes make_res(double2 *base, int elems) {
-  // the resource must be wave-uniform (scalar registers)
-  const unsigned long long a = (unsigned long long)base;
-  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)a);
-  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(a >> 32));
-  double2 *ub = (double2 *)(((unsigned long long)hi << 32) | lo);
-  return __builtin_amdgcn_make_buffer_rsrc(ub, 0, __builtin_amdgcn_readfirstlane(elems * 16),
-                                           0x00020000);
-}
-__device__ __forceinline__ double2 bload(BufRes r, int elem) {
-  return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, elem * 16, 0, 0));
-}
-__device__ __forceinline__ void bstore(BufRes r, int elem, double2 x) {
-  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, x), r, elem * 16, 0, 0);
-}
-
 // v_mfma_f64_16x16x4f64 operand layout (lane l = 0..63): A[l%16][l/16],
 // B[l/16][l%16]; result entry v of lane l is D[l/16 + 4v][l%16] (rows
 // strided by 4, unlike the float32 16x16 results).

@@ -17,6 +17,7 @@
 // I - V T V^H (compact WY, T upper triangular).  Everything is float64.
 #include "tnsim_internal.h"
 #include "tn_complex.h"
+#include "tn_buffer.h"
 
 namespace tn {
 
@@ -407,29 +408,32 @@ __global__ __launch_bounds__(256) void k_qrg_s(const GateDesc *descs, int stage,
   const int l16 = lane & 15, lg = lane >> 4;
   const int tp = (wave >> 1) * 16, tc = (wave & 1) * 16;  // this wave's 16x16 tile of S
   qd4_t accR = {0.0, 0.0, 0.0, 0.0}, accI = {0.0, 0.0, 0.0, 0.0};
-  // the next 32 rows of V and B are loaded into registers while the current
-  // ones are multiplied
+  // Rows come in chunks of 32, each thread holding 4 elements of V and 4 of
+  // B per chunk.  Two chunks are in flight ahead of the one being
+  // multiplied: buffer loads (counted apart from the LDS accesses), never
+  // skipped, and masked only when written to LDS.
   static_assert(32 * QG == 4 * 256 && 32 * QGT == 4 * 256, "four elements per thread");
-  double2 vr[4], br[4];
-  auto load = [&](int r0) {
+  const BufRes rA = make_res(q.A, q.ld * q.cols);
+  const BufRes rB = make_res(t.B, t.ldb * t.ncols);
+  auto load = [&](int r0, double2 *vv, double2 *bb) {
 #pragma unroll
     for (int k = 0; k < 4; k++) {
       const int e = tid + 256 * k, r = e % 32, p = e / 32;
-      vr[k] = (r0 + r < rend) ? qr_vget(q, j0, w, r0 + r, p) : make_double2(0.0, 0.0);
-      br[k] = (r0 + r < rend && c0 + p < t.ncols) ? t.B[(size_t)(c0 + p) * t.ldb + r0 + r]
-                                                  : make_double2(0.0, 0.0);
+      vv[k] = bload(rA, (j0 + p) * q.ld + r0 + r);
+      bb[k] = bload(rB, (c0 + p) * t.ldb + r0 + r);
     }
   };
-  load(rbeg);
-  for (int r0 = rbeg; r0 < rend; r0 += 32) {
+  auto to_lds = [&](int r0, const double2 *vv, const double2 *bb) {
 #pragma unroll
     for (int k = 0; k < 4; k++) {
       const int e = tid + 256 * k, r = e % 32, p = e / 32;
-      Vs[r][p] = vr[k];
-      Bs[r][p] = br[k];
+      const int rr = r0 + r, dr = rr - (j0 + p);  // reflector p: 1 on its diagonal, stored below
+      const bool in = rr < rend;
+      Vs[r][p] = (in && p < w && dr > 0) ? vv[k] : make_double2(in && p < w && dr == 0 ? 1.0 : 0.0, 0.0);
+      Bs[r][p] = (in && c0 + p < t.ncols) ? bb[k] : make_double2(0.0, 0.0);
     }
-    __syncthreads();
-    if (r0 + 32 < rend) load(r0 + 32);
+  };
+  auto chunk = [&]() {
 #pragma unroll
     for (int kk = 0; kk < 32; kk += 4) {
       const double2 a = Vs[kk + lg][tp + l16];  // S = conj(V)^T B
@@ -439,6 +443,22 @@ __global__ __launch_bounds__(256) void k_qrg_s(const GateDesc *descs, int stage,
       accI = qmfma(a.x, b.y, accI);
       accI = qmfma(-a.y, b.x, accI);
     }
+  };
+  const int nchunk = (rend - rbeg + 31) / 32;
+  double2 va[4], ba[4], vb[4], bb[4];
+  load(rbeg, va, ba);
+  load(rbeg + 32, vb, bb);
+  for (int c = 0; c < nchunk; c += 2) {  // an odd last chunk is followed by an all-zero one
+    const int r0 = rbeg + 32 * c;
+    to_lds(r0, va, ba);
+    __syncthreads();
+    load(r0 + 64, va, ba);
+    chunk();
+    __syncthreads();
+    to_lds(r0 + 32, vb, bb);
+    __syncthreads();
+    load(r0 + 96, vb, bb);
+    chunk();
     __syncthreads();
   }
   double2 *Sp = t.scr + (size_t)blockIdx.y * QG * t.ldS;
@@ -517,47 +537,52 @@ __global__ __launch_bounds__(256) void k_qrg_b(const GateDesc *descs, int stage,
   // the next tile's V and B entries are loaded while the current tile is
   // multiplied (row tiles of one wave never overlap those of another)
   const int tc = (wave & 1) * 16;
-  double2 vc[QG / 4], bc[4];
+  // Buffer loads and stores (counted apart from the LDS reads of Y), never
+  // skipped: what lies past the chunk is masked when used, stores past it
+  // are dropped by their offset.  Row tiles of one wave never overlap those
+  // of another; the next tile's V and B are loaded while the current tile
+  // is multiplied, into the other of two register sets.
+  const BufRes rA = make_res(q.A, q.ld * q.cols);
+  const BufRes rB = make_res(t.B, t.ldb * t.ncols);
   auto load = [&](int rt, double2 *vv, double2 *bb) {
-#pragma unroll
-    for (int k = 0; k < QG / 4; k++) vv[k] = qr_vget(q, j0, w, rt + l16, 4 * k + lg);  // V^T[k][row]
     const int r = rt + l16;
 #pragma unroll
-    for (int v = 0; v < 4; v++) {
-      const int c = c0 + tc + lg + 4 * v;
-      bb[v] = (r < rend && c < t.ncols) ? t.B[(size_t)c * t.ldb + r] : make_double2(0.0, 0.0);
-    }
+    for (int k = 0; k < QG / 4; k++) vv[k] = bload(rA, (j0 + 4 * k + lg) * q.ld + r);  // V^T[k][row]
+#pragma unroll
+    for (int v = 0; v < 4; v++) bb[v] = bload(rB, (c0 + tc + lg + 4 * v) * t.ldb + r);
   };
-  int rt = rbeg + (wave >> 1) * 16;
-  if (rt < rend) load(rt, vc, bc);
-  for (; rt < rend; rt += 32) {
-    double2 vn[QG / 4], bn[4];
-    if (rt + 32 < rend) load(rt + 32, vn, bn);
+  auto tile = [&](int rt, const double2 *vv, const double2 *bb) {
+    const int r = rt + l16;
     qd4_t accR = {0.0, 0.0, 0.0, 0.0}, accI = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < QG / 4; k++) {
+      const int p = 4 * k + lg, dr = r - (j0 + p);  // reflector p: 1 on its diagonal, stored below
+      const bool ok = r < rend && p < w;
+      const double2 b = (ok && dr > 0) ? vv[k] : make_double2(ok && dr == 0 ? 1.0 : 0.0, 0.0);
       const double2 a = Ys[4 * k + lg][tc + l16];  // Y^T[col][k]
-      const double2 b = vc[k];
       accR = qmfma(a.x, b.x, accR);
       accR = qmfma(-a.y, b.y, accR);
       accI = qmfma(a.x, b.y, accI);
       accI = qmfma(a.y, b.x, accI);
     }
-    const int r = rt + l16;
-    if (r < rend) {
 #pragma unroll
-      for (int v = 0; v < 4; v++) {
-        const int c = c0 + tc + lg + 4 * v;
-        if (c < t.ncols)
-          t.B[(size_t)c * t.ldb + r] = make_double2(bc[v].x - accR[v], bc[v].y - accI[v]);
-      }
+    for (int v = 0; v < 4; v++) {
+      const int c = c0 + tc + lg + 4 * v;
+      const bool ok = r < rend && c < t.ncols;
+      bstore_bytes(rB, ok ? (c * t.ldb + r) * 16 : BUF_DROP,
+                   make_double2(bb[v].x - accR[v], bb[v].y - accI[v]));
     }
-    if (rt + 32 < rend) {
-#pragma unroll
-      for (int k = 0; k < QG / 4; k++) vc[k] = vn[k];
-#pragma unroll
-      for (int v = 0; v < 4; v++) bc[v] = bn[v];
-    }
+  };
+  const int rt0 = rbeg + (wave >> 1) * 16;
+  const int ntile = rt0 < rend ? (rend - rt0 + 31) / 32 : 0;
+  double2 va[QG / 4], ba[4], vb[QG / 4], bb[4];
+  load(rt0, va, ba);
+  for (int i = 0; i < ntile; i += 2) {  // an odd last tile is followed by one past the chunk
+    const int rt = rt0 + 32 * i;
+    load(rt + 32, vb, bb);
+    tile(rt, va, ba);
+    load(rt + 64, va, ba);
+    tile(rt + 32, vb, bb);
   }
 }
 
