@@ -12,7 +12,7 @@ namespace tn {
 // C[i][j] (+)= alpha * sum_k opA(i,k) opB(k,j), with element strides and an
 // optional conjugation of each operand.  Used for the contractions of the
 // adjoint and of the loss environments.  Float64 matrix cores
-// (v_mfma_f64_16x16x4f64, four real products per complex one): a 64x64 tile
+// (v_mfma_f64_16x16x4f64, three real products per complex one): a 64x64 tile
 // of C per workgroup, K in steps of 16 through LDS with the next step loaded
 // into registers during the products; wavefront w owns the 32x32 quarter
 // (rows 32 (w&1), columns 32 (w>>1)), lane l supplies A[l%16][k + l/16] and

@@ -84,7 +84,7 @@ __device__ void theta_epilogue(const GateDesc &d, int r0, int c0, double2 *Cs) {
 }
 
 // float64 merge on the matrix cores (v_mfma_f64_16x16x4f64): a complex
-// product is four real products.  Wavefront w owns the 32x32 quarter (rows
+// product is three real products (Gauss: ac, bd, (a + b)(c + d)).  Wavefront w owns the 32x32 quarter (rows
 // 32 (w&1), columns 32 (w>>1)) as 2x2 tiles of 16x16; lane l supplies
 // A[l%16][k + l/16] and B[k + l/16][l%16] and holds D[l/16 + 4v][l%16] of
 // each tile.  The next 16-deep k step is loaded into registers while the

@@ -63,8 +63,8 @@ __global__ __launch_bounds__(256) void k_wb_left(const GateDesc *descs) {
 }
 
 // A_{i+1}' = (1/N) U_k^H theta'   (k x n), tiles of 64 x 64, K = m in steps of 16.
-// float64 product on the matrix cores (v_mfma_f64_16x16x4f64, four real
-// products per complex one).  Tile j (64 kept vectors) x c (64 columns
+// float64 product on the matrix cores (v_mfma_f64_16x16x4f64, three real
+// products per complex one: ac, bd, (a + b)(c + d)).  Tile j (64 kept vectors) x c (64 columns
 // of theta'), K = m rows in steps of 16 through LDS, the next step loaded
 // into registers while the current one is multiplied.  Wavefront w owns the
 // 32x32 quarter (rows 32 (w&1), columns 32 (w>>1)); lane l supplies
