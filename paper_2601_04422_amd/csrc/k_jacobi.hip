@@ -288,7 +288,8 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma2(const GateDesc *descs, in
 // ---------------------------------------------------------------- 64x64 Hermitian Jacobi
 
 constexpr int LDG = PW + 1;
-constexpr int EIG_THREADS = 1024;  // 16 wavefronts hide the LDS latency of the pair solve
+constexpr int EIG_THREADS = 512;  // 8 wavefronts; two pair solves share a CU
+constexpr int EIG_VROWS = PW / (EIG_THREADS / 64);  // rows of V held by each wavefront
 constexpr int EIG_OFFD = (PW / 2) * (PW / 2 - 1) / 2;  // off-diagonal 2x2 blocks (i < j)
 
 // Circle-method tournament over the 64 columns of a pair solve: in round r
@@ -319,11 +320,14 @@ __device__ __forceinline__ int gslot(int a, int b) { return a < b ? a * LDG + b 
 // 2x2 blocks (rows of pair i x columns of pair j, i < j) are updated by one
 // thread each, and the 2x2 diagonal block of a rotating pair takes its
 // exact values (new diagonal entries, zero coupling) when the rotation is
-// computed.  The rotations of round r + 1 are computed by the first
-// wavefront while the others apply round r to V (parameters double-
+// computed.  V lives in registers: wavefront w holds rows 8w .. 8w + 7,
+// lane j column j, and a lane takes its rotation partner's entries by a
+// lane permute, so LDS holds only G and the rotation parameters (69 KB:
+// two solves per CU).  The rotations of round r + 1 are computed by the
+// first wavefront while the others apply round r to V (parameters double-
 // buffered), so a round costs two barriers.  At most `inner_sweeps` sweeps;
 // the outer sweeps finish what a capped inner solve leaves.
-__global__ __launch_bounds__(EIG_THREADS) void k_eig(const GateDesc *descs, int round, int ksplit) {
+__global__ __launch_bounds__(EIG_THREADS, 4) void k_eig(const GateDesc *descs, int round, int ksplit) {
   const GateDesc &d = descs[blockIdx.y];
   const int pairIdx = blockIdx.x;
   if (!d.sc->active || round >= d.nblk - 1 || pairIdx >= d.nblk / 2) return;
@@ -334,11 +338,9 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(const GateDesc *descs, int 
     return;
   }
   __shared__ double2 Gs[PW * LDG];
-  __shared__ double2 Vs[PW * LDG];
   __shared__ double dg[PW];           // diagonal of G
   __shared__ double rc[2][PW / 2];    // cos
   __shared__ double2 rse[2][PW / 2];  // s * e^{i phi}
-  __shared__ int rp[2][PW / 2], rq[2][PW / 2];
   __shared__ int anyr[2];  // some rotation in the round held by that buffer
   __shared__ int sweep_rot, first_rot;
   const int tid = threadIdx.x;
@@ -361,8 +363,11 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(const GateDesc *descs, int 
       else
         dg[r] = sm.x;
     }
-    Vs[r * LDG + c] = make_double2(r == c ? 1.0 : 0.0, 0.0);
   }
+  const int lane = tid & 63, vrow0 = (tid >> 6) * EIG_VROWS;
+  double2 vr[EIG_VROWS];  // V[vrow0 + h][lane]
+#pragma unroll
+  for (int h = 0; h < EIG_VROWS; h++) vr[h] = make_double2(vrow0 + h == lane ? 1.0 : 0.0, 0.0);
   if (tid == 0) first_rot = 0;
   __syncthreads();
 
@@ -379,8 +384,6 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(const GateDesc *descs, int 
     if (tid < PW / 2) {
       int p, q;
       eig_pair(r, tid, p, q);
-      rp[b][tid] = p;
-      rq[b][tid] = q;
       const double a = dg[p], bb = dg[q];
       const int gs = gslot(p, q);
       const double2 g = p < q ? Gs[gs] : cconj(Gs[gs]);
@@ -432,7 +435,9 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(const GateDesc *descs, int 
         // block (row pair i, column pair j): B <- R_i^H B R_j.  A pair that
         // does not rotate has c = 1, s = 0, which leaves its entries exactly
         // as they are, so every block is updated without branches.
-        const int pi = rp[b][bi], qi = rq[b][bi], pj = rp[b][bj], qj = rq[b][bj];
+        int pi, qi, pj, qj;
+        eig_pair(r, bi, pi, qi);
+        eig_pair(r, bj, pj, qj);
         const int s00 = gslot(pi, pj), s01 = gslot(pi, qj), s10 = gslot(qi, pj), s11 = gslot(qi, qj);
         double2 b00 = Gs[s00], b01 = Gs[s01], b10 = Gs[s10], b11 = Gs[s11];
         if (pi > pj) b00 = cconj(b00);
@@ -465,25 +470,32 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(const GateDesc *descs, int 
       __syncthreads();  // G after round r
       if (tid < 64 && r + 1 < PW - 1) params(r + 1, b ^ 1);
       if (any) {
-        // V <- V R (columns); VPT rows per thread, loads first
-        constexpr int VPT = PW * (PW / 2) / EIG_THREADS;
-        static_assert(VPT * EIG_THREADS == PW * (PW / 2), "whole rows per thread");
-        const int j = tid & 31, row0 = tid >> 5;
-        const int pj = rp[b][j], qj = rq[b][j];
-        const double c = rc[b][j];
-        const double2 se = rse[b][j], sec = cconj(se);
-        double2 xp[VPT], xq[VPT];
-#pragma unroll
-        for (int h = 0; h < VPT; h++) {
-          const int row = row0 + (EIG_THREADS / 32) * h;
-          xp[h] = Vs[row * LDG + pj];
-          xq[h] = Vs[row * LDG + qj];
+        // V <- V R on this lane's column j: the pair (p, q) holding j (slot
+        // k; column 63 meets column r in slot 0), new x_p = c x_p - conj(se)
+        // x_q, new x_q = se x_p + c x_q, the partner's entries by permute
+        int k, partner;
+        bool isp;
+        if (lane == PW - 1 || lane == r) {
+          k = 0;
+          isp = lane == PW - 1;
+          partner = isp ? r : PW - 1;
+        } else {
+          k = lane - r;
+          if (k < 0) k += PW - 1;
+          isp = k < PW / 2;
+          if (!isp) k = PW - 1 - k;
+          partner = 2 * r - lane;
+          if (partner < 0) partner += PW - 1;
+          if (partner >= PW - 1) partner -= PW - 1;
         }
+        const double c = rc[b][k];
+        const double2 se = rse[b][k];
+        const double2 kap = isp ? make_double2(-se.x, se.y) : se;
 #pragma unroll
-        for (int h = 0; h < VPT; h++) {
-          const int row = row0 + (EIG_THREADS / 32) * h;
-          Vs[row * LDG + pj] = csub(cscale(xp[h], c), cmul(sec, xq[h]));
-          Vs[row * LDG + qj] = cadd(cmul(se, xp[h]), cscale(xq[h], c));
+        for (int h = 0; h < EIG_VROWS; h++) {
+          const double2 x = vr[h];
+          const double2 y = make_double2(__shfl(x.x, partner, 64), __shfl(x.y, partner, 64));
+          vr[h] = cadd(cscale(x, c), cmul(kap, y));
         }
         if (tid == 0) sweep_rot = 1;
       }
@@ -515,7 +527,8 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(const GateDesc *descs, int 
   }
   if (first_rot) {
     double2 *V = d.V + (size_t)pairIdx * (PW * PW);
-    for (int e = tid; e < PW * PW; e += EIG_THREADS) V[e] = Vs[(e / PW) * LDG + e % PW];
+#pragma unroll
+    for (int h = 0; h < EIG_VROWS; h++) V[(vrow0 + h) * PW + lane] = vr[h];
   }
 }
 
