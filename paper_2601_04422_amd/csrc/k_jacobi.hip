@@ -292,21 +292,35 @@ constexpr int EIG_THREADS = 512;  // 8 wavefronts; two pair solves share a CU
 constexpr int EIG_VROWS = PW / (EIG_THREADS / 64);  // rows of V held by each wavefront
 constexpr int EIG_OFFD = (PW / 2) * (PW / 2 - 1) / 2;  // off-diagonal 2x2 blocks (i < j)
 
-// Circle-method tournament over the 64 columns of a pair solve: in round r
-// slot 0 pairs column 63 with column r, slot k >= 1 pairs (r + k) mod 63
-// with (r - k) mod 63.  Neighbouring slots hold neighbouring columns, so the
-// LDS addresses of neighbouring lanes (row * 65 + column) fall in distinct
-// banks.  Columns are not reordered within a pair.
+// Order of the 2016 column pairs of a pair solve (columns 0-31 from block I,
+// 32-63 from block J).  Rounds 0-31 pair the blocks: slot k pairs column k
+// with column 32 + (k + r) mod 32.  Rounds 32-62 pair columns inside each
+// block by the circle method on 32 (round r' = r - 32; slots 0-15 block I,
+// 16-31 block J, s = k mod 16): s = 0 pairs 31 with r', s >= 1 pairs
+// (r' + s) mod 31 with (r' - s) mod 31.  After the first outer sweep a
+// block's own columns enter a pair solve mutually orthogonal (its last pair
+// solve made them so), so in the later sweeps the rounds inside the blocks
+// often rotate nothing and cost only their rotation test.  Neighbouring
+// slots hold neighbouring columns (distinct LDS banks of row * 65 + column).
 __device__ __forceinline__ void eig_pair(int r, int k, int &p, int &q) {
-  if (k == 0) {
-    p = PW - 1;
-    q = r;
-  } else {
-    p = r + k;
-    if (p >= PW - 1) p -= PW - 1;
-    q = r - k;
-    if (q < 0) q += PW - 1;
+  constexpr int H = PW / 2;
+  if (r < H) {
+    p = k;
+    q = H + ((k + r) & (H - 1));
+    return;
   }
+  const int rr = r - H, off = k >= H / 2 ? H : 0, s = k & (H / 2 - 1);
+  if (s == 0) {
+    p = H - 1;
+    q = rr;
+  } else {
+    p = rr + s;
+    if (p >= H - 1) p -= H - 1;
+    q = rr - s;
+    if (q < 0) q += H - 1;
+  }
+  p += off;
+  q += off;
 }
 
 // Off-diagonal entry (a, b), a != b, of the Hermitian pair Gram: only the
@@ -325,8 +339,9 @@ __device__ __forceinline__ int gslot(int a, int b) { return a < b ? a * LDG + b 
 // lane permute, so LDS holds only G and the rotation parameters (69 KB:
 // two solves per CU).  The rotations of round r + 1 are computed by the
 // first wavefront while the others apply round r to V (parameters double-
-// buffered), so a round costs two barriers.  At most `inner_sweeps` sweeps;
-// the outer sweeps finish what a capped inner solve leaves.
+// buffered), so a round costs two barriers (one if it rotates nothing).  At
+// most `inner_sweeps` sweeps; the outer sweeps finish what a capped inner
+// solve leaves.
 __global__ __launch_bounds__(EIG_THREADS, 4) void k_eig(const GateDesc *descs, int round, int ksplit) {
   const GateDesc &d = descs[blockIdx.y];
   const int pairIdx = blockIdx.x;
@@ -467,26 +482,33 @@ __global__ __launch_bounds__(EIG_THREADS, 4) void k_eig(const GateDesc *descs, i
         Gs[s10] = qi < pj ? b10 : cconj(b10);
         Gs[s11] = qi < qj ? b11 : cconj(b11);
       }
-      __syncthreads();  // G after round r
+      // G after round r (a round without rotations leaves G as it was, and
+      // the next rotations go to the other buffer)
+      if (any) __syncthreads();
       if (tid < 64 && r + 1 < PW - 1) params(r + 1, b ^ 1);
       if (any) {
         // V <- V R on this lane's column j: the pair (p, q) holding j (slot
-        // k; column 63 meets column r in slot 0), new x_p = c x_p - conj(se)
-        // x_q, new x_q = se x_p + c x_q, the partner's entries by permute
+        // k of the order above), new x_p = c x_p - conj(se) x_q, new x_q =
+        // se x_p + c x_q, the partner's entries by permute
+        constexpr int H = PW / 2;
         int k, partner;
         bool isp;
-        if (lane == PW - 1 || lane == r) {
-          k = 0;
-          isp = lane == PW - 1;
-          partner = isp ? r : PW - 1;
+        if (r < H) {
+          isp = lane < H;
+          k = isp ? lane : ((lane - H - r) & (H - 1));
+          partner = isp ? H + ((lane + r) & (H - 1)) : k;
         } else {
-          k = lane - r;
-          if (k < 0) k += PW - 1;
-          isp = k < PW / 2;
-          if (!isp) k = PW - 1 - k;
-          partner = 2 * r - lane;
-          if (partner < 0) partner += PW - 1;
-          if (partner >= PW - 1) partner -= PW - 1;
+          const int rr = r - H, off = lane & H, jj = lane & (H - 1);
+          int d = jj - rr;
+          d += d < 0 ? H - 1 : 0;
+          int pt = 2 * rr - jj;
+          pt += pt < 0 ? H - 1 : (pt >= H - 1 ? 1 - H : 0);
+          const bool last = jj == H - 1, atr = jj == rr;
+          isp = last ? true : (atr ? false : d <= H / 2 - 1);
+          k = (last || atr) ? 0 : (d <= H / 2 - 1 ? d : H - 1 - d);
+          pt = last ? rr : (atr ? H - 1 : pt);
+          k += off >> 1;
+          partner = pt + off;
         }
         const double c = rc[b][k];
         const double2 se = rse[b][k];
