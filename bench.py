@@ -852,7 +852,7 @@ def main():
     if args.storage is None:
         args.storage = "c128" if headline else "c64"
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no "
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the library has no "
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
     if args.workload != "chi1024":
